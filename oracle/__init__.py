@@ -1,0 +1,25 @@
+"""Plain CPU oracle for the Projected Adam condition-number estimator.
+
+TEST INFRASTRUCTURE ONLY. This package is the slow, obviously-correct
+reference that the GPU library is checked against. Only the test suite, the
+smoke check and the CPU-baseline leg of the benchmark may import it; the
+library and its Python binding never do, and it imports nothing from them.
+
+Everything is float64, single thread, written in the order the paper states
+the method:
+
+* ``csr``      -- CSR validation, explicit transpose, reference products;
+* ``padam``    -- Algorithm 1 (Projected Adam) with the gradient of
+                  equation ``nabla_loss``;
+* ``inverse``  -- Algorithm 2: the gradient for A^-1 from one LU
+                  factorisation (SciPy's SuperLU, or a dense LU for tiny
+                  matrices);
+* ``estimate`` -- kappa_2 = sigma_max / sigma_min from the two runs;
+* ``exact``    -- closed forms and extended-precision singular values used to
+                  pin the oracle itself.
+"""
+
+from .csr import validate_csr, transpose_csr, spmv, spmv_abs  # noqa: F401
+from .padam import PAOptions, PAResult, projected_adam  # noqa: F401
+from .inverse import LUInverse  # noqa: F401
+from .estimate import estimate_cond, forward_apply  # noqa: F401
