@@ -1,0 +1,208 @@
+"""Benchmark: time-to-kappa of the Projected Adam estimator on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload hm201|hm1001|stokes10]
+
+One step = one full estimate of kappa_2 for one matrix: the sigma_max run
+(SpMV with A and A^T, global norms, fused Adam moment update and projection)
+and the sigma_min run (Algorithm 2: four sparse triangular solves per
+update), each until the stop rule fires. The matrix, its transpose and the
+LU factors are resident in HBM before the timed region (host set-up is
+reported apart as setup_s). Prints one JSON line.
+
+Roofline: a profiled run (HIP event pair around every launch, on the plan's
+stream) gives each kernel's average duration; the dominant kernel's
+algorithmic bytes per launch / duration is "achieved". The SpMV figures are
+reported beside it.
+
+cpu_baseline: the CPU oracle (float64, one thread) timed on a bounded sample
+of the same workload and scaled to the same iteration counts.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+os.environ.setdefault("OPENBLAS_NUM_THREADS", "1")
+os.environ.setdefault("OMP_NUM_THREADS", "1")
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "hm201": dict(kind="hm", side=201, seed=1, golden="hm_side201_seed1.json"),
+    "hm1001": dict(kind="hm", side=1001, seed=2, golden=None),
+    "stokes10": dict(kind="stokes", side=10, seed=0, golden="c1_stokes_10x10_seed0.json"),
+}
+
+
+def make_matrix(w):
+    from synth import hydromech2d, stokes2d
+
+    if w["kind"] == "hm":
+        return hydromech2d(w["side"], seed=w["seed"])
+    return stokes2d(w["side"], w["side"], seed=w["seed"])
+
+
+def golden_kappa(w):
+    if not w["golden"]:
+        return None
+    path = os.path.join(ROOT, "tests", "golden", w["golden"])
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        g = json.load(f)
+    return g.get("kappa", g.get("kappa_svd"))
+
+
+def cpu_baseline(a, iters_max, iters_min, budget_s=25.0):
+    """Oracle per-update times on a bounded sample, scaled to the GPU's update counts."""
+    from oracle import PAOptions
+    from oracle.estimate import forward_apply
+    from oracle.inverse import LUInverse
+    from oracle.padam import projected_adam
+    from synth import start_vector
+
+    x0 = start_vector(a.n, 11)
+    apply_f, eval_f = forward_apply(a.n, a.rowptr, a.col, a.val)
+    t0 = time.perf_counter()
+    projected_adam(apply_f, eval_f, x0, PAOptions(max_iter=3))
+    per_max = (time.perf_counter() - t0) / 4
+    k_max = int(max(3, min(iters_max, 0.2 * budget_s / max(per_max, 1e-9))))
+    t0 = time.perf_counter()
+    projected_adam(apply_f, eval_f, x0, PAOptions(max_iter=k_max))
+    per_max = (time.perf_counter() - t0) / (k_max + 1)
+    t0 = time.perf_counter()
+    inv = LUInverse(a.n, a.rowptr, a.col, a.val)
+    lu_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    projected_adam(inv.apply, inv.evaluate, start_vector(a.n, 12), PAOptions(max_iter=2))
+    per_min = (time.perf_counter() - t0) / 3
+    left = budget_s - lu_s - k_max * per_max
+    k_min = int(max(2, min(iters_min, 0.8 * left / max(per_min, 1e-9))))
+    t0 = time.perf_counter()
+    projected_adam(inv.apply, inv.evaluate, start_vector(a.n, 12), PAOptions(max_iter=k_min))
+    per_min = (time.perf_counter() - t0) / (k_min + 1)
+    value = iters_max * per_max + iters_min * per_min
+    return {
+        "value": value, "unit": "s", "cores": 1, "kind": "oracle",
+        "sample": (f"{k_max} sigma_max updates and {k_min} sigma_min updates of the oracle on "
+                   f"the same matrix, scaled to the GPU's {iters_max} + {iters_min} updates; "
+                   f"SuperLU factorisation ({lu_s:.1f} s) excluded like the GPU's host LU"),
+        "per_update_ms": {"sigma_max": per_max * 1e3, "sigma_min": per_min * 1e3},
+        "lu_s": lu_s,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="hm201", choices=sorted(WORKLOADS))
+    ap.add_argument("--max-iter", type=int, default=3000)
+    ap.add_argument("--stop-rtol", type=float, default=1e-6)
+    ap.add_argument("--stop-window", type=int, default=25)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2409_11515_amd as pa
+    from synth import start_vector
+
+    w = WORKLOADS[args.workload]
+    t0 = time.perf_counter()
+    a = make_matrix(w)
+    gen_s = time.perf_counter() - t0
+    print(f"[bench] workload {args.workload}: n={a.n} nnz={a.nnz} (generated in {gen_s:.1f}s)",
+          file=sys.stderr, flush=True)
+    opts = dict(max_iter=args.max_iter, stop_rtol=args.stop_rtol, stop_window=args.stop_window)
+    t0 = time.perf_counter()
+    plan = pa.Plan(a.n, a.rowptr, a.col, a.val, **opts)
+    plan.bind()
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    print(f"[bench] plan ready in {setup_s:.1f}s (workspace {plan.workspace_bytes/2**20:.0f} MiB)",
+          file=sys.stderr, flush=True)
+    x0a = torch.as_tensor(start_vector(a.n, 11), device="cuda")
+    x0b = torch.as_tensor(start_vector(a.n, 12), device="cuda")
+    for _ in range(args.warmup):
+        plan.run(x0a, x0b)
+    torch.cuda.synchronize()
+    times = []
+    res = None
+    for k in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = plan.run(x0a, x0b)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        print(f"[bench] step {k}: {times[-1]*1e3:.1f} ms kappa={res['kappa']:.6e} "
+              f"iters={res['iters_max']}/{res['iters_min']}", file=sys.stderr, flush=True)
+    step_s = float(np.mean(times))
+
+    # profiled run: per-kernel average durations from HIP events
+    prof = plan.run(x0a, x0b, profile=1)
+    stats = plan.kernel_stats()
+    dom = max(stats, key=lambda k: stats[k][0])
+    ms_tot, cnt, byts = stats[dom]
+    avg_ms = ms_tot / max(cnt, 1)
+    achieved = byts / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    kernels = {k: {"avg_us": (v[0] / v[1] * 1e3) if v[1] else None, "launches": v[1],
+                   "alg_bytes": v[2],
+                   "gbs": (v[2] / (v[0] / v[1] * 1e-3) / 1e9) if v[1] and v[0] > 0 else None}
+               for k, v in stats.items() if v[1]}
+    spmv = kernels.get("spmv_A")
+
+    gk = golden_kappa(w)
+    out = {
+        "metric": "time-to-kappa (1e-3 rel) per matrix + SpMV HBM GB/s",
+        "value": step_s,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_s * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: six-field staggered-grid hydro-mechanical matrix"
+                               if w["kind"] == "hm" else "tiny Stokes",
+                   "n": a.n, "nnz": a.nnz, "nnz_l": res["nnz_l"], "nnz_u": res["nnz_u"],
+                   "alpha": 1e-2, "max_iter": args.max_iter, "stop_rtol": args.stop_rtol,
+                   "stop_window": args.stop_window, "parallelism": "single GPU"},
+        "kappa": res["kappa"],
+        "kappa_golden": gk,
+        "kappa_rel_err": (abs(res["kappa"] - gk) / gk) if gk else None,
+        "iters": {"sigma_max": res["iters_max"], "sigma_min": res["iters_min"]},
+        "run_ms": {"sigma_max": res["ms_max"], "sigma_min": res["ms_min"]},
+        "setup_s": setup_s,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
+                     "avg_us": avg_ms * 1e3, "alg_bytes_per_launch": byts},
+        "spmv": spmv,
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(a, res["iters_max"], res["iters_min"])
+    plan.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,219 @@
+/*
+ * condest.h -- C ABI of the MI355X Projected Adam condition-number estimator.
+ *
+ * The library computes kappa_2(A) = sigma_max(A) / sigma_min(A) of a square
+ * sparse matrix without singular values, by the method of Ferrari,
+ * "A Comparison of Sparse Solvers for Severely Ill-Conditioned Linear Systems
+ * in Geophysical Marker-In-Cell Simulations" (arXiv 2409.11515):
+ *
+ *   - sigma_max = ||A||_2 as the maximum of ||A v|| / ||v|| (Theorem
+ *     "Equivalent definitions of the L2 matrix norm"), reached by Projected
+ *     Adam (Algorithm 1) on the loss L(v) = log||v|| - log||A v|| whose
+ *     gradient is v/||v||^2 - A^T A v/||A v||^2 (equation nabla_loss);
+ *   - 1/sigma_min = ||A^-1||_2 by the same iteration applied to A^-1, with the
+ *     gradient from one LU factorisation and triangular solves (Algorithm 2,
+ *     "Compute Gradient for A^-1");
+ *   - kappa_2 = ||A||_2 ||A^-1||_2 (equation kappa and its singular-value form
+ *     in section "Computing the condition number of a matrix").
+ *
+ * Conventions for every entry point:
+ *   - return 0 (COND_OK) on success or a negative COND_E* status; the text of
+ *     the last error on the calling thread is available from
+ *     cond_last_error();
+ *   - the caller owns every array it passes in; the library never frees or
+ *     keeps a caller pointer beyond the call, except the device workspace
+ *     handed to cond_plan_bind (kept until cond_plan_destroy);
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *     device memory on the current device;
+ *   - all floating point is IEEE double; indices are int32 except row
+ *     pointers, which are int64;
+ *   - one plan is used by one thread and one stream at a time.
+ */
+#ifndef CONDEST_H
+#define CONDEST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+#define COND_OK 0
+#define COND_EINVAL (-1)    /* malformed CSR (non-square, bad rowptr, column out of
+                               range), non-finite entry, zero matrix, bad option */
+#define COND_ESINGULAR (-2) /* the LU met an exactly zero pivot column: A is singular;
+                               sigma_min = 0 and kappa = +inf are reported */
+#define COND_ENOMEM (-3)    /* host allocation failed or the workspace is too small */
+#define COND_EHIP (-4)      /* a HIP runtime call failed */
+#define COND_ENUMERIC (-5)  /* a norm became zero or non-finite during the iteration */
+#define COND_ESTATE (-6)    /* entry points called out of order (e.g. run before bind) */
+#define COND_ETIMEOUT (-7)  /* a triangular-solve wait exceeded its spin limit */
+
+/* sigma_min route */
+#define COND_MIN_LU 0   /* the paper's route: Algorithm 2, one LU + triangular solves */
+#define COND_MIN_NONE 2 /* skip the sigma_min run */
+
+/* result flags */
+#define COND_F_NUMSING 1u  /* kappa >= 1/eps_mach: numerically singular (Theorem on
+                              numerical singularity) */
+#define COND_F_MAXITER 2u  /* a run ended at max_iter rather than by the stop rule */
+#define COND_F_SINGULAR 4u /* exactly singular (zero pivot) */
+
+/* ------------------------------------------------------------------- types */
+
+/* A square n x n CSR matrix in host memory. Column indices need not be
+ * sorted; duplicates are summed. rowptr[0] = 0, rowptr[n] = nnz. */
+typedef struct {
+  int32_t n;
+  int64_t nnz;
+  const int64_t* rowptr; /* host, n+1 */
+  const int32_t* col;    /* host, nnz */
+  const double* val;     /* host, nnz */
+} cond_csr_t;
+
+/* Options of Algorithm 1. The paper fixes none of alpha, beta1, beta2, eps or
+ * max_iter (they are inputs of the algorithm); cond_opts_default() gives
+ * alpha = 1e-2, beta1 = 0.9, beta2 = 0.999, eps = 1e-8, max_iter = 20000,
+ * no early stop. */
+typedef struct {
+  double alpha, beta1, beta2, eps;
+  int64_t max_iter;    /* Adam updates per run (>= 1) */
+  double stop_rtol;    /* early stop: after T updates, T a multiple of stop_window,
+                          T >= 2*stop_window, stop when
+                          best_T - best_{T-W} <= stop_rtol * best_T; 0 = off */
+  int64_t stop_window; /* W; 0 = off */
+  int32_t sigma_min_method; /* COND_MIN_LU or COND_MIN_NONE */
+  int32_t chunk;       /* iterations per captured HIP graph launch (0 = automatic) */
+  const int32_t* col_perm; /* optional fill-reducing column order for the LU (host,
+                              n entries, a permutation); NULL = built-in nested
+                              dissection */
+  double pivot_tol;    /* threshold partial pivoting: keep the diagonal candidate
+                          when |a_jj| >= pivot_tol * max |a_ij| (0 < tol <= 1;
+                          0 = default 1e-3) */
+  int32_t profile;     /* 1: launch eagerly (no graph) with a HIP event pair around
+                          every kernel; per-kernel times via cond_plan_kernel_stats */
+} cond_opts_t;
+
+typedef struct {
+  double sigma_max, sigma_min, kappa;
+  int64_t iters_max, iters_min; /* Adam updates performed by each run */
+  uint32_t flags;               /* COND_F_* */
+  int32_t status_max, status_min;
+  double ms_max, ms_min;        /* device time of each run (HIP events) */
+  double setup_ms;              /* host setup: validation, transpose, ordering, LU */
+  int64_t nnz_l, nnz_u;         /* LU fill (strictly lower L, upper U incl. diagonal) */
+} cond_result_t;
+
+typedef struct cond_plan cond_plan_t;
+typedef struct cond_lu cond_lu_t;
+
+/* ------------------------------------------------------------------ basics */
+const char* cond_strerror(int status);
+const char* cond_last_error(void);
+void cond_opts_default(cond_opts_t* o);
+int cond_version(void);
+
+/* -------------------------------------------------- host steps (no device)
+ * These run on the CPU only and are what the plan does at set-up; they are
+ * exported so each step can be checked on its own. */
+
+/* Validate a CSR matrix: square, monotone rowptr starting at 0, columns in
+ * [0, n), finite values, not all zero. Returns COND_OK or COND_EINVAL. */
+int cond_csr_check(const cond_csr_t* A);
+
+/* Explicit transpose A^T in CSR (the gradient of equation nabla_loss needs
+ * A^T A v). Output arrays are caller-allocated: t_rowptr[n+1], t_col[nnz],
+ * t_val[nnz]. Stable: within a row of A^T, entries appear in increasing row
+ * order of A. */
+int cond_csr_transpose(const cond_csr_t* A, int64_t* t_rowptr, int32_t* t_col, double* t_val);
+
+/* Fill-reducing order of the symmetric pattern of A + A^T by recursive
+ * level-structure bisection (nested dissection). perm[k] = the column of A
+ * placed at position k. */
+int cond_order_nd(const cond_csr_t* A, int32_t* perm);
+
+/* Sparse LU with threshold partial pivoting, P A Q = L U (Algorithm 2 writes
+ * A = L U; the permutations are this library's choice). L is unit lower
+ * triangular, U upper triangular. col_perm may be NULL (nested dissection).
+ * pivot_tol as in cond_opts_t. Fails with COND_ESINGULAR on a zero pivot
+ * column. */
+int cond_lu_factor(const cond_csr_t* A, const int32_t* col_perm, double pivot_tol, cond_lu_t** lu);
+void cond_lu_destroy(cond_lu_t* lu);
+/* nnz of strictly-lower L and of U (diagonal included). */
+int cond_lu_info(const cond_lu_t* lu, int32_t* n, int64_t* nnz_l, int64_t* nnz_u);
+/* Copy out the factors as CSR in pivot order plus the permutations:
+ * row_perm[k] = row of A that is row k of P A; col_perm[k] = column of A that
+ * is column k of A Q. Any output pointer may be NULL to skip it. l_* hold the
+ * strictly lower part of L; u_* the strictly upper part of U; u_diag the
+ * diagonal of U. */
+int cond_lu_export(const cond_lu_t* lu, int64_t* l_rowptr, int32_t* l_col, double* l_val,
+                   int64_t* u_rowptr, int32_t* u_col, double* u_val, double* u_diag,
+                   int32_t* row_perm, int32_t* col_perm);
+/* Host reference solve with the factors: trans = 0 gives r = A^-1 x,
+ * trans = 1 gives r = A^-T x. */
+int cond_lu_solve_host(const cond_lu_t* lu, int trans, const double* x, double* r);
+
+/* ------------------------------------------------------------ device plan
+ * cond_plan_create does the host set-up (validation, A^T, and for the
+ * sigma_min route the ordering and the LU); cond_plan_workspace_bytes says
+ * how much device memory the plan needs; cond_plan_bind takes that memory
+ * (workspace != NULL: caller-owned, e.g. allocated by PyTorch; NULL: the
+ * library allocates it with hipMalloc and frees it in destroy) and uploads
+ * the matrices on the given stream (hipStream_t; NULL = default stream).
+ * Every later device call of this plan is enqueued on that stream. */
+int cond_plan_create(const cond_csr_t* A, const cond_opts_t* o, cond_plan_t** plan);
+int cond_plan_workspace_bytes(const cond_plan_t* plan, size_t* bytes);
+int cond_plan_bind(cond_plan_t* plan, void* workspace, size_t bytes, void* stream);
+void cond_plan_destroy(cond_plan_t* plan);
+
+/* Run both Projected Adam passes and assemble kappa. x0_max, x0_min: device
+ * start vectors of length n (any non-zero scale; normalised inside; x0_min
+ * may equal x0_max). trace_max / trace_min: optional device arrays of length
+ * o->max_iter receiving best-sigma after each evaluated iterate (trace[t-1] =
+ * best over x_1..x_t; for the sigma_min run the values are ||A^-1 x||, i.e.
+ * 1/sigma_min estimates). x_best_max / x_best_min: optional device outputs
+ * (length n) of the maximising iterates. o may differ from the create-time
+ * options only in alpha, beta1, beta2, eps, max_iter, stop_*, chunk.
+ * Returns after the result is on the host. */
+int cond_plan_run(cond_plan_t* plan, const cond_opts_t* o, const double* x0_max,
+                  const double* x0_min, cond_result_t* out, double* trace_max,
+                  double* trace_min, double* x_best_max, double* x_best_min);
+
+/* Kernel ids of cond_plan_kernel_stats. */
+#define COND_K_NORMALISE 0
+#define COND_K_SPMV_A 1
+#define COND_K_SPMV_AT 2
+#define COND_K_SUMSQ 3
+#define COND_K_TRSV_L 4
+#define COND_K_TRSV_U 5
+#define COND_K_TRSV_UT 6
+#define COND_K_TRSV_LT 7
+#define COND_K_ADAM1 8
+#define COND_K_ADAM2 9
+#define COND_K_COUNT 10
+
+/* Per-kernel device time of the last cond_plan_run with opts.profile = 1:
+ * ms[k] = total milliseconds and launches[k] = number of launches of kernel
+ * k (arrays of COND_K_COUNT entries, caller-allocated). Also reports the
+ * algorithmic bytes one launch of each kernel must move (bytes[k], may be
+ * NULL): matrix/factor entries 12 B each plus row pointers and every vector
+ * read or written once. */
+int cond_plan_kernel_stats(const cond_plan_t* plan, double* ms, int64_t* launches, double* bytes);
+
+/* One step of the path at a time, on device vectors of length n (for checks
+ * against the oracle): y = A x; y = A^T x; r = A^-1 x and s = A^-T r
+ * (Algorithm 2). Asynchronous on the plan's stream. */
+int cond_plan_spmv(cond_plan_t* plan, int transpose, const double* x, double* y);
+int cond_plan_inverse_apply(cond_plan_t* plan, const double* x, double* r, double* s);
+
+/* create + bind (library-owned memory) + run + destroy. */
+int cond_estimate(const cond_csr_t* A, const cond_opts_t* o, const double* x0_max,
+                  const double* x0_min, void* stream, cond_result_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CONDEST_H */

@@ -1,0 +1,229 @@
+"""MI355X Projected Adam condition-number estimator (arXiv 2409.11515).
+
+Python face of the C-ABI library ``libcondest.so`` (declared in
+``include/condest.h``). The functions here have the same names as the C
+entry points without the ``cond_`` prefix and only marshal arguments:
+numpy arrays for host data, torch tensors for device memory and streams.
+
+    from paper_2409_11515_amd import estimate_cond
+    r = estimate_cond(n, rowptr, col, val, x0_max=x0)   # x0: torch float64 on cuda
+    r["kappa"], r["sigma_max"], r["sigma_min"]
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from ._binding import (  # noqa: F401
+    COND_F_MAXITER,
+    COND_F_NUMSING,
+    COND_MIN_LU,
+    COND_MIN_NONE,
+    CondError,
+    HostCsr,
+    ResultT,
+    check,
+    lib,
+    make_opts,
+)
+
+__all__ = ["csr_check", "csr_transpose", "order_nd", "LU", "Plan", "estimate_cond", "CondError"]
+
+
+def version() -> int:
+    return lib().cond_version()
+
+
+def csr_check(n, rowptr, col, val) -> None:
+    h = HostCsr(n, rowptr, col, val)
+    check(lib().cond_csr_check(C.byref(h.struct)), "csr_check")
+
+
+def csr_transpose(n, rowptr, col, val):
+    """(t_rowptr int64, t_col int32, t_val float64) of A^T, computed by the library."""
+    h = HostCsr(n, rowptr, col, val)
+    nnz = int(h.rowptr[-1])
+    tr = np.empty(n + 1, np.int64)
+    tc = np.empty(nnz, np.int32)
+    tv = np.empty(nnz, np.float64)
+    check(lib().cond_csr_transpose(C.byref(h.struct), tr.ctypes.data, tc.ctypes.data,
+                                   tv.ctypes.data), "csr_transpose")
+    return tr, tc, tv
+
+
+def order_nd(n, rowptr, col, val) -> np.ndarray:
+    h = HostCsr(n, rowptr, col, val)
+    perm = np.empty(n, np.int32)
+    check(lib().cond_order_nd(C.byref(h.struct), perm.ctypes.data), "order_nd")
+    return perm
+
+
+class LU:
+    """Host LU of the library, P A Q = L U (for checks of the set-up step)."""
+
+    def __init__(self, n, rowptr, col, val, col_perm=None, pivot_tol=1e-3):
+        h = HostCsr(n, rowptr, col, val)
+        cp = None if col_perm is None else np.ascontiguousarray(col_perm, np.int32)
+        self._h = C.c_void_p()
+        check(lib().cond_lu_factor(C.byref(h.struct), None if cp is None else cp.ctypes.data,
+                                   float(pivot_tol), C.byref(self._h)), "lu_factor")
+        n_ = C.c_int32()
+        nl = C.c_int64()
+        nu = C.c_int64()
+        check(lib().cond_lu_info(self._h, C.byref(n_), C.byref(nl), C.byref(nu)), "lu_info")
+        self.n, self.nnz_l, self.nnz_u = n_.value, nl.value, nu.value
+
+    def export(self) -> dict:
+        n = self.n
+        nl = self.nnz_l
+        nus = self.nnz_u - n
+        out = dict(l_rowptr=np.empty(n + 1, np.int64), l_col=np.empty(nl, np.int32),
+                   l_val=np.empty(nl), u_rowptr=np.empty(n + 1, np.int64),
+                   u_col=np.empty(nus, np.int32), u_val=np.empty(nus), u_diag=np.empty(n),
+                   row_perm=np.empty(n, np.int32), col_perm=np.empty(n, np.int32))
+        keys = ["l_rowptr", "l_col", "l_val", "u_rowptr", "u_col", "u_val", "u_diag", "row_perm",
+                "col_perm"]
+        check(lib().cond_lu_export(self._h, *[out[k].ctypes.data for k in keys]), "lu_export")
+        return out
+
+    def solve(self, x, trans=False) -> np.ndarray:
+        x = np.ascontiguousarray(x, np.float64)
+        r = np.empty_like(x)
+        check(lib().cond_lu_solve_host(self._h, 1 if trans else 0, x.ctypes.data, r.ctypes.data),
+              "lu_solve_host")
+        return r
+
+    def __del__(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().cond_lu_destroy(self._h)
+            self._h = C.c_void_p()
+
+
+def _stream_ptr(torch, stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+class Plan:
+    """Device plan: host set-up at construction, device memory from torch.
+
+    ``Plan(n, rowptr, col, val, **opts)`` validates the matrix, builds A^T
+    and (unless ``sigma_min_method=COND_MIN_NONE``) the LU on the host;
+    ``bind()`` allocates the workspace as a torch uint8 CUDA tensor and
+    uploads; ``run()`` performs both Projected Adam runs.
+    """
+
+    def __init__(self, n, rowptr, col, val, col_perm=None, **opts):
+        self._h = C.c_void_p()
+        self.n = int(n)
+        self.opts = make_opts(**opts)
+        h = HostCsr(n, rowptr, col, val)
+        cp = None if col_perm is None else np.ascontiguousarray(col_perm, np.int32)
+        self.opts.col_perm = None if cp is None else cp.ctypes.data
+        check(lib().cond_plan_create(C.byref(h.struct), C.byref(self.opts), C.byref(self._h)),
+              "plan_create")
+        self.opts.col_perm = None
+        sz = C.c_size_t()
+        check(lib().cond_plan_workspace_bytes(self._h, C.byref(sz)), "plan_workspace_bytes")
+        self.workspace_bytes = sz.value
+        self.workspace = None
+
+    def bind(self, device="cuda", stream=None, own_memory=False):
+        import torch
+
+        if own_memory:
+            ptr = None
+        else:
+            self.workspace = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8,
+                                         device=device)
+            base = self.workspace.data_ptr()
+            ptr = (base + 255) // 256 * 256
+        check(lib().cond_plan_bind(self._h, ptr, self.workspace_bytes,
+                                   _stream_ptr(torch, stream)), "plan_bind")
+        return self
+
+    def run(self, x0_max, x0_min=None, trace=False, x_best=False, **opts) -> dict:
+        import torch
+
+        o = make_opts(**{**self._opts_dict(), **opts})
+        dev = x0_max.device
+        T = int(o.max_iter)
+        tmax = torch.zeros(T, dtype=torch.float64, device=dev) if trace else None
+        tmin = torch.zeros(T, dtype=torch.float64, device=dev) if trace else None
+        bmax = torch.zeros(self.n, dtype=torch.float64, device=dev) if x_best else None
+        bmin = torch.zeros(self.n, dtype=torch.float64, device=dev) if x_best else None
+        res = ResultT()
+        st = lib().cond_plan_run(self._h, C.byref(o), x0_max.data_ptr(),
+                                 None if x0_min is None else x0_min.data_ptr(), C.byref(res),
+                                 None if tmax is None else tmax.data_ptr(),
+                                 None if tmin is None else tmin.data_ptr(),
+                                 None if bmax is None else bmax.data_ptr(),
+                                 None if bmin is None else bmin.data_ptr())
+        out = {f: getattr(res, f) for f, _ in ResultT._fields_}
+        out["status"] = st
+        if trace:
+            out["trace_max"] = tmax[: max(res.iters_max, 0)].cpu().numpy()
+            out["trace_min"] = tmin[: max(res.iters_min, 0)].cpu().numpy()
+        if x_best:
+            out["x_best_max"] = bmax
+            out["x_best_min"] = bmin
+        check(st, "plan_run")
+        return out
+
+    def _opts_dict(self):
+        return {f: getattr(self.opts, f) for f, _ in self.opts._fields_ if f != "col_perm"}
+
+    def kernel_stats(self) -> dict:
+        """{kernel: (total_ms, launches, algorithmic_bytes_per_launch)} of the last profiled run."""
+        from ._binding import KERNEL_NAMES
+
+        k = len(KERNEL_NAMES)
+        ms = np.zeros(k)
+        cnt = np.zeros(k, np.int64)
+        by = np.zeros(k)
+        check(lib().cond_plan_kernel_stats(self._h, ms.ctypes.data, cnt.ctypes.data, by.ctypes.data),
+              "plan_kernel_stats")
+        return {name: (float(ms[i]), int(cnt[i]), float(by[i])) for i, name in enumerate(KERNEL_NAMES)}
+
+    def spmv(self, x, transpose=False):
+        import torch
+
+        y = torch.empty_like(x)
+        check(lib().cond_plan_spmv(self._h, 1 if transpose else 0, x.data_ptr(), y.data_ptr()),
+              "plan_spmv")
+        return y
+
+    def inverse_apply(self, x):
+        import torch
+
+        r = torch.empty_like(x)
+        s = torch.empty_like(x)
+        check(lib().cond_plan_inverse_apply(self._h, x.data_ptr(), r.data_ptr(), s.data_ptr()),
+              "plan_inverse_apply")
+        return r, s
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().cond_plan_destroy(self._h)
+            self._h = C.c_void_p()
+        self.workspace = None
+
+    def __del__(self):
+        self.close()
+
+
+def estimate_cond(n, rowptr, col, val, x0_max, x0_min=None, stream=None, **opts) -> dict:
+    """kappa_2 of the CSR matrix: create + bind (library memory) + run + destroy."""
+    import torch
+
+    h = HostCsr(n, rowptr, col, val)
+    o = make_opts(**opts)
+    res = ResultT()
+    st = lib().cond_estimate(C.byref(h.struct), C.byref(o), x0_max.data_ptr(),
+                             None if x0_min is None else x0_min.data_ptr(),
+                             _stream_ptr(torch, stream), C.byref(res))
+    check(st, "estimate")
+    return {f: getattr(res, f) for f, _ in ResultT._fields_}

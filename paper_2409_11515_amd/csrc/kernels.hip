@@ -1,0 +1,479 @@
+// HIP kernels for gfx950 (iteration layout and conventions in kernels.hpp).
+//
+// Row ranges: every fixed-grid kernel gives block b the contiguous row range
+// of logical block lb = (b % 8) * (grid / 8) + b / 8 (grid a multiple of 8).
+// The hardware hands consecutive block ids to the 8 XCDs in turn, so the
+// logical ranges of one XCD are adjacent and the gathers of a banded matrix
+// stay inside that XCD's L2.
+
+#include "condest.h"
+#include "kernels.hpp"
+
+namespace condest {
+
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v) {
+  // xor butterfly: every lane ends with the same, order-fixed sum
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum over the block; every thread gets the same value. Fixed order.
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double red[kBlock / 64];
+  v = wave_sum(v);
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[wave] = v;
+  __syncthreads();
+  double r = red[0];
+#pragma unroll
+  for (int k = 1; k < kBlock / 64; ++k) r += red[k];
+  __syncthreads();
+  return r;
+}
+
+// Sum of the `count` partial slots; identical in every block.
+__device__ __forceinline__ double sum_parts(const double* parts, int count) {
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < count; k += kBlock) acc += parts[k];
+  return block_sum(acc);
+}
+
+__device__ __forceinline__ int logical_block() {
+  const int b = blockIdx.x, g = gridDim.x;
+  return (g % 8 == 0) ? (b % 8) * (g / 8) + b / 8 : b;
+}
+
+__device__ __forceinline__ void block_range(long long n, int lb, long long& r0, long long& r1) {
+  r0 = n * lb / gridDim.x;
+  r1 = n * (lb + 1) / gridDim.x;
+}
+
+// ------------------------------------------------------------------ init
+__global__ __launch_bounds__(kBlock) void init_k(int n, const double* __restrict__ x0,
+                                                 double* __restrict__ x, double* __restrict__ m,
+                                                 double* __restrict__ v, double* __restrict__ parts_xx,
+                                                 RunState* st) {
+  const int lb = logical_block();
+  long long r0, r1;
+  block_range(n, lb, r0, r1);
+  double acc = 0.0;
+  for (long long i = r0 + threadIdx.x; i < r1; i += kBlock) {
+    const double xi = x0[i];
+    x[i] = xi;
+    m[i] = 0.0;
+    v[i] = 0.0;
+    acc += xi * xi;
+  }
+  const double s = block_sum(acc);
+  if (threadIdx.x == 0) parts_xx[lb] = s;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->best = -1.0;  // below any norm ratio: the first evaluation always improves
+    st->best_next = -1.0;
+    st->b1t = 1.0;
+    st->b2t = 1.0;
+    st->t_done = 0;
+    st->iters = 0;
+    st->stop_req = 0;
+    st->done = 0;
+    st->status = 0;
+    st->flags = 0;
+    st->abort_wait = 0;
+    st->ckpt = -1.0;
+    st->ckpt_next = -1.0;
+  }
+}
+
+// ------------------------------------------------------------ normalise
+// x <- x / ||x|| (the last step of Algorithm 1's update), partials of x.x for
+// the next gradient; optionally re-arms the triangular-solve vectors.
+struct Resets {
+  double* p[4];
+  int count;
+};
+
+__global__ __launch_bounds__(kBlock) void normalise_k(int n, double* __restrict__ x,
+                                                      const double* __restrict__ parts_xx, int np,
+                                                      double* __restrict__ parts_x, RunState* st,
+                                                      Resets resets, unsigned* tickets, int ntickets) {
+#pragma clang fp contract(off)
+  if (st->stop_req) return;
+  const double nrm = sqrt(sum_parts(parts_xx, np));
+  const int lb = logical_block();
+  long long r0, r1;
+  block_range(n, lb, r0, r1);
+  double acc = 0.0;
+  for (long long i = r0 + threadIdx.x; i < r1; i += kBlock) {
+    const double xi = x[i] / nrm;
+    x[i] = xi;
+    acc += xi * xi;
+  }
+  for (int k = 0; k < resets.count; ++k) {
+    unsigned long long* p = reinterpret_cast<unsigned long long*>(resets.p[k]);
+    for (long long i = r0 + threadIdx.x; i < r1; i += kBlock) p[i] = kPending;
+  }
+  const double s = block_sum(acc);
+  if (threadIdx.x == 0) parts_x[lb] = s;
+  if (blockIdx.x == 0 && threadIdx.x < ntickets) tickets[threadIdx.x] = 0u;
+}
+
+// ----------------------------------------------------------------- spmv
+// y = A x, vector CSR: LPR lanes per row, partial sums of y.y per block.
+template <int LPR, typename IT>
+__global__ __launch_bounds__(kBlock) void spmv_k(int n, const IT* __restrict__ rowptr,
+                                                 const int* __restrict__ col,
+                                                 const double* __restrict__ val,
+                                                 const double* __restrict__ x, double* __restrict__ y,
+                                                 double* __restrict__ parts, const RunState* st) {
+  if (st && st->stop_req) return;
+  constexpr int kGroups = kBlock / LPR;
+  const int lb = logical_block();
+  long long r0, r1;
+  block_range(n, lb, r0, r1);
+  const int lane = threadIdx.x % LPR;
+  const int grp = threadIdx.x / LPR;
+  double sq = 0.0;
+  for (long long r = r0 + grp; r < r1; r += kGroups) {
+    const IT p0 = rowptr[r], p1 = rowptr[r + 1];
+    double acc = 0.0;
+    for (IT p = p0 + lane; p < p1; p += LPR) acc += val[p] * x[col[p]];
+#pragma unroll
+    for (int off = LPR / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, LPR);
+    if (lane == 0) {
+      y[r] = acc;
+      sq += acc * acc;
+    }
+  }
+  if (parts) {
+    const double s = block_sum(sq);
+    if (threadIdx.x == 0) parts[lb] = s;
+  }
+}
+
+// ---------------------------------------------------------------- sumsq
+__global__ __launch_bounds__(kBlock) void sumsq_k(int n, const double* __restrict__ z,
+                                                  double* __restrict__ parts, const RunState* st) {
+  if (st->stop_req) return;
+  const int lb = logical_block();
+  long long r0, r1;
+  block_range(n, lb, r0, r1);
+  double acc = 0.0;
+  for (long long i = r0 + threadIdx.x; i < r1; i += kBlock) {
+    const double zi = z[i];
+    acc += zi * zi;
+  }
+  const double s = block_sum(acc);
+  if (threadIdx.x == 0) parts[lb] = s;
+}
+
+// ----------------------------------------------------------------- trsv
+// Sparse triangular solve, one wave per row, rows taken in chunks from a
+// ticket counter in dependency order (increasing rows for a lower factor,
+// decreasing for an upper one). Every dependency of a row therefore belongs
+// to a chunk handed out earlier -- to this wave, already finished, or to a
+// wave that is resident and itself only waits on earlier chunks -- so the
+// waits always end. A solved entry is published by one 64-bit atomic store;
+// until then it holds the kPending pattern, so the value is its own ready
+// flag. A wait that spins past kSpinLimit marks the run aborted and returns
+// NaN instead of hanging.
+constexpr int kChunkRows = 16;
+constexpr unsigned kSpinLimit = 1u << 21;
+
+__device__ __forceinline__ double wait_value(const double* p, RunState* st) {
+  const unsigned long long* q = reinterpret_cast<const unsigned long long*>(p);
+  // cached read first; only a still-pending entry goes to the coherent level
+  unsigned long long bits =
+      __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  if (bits != kPending) return __longlong_as_double(static_cast<long long>(bits));
+  unsigned spins = 0;
+  for (;;) {
+    bits = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (bits != kPending) break;
+    ++spins;
+    if ((spins & 255u) == 0u) {
+      if (__hip_atomic_load(&st->abort_wait, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        return __longlong_as_double(0x7FF8000000000000ll);
+      if (spins >= kSpinLimit) {
+        __hip_atomic_store(&st->abort_wait, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return __longlong_as_double(0x7FF8000000000000ll);
+      }
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return __longlong_as_double(static_cast<long long>(bits));
+}
+
+template <bool UPPER, bool UNIT>
+__global__ __launch_bounds__(kBlock) void trsv_k(int n, const long long* __restrict__ rowptr,
+                                                 const int* __restrict__ col,
+                                                 const double* __restrict__ val,
+                                                 const double* __restrict__ diag,
+                                                 const double* __restrict__ rhs,
+                                                 const int* __restrict__ rhs_perm, double* out,
+                                                 double* __restrict__ scatter,
+                                                 const int* __restrict__ scatter_perm,
+                                                 unsigned* ticket, RunState* st) {
+  if (st->stop_req || st->abort_wait) return;
+  const int lane = threadIdx.x & 63;
+  const unsigned nchunks = static_cast<unsigned>((static_cast<long long>(n) + kChunkRows - 1) / kChunkRows);
+  for (;;) {
+    unsigned c = 0;
+    if (lane == 0) c = atomicAdd(ticket, 1u);
+    c = __shfl(c, 0, 64);
+    if (c >= nchunks) break;
+    for (int r = 0; r < kChunkRows; ++r) {
+      const long long k = static_cast<long long>(c) * kChunkRows + r;
+      if (k >= n) break;
+      const int i = UPPER ? static_cast<int>(n - 1 - k) : static_cast<int>(k);
+      const long long p0 = rowptr[i], p1 = rowptr[i + 1];
+      double acc = 0.0;
+      for (long long p = p0 + lane; p < p1; p += 64) acc += val[p] * wait_value(out + col[p], st);
+      acc = wave_sum(acc);
+      if (lane == 0) {
+        const double b = rhs_perm ? rhs[rhs_perm[i]] : rhs[i];
+        double xi = b - acc;
+        if (!UNIT) xi = xi / diag[i];
+        __hip_atomic_store(reinterpret_cast<unsigned long long*>(out + i),
+                           static_cast<unsigned long long>(__double_as_longlong(xi)),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (scatter) scatter[scatter_perm[i]] = xi;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------- adam pass 1
+// Evaluation of the previous iterate, best-iterate tracking, stop rule, and
+// the moment update with bias correction (Algorithm 1), partials of x.dx.
+__global__ __launch_bounds__(kBlock) void pass1_k(int n, const double* __restrict__ x,
+                                                  const double* __restrict__ w,
+                                                  double* __restrict__ m, double* __restrict__ v,
+                                                  double* __restrict__ d, double* __restrict__ xbest,
+                                                  const double* __restrict__ parts_x,
+                                                  const double* __restrict__ parts_y, int np,
+                                                  double* __restrict__ parts_xd, RunState* st,
+                                                  double* __restrict__ trace, AdamParams p) {
+#pragma clang fp contract(off)
+  if (st->done) return;
+  const long long t = st->t_done + 1;  // index of the update this pass prepares
+  const double nx2 = sum_parts(parts_x, np);
+  const double ny2 = sum_parts(parts_y, np);
+  const double best = st->best;
+  double best_next = best;
+  double ckpt_next = st->ckpt;
+  bool improved = false;
+  int stop = 0, status = COND_OK, flags = 0;
+  long long iters = t - 1;
+  if (st->abort_wait) {
+    stop = 1;
+    status = COND_ETIMEOUT;
+  } else if (!(nx2 > 0.0) || !(ny2 > 0.0) || !isfinite(nx2) || !isfinite(ny2)) {
+    stop = 1;
+    status = COND_ENUMERIC;
+  } else if (t >= 2) {
+    // sigma(x_{t-1}) = ||M x|| / ||x||; strict ">" keeps the earliest best
+    const double sigma = sqrt(ny2 / nx2);
+    if (sigma > best) {
+      improved = true;
+      best_next = sigma;
+    }
+    const long long T = t - 1;
+    if (T >= p.max_iter) {
+      stop = 1;
+      flags |= static_cast<int>(COND_F_MAXITER);
+    } else if (p.stop_window > 0 && p.stop_rtol > 0.0 && T % p.stop_window == 0) {
+      if (T >= 2 * p.stop_window && best_next - st->ckpt <= p.stop_rtol * best_next) stop = 1;
+      ckpt_next = best_next;
+    }
+  }
+  const int lb = logical_block();
+  long long r0, r1;
+  block_range(n, lb, r0, r1);
+  if (improved && xbest)
+    for (long long i = r0 + threadIdx.x; i < r1; i += kBlock) xbest[i] = x[i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->best_next = best_next;
+    st->ckpt_next = ckpt_next;
+    if (t >= 2 && trace && status == COND_OK) trace[t - 2] = best_next;
+    if (stop) {
+      st->iters = iters;
+      st->status = status;
+      st->flags = flags;
+      st->stop_req = 1;
+    }
+  }
+  if (stop) return;
+  const double b1 = p.beta1, b2 = p.beta2;
+  const double b1t = st->b1t * b1, b2t = st->b2t * b2;
+  double acc = 0.0;
+  for (long long i = r0 + threadIdx.x; i < r1; i += kBlock) {
+    const double xi = x[i];
+    const double g = xi / nx2 - w[i] / ny2;  // equation nabla_loss
+    const double mi = b1 * m[i] + (1.0 - b1) * g;
+    const double vi = b2 * v[i] + (1.0 - b2) * (g * g);
+    const double mh = mi / (1.0 - b1t);
+    const double vh = vi / (1.0 - b2t);
+    const double di = p.alpha * mh / (sqrt(vh) + p.eps);
+    m[i] = mi;
+    v[i] = vi;
+    d[i] = di;
+    acc += xi * di;
+  }
+  const double s = block_sum(acc);
+  if (threadIdx.x == 0) parts_xd[lb] = s;
+}
+
+// ---------------------------------------------------------- adam pass 2
+// Tangent projection dx <- dx - (x.dx) x and the update x <- x - dx; partials
+// of ||x||^2 for the normalisation that opens the next iteration.
+__global__ __launch_bounds__(kBlock) void pass2_k(int n, double* __restrict__ x,
+                                                  const double* __restrict__ d,
+                                                  const double* __restrict__ parts_xd, int np,
+                                                  double* __restrict__ parts_xx, RunState* st,
+                                                  AdamParams p) {
+#pragma clang fp contract(off)
+  if (st->done) return;
+  if (st->stop_req) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st->best = st->best_next;
+      st->done = 1;
+    }
+    return;
+  }
+  const double xd = sum_parts(parts_xd, np);
+  const int lb = logical_block();
+  long long r0, r1;
+  block_range(n, lb, r0, r1);
+  double acc = 0.0;
+  for (long long i = r0 + threadIdx.x; i < r1; i += kBlock) {
+    const double xi = x[i];
+    const double dd = d[i] - xd * xi;
+    const double xn = xi - dd;
+    x[i] = xn;
+    acc += xn * xn;
+  }
+  const double s = block_sum(acc);
+  if (threadIdx.x == 0) parts_xx[lb] = s;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->t_done = st->t_done + 1;
+    st->b1t = st->b1t * p.beta1;
+    st->b2t = st->b2t * p.beta2;
+    st->best = st->best_next;
+    st->ckpt = st->ckpt_next;
+  }
+}
+
+__global__ void fill_k(long long n, unsigned long long* p, unsigned long long bits) {
+  for (long long i = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<long long>(gridDim.x) * blockDim.x)
+    p[i] = bits;
+}
+
+__global__ void zero_u32_k(unsigned* p, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0u;
+}
+
+template <typename IT>
+void spmv_dispatch(const DevCsr& a, const double* x, double* y, double* parts, int grid,
+                   const RunState* st, hipStream_t s) {
+  const IT* rp = static_cast<const IT*>(a.rowptr);
+  switch (a.lpr) {
+    case 4: spmv_k<4, IT><<<grid, kBlock, 0, s>>>(a.n, rp, a.col, a.val, x, y, parts, st); break;
+    case 8: spmv_k<8, IT><<<grid, kBlock, 0, s>>>(a.n, rp, a.col, a.val, x, y, parts, st); break;
+    case 16: spmv_k<16, IT><<<grid, kBlock, 0, s>>>(a.n, rp, a.col, a.val, x, y, parts, st); break;
+    case 32: spmv_k<32, IT><<<grid, kBlock, 0, s>>>(a.n, rp, a.col, a.val, x, y, parts, st); break;
+    default: spmv_k<64, IT><<<grid, kBlock, 0, s>>>(a.n, rp, a.col, a.val, x, y, parts, st); break;
+  }
+}
+
+}  // namespace
+
+int grid_for(int n) {
+  // about 256 rows per block, at most kMaxParts blocks, a multiple of 8
+  long long g = (static_cast<long long>(n) + 255) / 256;
+  if (g < 8) g = 8;
+  if (g > kMaxParts) g = kMaxParts;
+  return static_cast<int>((g + 7) / 8 * 8);
+}
+
+void launch_init(int n, const double* x0, double* x, double* m, double* v, double* parts_xx,
+                 int grid, RunState* st, hipStream_t s) {
+  init_k<<<grid, kBlock, 0, s>>>(n, x0, x, m, v, parts_xx, st);
+}
+
+void launch_normalise(int n, double* x, const double* parts_xx, int grid, double* parts_x,
+                      RunState* st, double* const* resets, int nresets, unsigned* tickets,
+                      int ntickets, hipStream_t s) {
+  Resets r{};
+  r.count = nresets;
+  for (int k = 0; k < nresets && k < 4; ++k) r.p[k] = resets[k];
+  normalise_k<<<grid, kBlock, 0, s>>>(n, x, parts_xx, grid, parts_x, st, r, tickets, ntickets);
+}
+
+void launch_spmv(const DevCsr& a, const double* x, double* y, double* parts_y, int grid,
+                 const RunState* st, hipStream_t s) {
+  if (a.idx64)
+    spmv_dispatch<long long>(a, x, y, parts_y, grid, st, s);
+  else
+    spmv_dispatch<int>(a, x, y, parts_y, grid, st, s);
+}
+
+void launch_sumsq(int n, const double* z, double* parts, int grid, const RunState* st,
+                  hipStream_t s) {
+  sumsq_k<<<grid, kBlock, 0, s>>>(n, z, parts, st);
+}
+
+void launch_trsv(const DevTri& t, const double* rhs, const int* rhs_perm, double* out,
+                 double* scatter, const int* scatter_perm, unsigned* ticket, RunState* st,
+                 hipStream_t s) {
+  const long long chunks = (static_cast<long long>(t.n) + kChunkRows - 1) / kChunkRows;
+  long long blocks = (chunks + (kBlock / 64) - 1) / (kBlock / 64);
+  if (blocks > 2048) blocks = 2048;
+  if (blocks < 1) blocks = 1;
+  const int g = static_cast<int>(blocks);
+  const bool unit = (t.diag == nullptr);
+  if (t.upper) {
+    if (unit)
+      trsv_k<true, true><<<g, kBlock, 0, s>>>(t.n, t.rowptr, t.col, t.val, t.diag, rhs, rhs_perm,
+                                               out, scatter, scatter_perm, ticket, st);
+    else
+      trsv_k<true, false><<<g, kBlock, 0, s>>>(t.n, t.rowptr, t.col, t.val, t.diag, rhs, rhs_perm,
+                                                out, scatter, scatter_perm, ticket, st);
+  } else {
+    if (unit)
+      trsv_k<false, true><<<g, kBlock, 0, s>>>(t.n, t.rowptr, t.col, t.val, t.diag, rhs, rhs_perm,
+                                                out, scatter, scatter_perm, ticket, st);
+    else
+      trsv_k<false, false><<<g, kBlock, 0, s>>>(t.n, t.rowptr, t.col, t.val, t.diag, rhs,
+                                                 rhs_perm, out, scatter, scatter_perm, ticket, st);
+  }
+}
+
+void launch_pass1(int n, const double* x, const double* w, double* m, double* v, double* d,
+                  double* xbest, const double* parts_x, const double* parts_y, int grid,
+                  double* parts_xd, RunState* st, double* trace, const AdamParams& p,
+                  hipStream_t s) {
+  pass1_k<<<grid, kBlock, 0, s>>>(n, x, w, m, v, d, xbest, parts_x, parts_y, grid, parts_xd, st,
+                                  trace, p);
+}
+
+void launch_pass2(int n, double* x, const double* d, const double* parts_xd, int grid,
+                  double* parts_xx, RunState* st, const AdamParams& p, hipStream_t s) {
+  pass2_k<<<grid, kBlock, 0, s>>>(n, x, d, parts_xd, grid, parts_xx, st, p);
+}
+
+void launch_fill(int n, double* p, unsigned long long bits, hipStream_t s) {
+  int blocks = (n + kBlock - 1) / kBlock;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  fill_k<<<blocks, kBlock, 0, s>>>(n, reinterpret_cast<unsigned long long*>(p), bits);
+}
+
+void launch_zero_u32(unsigned* p, int count, hipStream_t s) {
+  zero_u32_k<<<(count + 63) / 64, 64, 0, s>>>(p, count);
+}
+
+}  // namespace condest

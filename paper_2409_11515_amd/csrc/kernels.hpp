@@ -1,0 +1,100 @@
+// Device kernels of the Projected Adam estimator (gfx950, wave64, FP64).
+//
+// One iteration of Algorithm 1 is a fixed sequence of launches on one stream:
+//
+//   sigma_max (M = A):      normalise -> spmv(A) -> spmv(A^T) -> adam_pass1 -> adam_pass2
+//   sigma_min (M = A^-1):   normalise -> trsv(L) -> trsv(U) -> sumsq -> trsv(U^T)
+//                           -> trsv(L^T) -> adam_pass1 -> adam_pass2
+//
+// Global sums (||x||^2, ||M x||^2, x.dx) are deterministic: every producer
+// block writes one partial into a fixed slot, and every consumer block adds
+// the same slots in the same order, so all blocks see bit-identical scalars
+// and two runs give bit-identical results. No floating-point atomics are used.
+//
+// All per-run scalars live in a device-resident RunState so that a whole
+// chunk of iterations can be captured in one HIP graph and replayed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace condest {
+
+constexpr int kBlock = 256;      // threads per block (4 waves of 64)
+constexpr int kMaxParts = 2048;  // max blocks (and partial slots) of a fixed-grid kernel
+// A signalling-NaN bit pattern marks "not solved yet" in the triangular
+// solves; arithmetic never produces a signalling NaN, so a solved entry,
+// even a NaN one, can never be mistaken for it.
+constexpr unsigned long long kPending = 0x7FF0DEAD0000BEEFull;
+
+// Device-resident state of one Projected Adam run. Each field has one
+// writer kernel (noted) so that no kernel reads a field it may be changing.
+struct RunState {
+  double best;       // best sigma over evaluated iterates (adam_pass2, block 0)
+  double best_next;  // best after this iteration's evaluation (adam_pass1, block 0)
+  double ckpt;       // best at the last stop-window boundary (adam_pass2, block 0)
+  double ckpt_next;  // (adam_pass1, block 0)
+  double b1t, b2t;   // beta1^t, beta2^t for t = updates done (adam_pass2, block 0)
+  long long t_done;  // Adam updates done (adam_pass2, block 0)
+  long long iters;   // final T (adam_pass1, block 0, when stopping)
+  int stop_req;      // 1 once the run has decided to stop (adam_pass1, block 0)
+  int done;          // 1 after the stopping iteration has drained (adam_pass2, block 0)
+  int status;        // COND_OK or an error code (adam_pass1, block 0)
+  int flags;         // COND_F_* bits of this run (adam_pass1, block 0)
+  int abort_wait;    // 1 when a triangular-solve wait timed out (trsv)
+  int pad_;
+};
+
+struct AdamParams {
+  double alpha, beta1, beta2, eps;
+  double stop_rtol;
+  long long stop_window;
+  long long max_iter;
+};
+
+// CSR on the device. rowptr is int32 when idx64 == 0, else int64.
+struct DevCsr {
+  int n = 0;
+  long long nnz = 0;
+  const void* rowptr = nullptr;
+  int idx64 = 0;
+  const int* col = nullptr;
+  const double* val = nullptr;
+  int lpr = 8;  // lanes per row for the SpMV (power of two, 4..64)
+};
+
+// A strictly triangular factor for a row-oriented solve (int64 rowptr).
+struct DevTri {
+  int n = 0;
+  const long long* rowptr = nullptr;
+  const int* col = nullptr;
+  const double* val = nullptr;
+  const double* diag = nullptr;  // nullptr: unit diagonal
+  int upper = 0;                 // 1: backward substitution (row i needs j > i)
+};
+
+int grid_for(int n);  // fixed grid size of the reduction kernels for length n
+
+void launch_init(int n, const double* x0, double* x, double* m, double* v, double* parts_xx,
+                 int grid, RunState* st, hipStream_t s);
+void launch_normalise(int n, double* x, const double* parts_xx, int grid, double* parts_x,
+                      RunState* st, double* const* resets, int nresets, unsigned* tickets,
+                      int ntickets, hipStream_t s);
+void launch_spmv(const DevCsr& a, const double* x, double* y, double* parts_y, int grid,
+                 const RunState* st, hipStream_t s);
+void launch_sumsq(int n, const double* z, double* parts, int grid, const RunState* st,
+                  hipStream_t s);
+void launch_trsv(const DevTri& t, const double* rhs, const int* rhs_perm, double* out,
+                 double* scatter, const int* scatter_perm, unsigned* ticket, RunState* st,
+                 hipStream_t s);
+void launch_pass1(int n, const double* x, const double* w, double* m, double* v, double* d,
+                  double* xbest, const double* parts_x, const double* parts_y, int grid,
+                  double* parts_xd, RunState* st, double* trace, const AdamParams& p,
+                  hipStream_t s);
+void launch_pass2(int n, double* x, const double* d, const double* parts_xd, int grid,
+                  double* parts_xx, RunState* st, const AdamParams& p, hipStream_t s);
+void launch_fill(int n, double* p, unsigned long long bits, hipStream_t s);
+void launch_zero_u32(unsigned* p, int count, hipStream_t s);
+
+}  // namespace condest

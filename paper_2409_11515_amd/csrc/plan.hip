@@ -1,0 +1,659 @@
+// Device plan: host set-up, workspace layout, and the driver loop that
+// replays captured iterations of Algorithm 1 until the run stops.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "condest.h"
+#include "internal.hpp"
+#include "kernels.hpp"
+
+namespace condest {
+int lu_factor(const HostCsr& a, const HostCsr& at, const int32_t* col_perm_in, double tol,
+              cond_lu& lu);
+}
+
+using namespace condest;
+
+#define CHK(expr)                                                                    \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return fail(COND_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+struct Layout {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    size_t o = (off + kAlign - 1) / kAlign * kAlign;
+    off = o + bytes;
+    return o;
+  }
+};
+
+struct GraphKey {
+  int route = -1;
+  int chunk = 0;
+  const void* trace = nullptr;
+  const void* xbest = nullptr;
+  AdamParams p{};
+  bool operator==(const GraphKey& o) const {
+    return route == o.route && chunk == o.chunk && trace == o.trace && xbest == o.xbest &&
+           std::memcmp(&p, &o.p, sizeof(p)) == 0;
+  }
+};
+
+int choose_lpr(double mean_nnz_per_row) {
+  int l = 4;
+  while (l < 64 && l < mean_nnz_per_row) l <<= 1;
+  return l;
+}
+
+}  // namespace
+
+struct cond_plan {
+  int32_t n = 0;
+  cond_opts_t opts{};
+  HostCsr a, at;
+  std::unique_ptr<cond_lu> lu;
+  bool want_min = false;
+  double setup_ms = 0.0;
+  // device
+  bool bound = false;
+  hipStream_t user_stream = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev_start = nullptr, ev_stop = nullptr, ev_a = nullptr, ev_b = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool own_ws = false;
+  DevCsr dA, dAt;
+  DevTri dL, dU, dUt, dLt;
+  int* d_row_perm = nullptr;
+  int* d_col_perm = nullptr;
+  double *x = nullptr, *m = nullptr, *v = nullptr, *d = nullptr, *y = nullptr, *w = nullptr;
+  double *c = nullptr, *z = nullptr, *h = nullptr, *wv = nullptr;
+  double *parts_x = nullptr, *parts_y = nullptr, *parts_xd = nullptr, *parts_xx = nullptr;
+  RunState* st = nullptr;
+  RunState* st_free = nullptr;
+  unsigned* tickets = nullptr;
+  RunState* h_state = nullptr;  // pinned, two slots
+  int grid = 8;
+  GraphKey key[2];
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  // eager profiling (opts.profile): event pairs around every launch
+  std::vector<hipEvent_t> evpool;
+  struct Rec {
+    int k;
+    double bytes;
+  };
+  std::vector<Rec> recs;
+  double kms[COND_K_COUNT] = {};
+  long long kcnt[COND_K_COUNT] = {};
+  double kbytes[COND_K_COUNT] = {};
+  bool profiling = false;
+  size_t need_bytes = 0;
+  // offsets into the workspace
+  struct {
+    size_t a_rp, a_col, a_val, at_rp, at_col, at_val;
+    size_t l_rp, l_col, l_val, u_rp, u_col, u_val, ut_rp, ut_col, ut_val, lt_rp, lt_col, lt_val;
+    size_t u_diag, row_perm, col_perm;
+    size_t vec[10];
+    size_t parts[4];
+    size_t st, st_free, tickets;
+  } o{};
+};
+
+namespace {
+
+bool idx64_needed(const HostCsr& a) { return a.nnz() >= (1LL << 31) - 1; }
+
+void plan_layout(cond_plan* p) {
+  Layout L;
+  const size_t n = p->n;
+  const bool a64 = idx64_needed(p->a);
+  const size_t ri = a64 ? 8 : 4;
+  p->o.a_rp = L.take((n + 1) * ri);
+  p->o.a_col = L.take(p->a.nnz() * 4);
+  p->o.a_val = L.take(p->a.nnz() * 8);
+  p->o.at_rp = L.take((n + 1) * ri);
+  p->o.at_col = L.take(p->at.nnz() * 4);
+  p->o.at_val = L.take(p->at.nnz() * 8);
+  if (p->want_min) {
+    const cond_lu& f = *p->lu;
+    p->o.l_rp = L.take((n + 1) * 8);
+    p->o.l_col = L.take(f.l_rows.nnz() * 4);
+    p->o.l_val = L.take(f.l_rows.nnz() * 8);
+    p->o.u_rp = L.take((n + 1) * 8);
+    p->o.u_col = L.take(f.u_rows.nnz() * 4);
+    p->o.u_val = L.take(f.u_rows.nnz() * 8);
+    p->o.ut_rp = L.take((n + 1) * 8);
+    p->o.ut_col = L.take(f.u_cols.nnz() * 4);
+    p->o.ut_val = L.take(f.u_cols.nnz() * 8);
+    p->o.lt_rp = L.take((n + 1) * 8);
+    p->o.lt_col = L.take(f.l_cols.nnz() * 4);
+    p->o.lt_val = L.take(f.l_cols.nnz() * 8);
+    p->o.u_diag = L.take(n * 8);
+    p->o.row_perm = L.take(n * 4);
+    p->o.col_perm = L.take(n * 4);
+  }
+  const int nvec = p->want_min ? 10 : 6;
+  for (int k = 0; k < nvec; ++k) p->o.vec[k] = L.take(n * 8);
+  for (int k = 0; k < 4; ++k) p->o.parts[k] = L.take(kMaxParts * 8);
+  p->o.st = L.take(sizeof(RunState));
+  p->o.st_free = L.take(sizeof(RunState));
+  p->o.tickets = L.take(64);
+  p->need_bytes = L.off;
+}
+
+template <typename T>
+T* at_off(cond_plan* p, size_t off) {
+  return reinterpret_cast<T*>(p->ws + off);
+}
+
+int upload(cond_plan* p, size_t off, const void* src, size_t bytes) {
+  if (!bytes) return COND_OK;
+  CHK(hipMemcpyAsync(p->ws + off, src, bytes, hipMemcpyHostToDevice, p->stream));
+  return COND_OK;
+}
+
+int upload_csr(cond_plan* p, const HostCsr& a, size_t rp, size_t col, size_t val, bool idx64,
+               DevCsr& out) {
+  const size_t n = a.n;
+  int st;
+  if (idx64) {
+    st = upload(p, rp, a.rowptr.data(), (n + 1) * 8);
+  } else {
+    std::vector<int32_t> r32(a.rowptr.begin(), a.rowptr.end());
+    st = upload(p, rp, r32.data(), (n + 1) * 4);
+    if (!st) CHK(hipStreamSynchronize(p->stream));  // r32 is a temporary
+  }
+  if (st) return st;
+  if ((st = upload(p, col, a.col.data(), a.nnz() * 4))) return st;
+  if ((st = upload(p, val, a.val.data(), a.nnz() * 8))) return st;
+  out.n = a.n;
+  out.nnz = a.nnz();
+  out.rowptr = p->ws + rp;
+  out.idx64 = idx64 ? 1 : 0;
+  out.col = at_off<int>(p, col);
+  out.val = at_off<double>(p, val);
+  out.lpr = choose_lpr(static_cast<double>(a.nnz()) / std::max(1, a.n));
+  return COND_OK;
+}
+
+int upload_tri(cond_plan* p, const HostCsr& t, size_t rp, size_t col, size_t val,
+               const double* diag_dev, int upper, DevTri& out) {
+  int st;
+  if ((st = upload(p, rp, t.rowptr.data(), (t.n + 1) * 8))) return st;
+  if ((st = upload(p, col, t.col.data(), t.nnz() * 4))) return st;
+  if ((st = upload(p, val, t.val.data(), t.nnz() * 8))) return st;
+  out.n = t.n;
+  out.rowptr = at_off<long long>(p, rp);
+  out.col = at_off<int>(p, col);
+  out.val = at_off<double>(p, val);
+  out.diag = diag_dev;
+  out.upper = upper;
+  return COND_OK;
+}
+
+AdamParams params_of(const cond_opts_t& o) {
+  AdamParams p{};
+  p.alpha = o.alpha;
+  p.beta1 = o.beta1;
+  p.beta2 = o.beta2;
+  p.eps = o.eps;
+  p.stop_rtol = o.stop_rtol;
+  p.stop_window = o.stop_window;
+  p.max_iter = o.max_iter;
+  return p;
+}
+
+int check_opts(const cond_opts_t* o) {
+  if (!o) return fail(COND_EINVAL, "null options");
+  if (!(o->alpha > 0) || !(o->beta1 >= 0 && o->beta1 < 1) || !(o->beta2 >= 0 && o->beta2 < 1) ||
+      !(o->eps >= 0) || o->max_iter < 1 || o->stop_window < 0 || !(o->stop_rtol >= 0) ||
+      o->chunk < 0)
+    return fail(COND_EINVAL, "invalid Projected Adam options");
+  if (o->sigma_min_method != COND_MIN_LU && o->sigma_min_method != COND_MIN_NONE)
+    return fail(COND_EINVAL, "unknown sigma_min method");
+  return COND_OK;
+}
+
+// Algorithmic bytes of one launch: matrix entries 12 B, row pointers, and
+// every vector read or written once (gathers counted as one pass).
+double spmv_bytes(const DevCsr& a) {
+  return 12.0 * a.nnz + (a.idx64 ? 8.0 : 4.0) * (a.n + 1) + 16.0 * a.n;
+}
+// Scope guard of one launch in profiling mode: records an event before and
+// after it on the plan stream (event pair r is evpool[2r], evpool[2r+1]).
+struct Prof {
+  cond_plan* p;
+  int k;
+  double bytes;
+  Prof(cond_plan* pp, int kk, double by) : p(pp), k(kk), bytes(by) {
+    if (p->profiling) mark(2 * p->recs.size());
+  }
+  ~Prof() {
+    if (p->profiling) {
+      mark(2 * p->recs.size() + 1);
+      p->recs.push_back({k, bytes});
+    }
+  }
+  void mark(size_t idx) {
+    while (p->evpool.size() <= idx) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return;
+      p->evpool.push_back(e);
+    }
+    hipEventRecord(p->evpool[idx], p->stream);
+  }
+};
+
+// One iteration of the chosen route, enqueued on the plan stream.
+void enqueue_iteration(cond_plan* p, int route, double* trace, double* xbest, const AdamParams& ap) {
+  hipStream_t s = p->stream;
+  const int n = p->n, g = p->grid;
+  const double dn = n;
+  if (route == 0) {
+    { Prof pr(p, COND_K_NORMALISE, 16.0 * dn);
+      launch_normalise(n, p->x, p->parts_xx, g, p->parts_x, p->st, nullptr, 0, nullptr, 0, s); }
+    { Prof pr(p, COND_K_SPMV_A, spmv_bytes(p->dA));
+      launch_spmv(p->dA, p->x, p->y, p->parts_y, g, p->st, s); }
+    { Prof pr(p, COND_K_SPMV_AT, spmv_bytes(p->dAt));
+      launch_spmv(p->dAt, p->y, p->w, nullptr, g, p->st, s); }
+  } else {
+    const double nl = static_cast<double>(p->lu->l_rows.nnz());
+    const double nu = static_cast<double>(p->lu->u_rows.nnz());
+    const double rp = 8.0 * (dn + 1);
+    double* resets[4] = {p->c, p->z, p->h, p->wv};
+    { Prof pr(p, COND_K_NORMALISE, 48.0 * dn);
+      launch_normalise(n, p->x, p->parts_xx, g, p->parts_x, p->st, resets, 4, p->tickets, 4, s); }
+    // r = A^-1 x: L c = P x, U z = c (r = Q z; ||r|| = ||z||)
+    { Prof pr(p, COND_K_TRSV_L, 12.0 * nl + rp + 28.0 * dn);
+      launch_trsv(p->dL, p->x, p->d_row_perm, p->c, nullptr, nullptr, p->tickets + 0, p->st, s); }
+    { Prof pr(p, COND_K_TRSV_U, 12.0 * nu + rp + 32.0 * dn);
+      launch_trsv(p->dU, p->c, nullptr, p->z, nullptr, nullptr, p->tickets + 1, p->st, s); }
+    { Prof pr(p, COND_K_SUMSQ, 8.0 * dn);
+      launch_sumsq(n, p->z, p->parts_y, g, p->st, s); }
+    // s = A^-T r: U^T h = Q^T r = z, L^T wv = h, s = P^T wv
+    { Prof pr(p, COND_K_TRSV_UT, 12.0 * nu + rp + 32.0 * dn);
+      launch_trsv(p->dUt, p->z, nullptr, p->h, nullptr, nullptr, p->tickets + 2, p->st, s); }
+    { Prof pr(p, COND_K_TRSV_LT, 12.0 * nl + rp + 36.0 * dn);
+      launch_trsv(p->dLt, p->h, nullptr, p->wv, p->w, p->d_row_perm, p->tickets + 3, p->st, s); }
+  }
+  { Prof pr(p, COND_K_ADAM1, 56.0 * dn);
+    launch_pass1(n, p->x, p->w, p->m, p->v, p->d, xbest, p->parts_x, p->parts_y, g, p->parts_xd,
+                 p->st, trace, ap, s); }
+  { Prof pr(p, COND_K_ADAM2, 24.0 * dn);
+    launch_pass2(n, p->x, p->d, p->parts_xd, g, p->parts_xx, p->st, ap, s); }
+}
+
+// Fold the recorded event pairs into the per-kernel totals (stream synchronised).
+int collect_profile(cond_plan* p) {
+  for (size_t r = 0; r < p->recs.size(); ++r) {
+    float ms = 0.f;
+    CHK(hipEventElapsedTime(&ms, p->evpool[2 * r], p->evpool[2 * r + 1]));
+    const int k = p->recs[r].k;
+    p->kms[k] += ms;
+    p->kcnt[k] += 1;
+    p->kbytes[k] += p->recs[r].bytes;
+  }
+  p->recs.clear();
+  return COND_OK;
+}
+
+int get_graph(cond_plan* p, int route, int chunk, double* trace, double* xbest,
+              const AdamParams& ap, hipGraphExec_t* out) {
+  GraphKey k;
+  k.route = route;
+  k.chunk = chunk;
+  k.trace = trace;
+  k.xbest = xbest;
+  k.p = ap;
+  if (p->exec[route] && p->key[route] == k) {
+    *out = p->exec[route];
+    return COND_OK;
+  }
+  if (p->exec[route]) {
+    CHK(hipGraphExecDestroy(p->exec[route]));
+    p->exec[route] = nullptr;
+  }
+  hipGraph_t graph = nullptr;
+  CHK(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
+  for (int it = 0; it < chunk; ++it) enqueue_iteration(p, route, trace, xbest, ap);
+  hipError_t e = hipStreamEndCapture(p->stream, &graph);
+  if (e != hipSuccess) return fail(COND_EHIP, std::string("capture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(&p->exec[route], graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail(COND_EHIP, std::string("instantiate: ") + hipGetErrorString(e));
+  p->key[route] = k;
+  *out = p->exec[route];
+  return COND_OK;
+}
+
+// Replays the captured chunk until the device state says the run stopped,
+// launching one chunk ahead of the poll so the device never waits on the host.
+int replay_until_stop(cond_plan* p, hipGraphExec_t exec, int chunk, long long total) {
+  long long launched = 0;
+  RunState* slot[2] = {p->h_state, p->h_state + 1};
+  hipEvent_t ev[2] = {p->ev_a, p->ev_b};
+  int cur = 0;
+  CHK(hipGraphLaunch(exec, p->stream));
+  launched += chunk;
+  CHK(hipMemcpyAsync(slot[0], p->st, sizeof(RunState), hipMemcpyDeviceToHost, p->stream));
+  CHK(hipEventRecord(ev[0], p->stream));
+  bool pending_next = false;
+  for (;;) {
+    if (launched < total) {
+      CHK(hipGraphLaunch(exec, p->stream));
+      launched += chunk;
+      CHK(hipMemcpyAsync(slot[cur ^ 1], p->st, sizeof(RunState), hipMemcpyDeviceToHost,
+                         p->stream));
+      CHK(hipEventRecord(ev[cur ^ 1], p->stream));
+      pending_next = true;
+    } else {
+      pending_next = false;
+    }
+    CHK(hipEventSynchronize(ev[cur]));
+    if (slot[cur]->done || slot[cur]->stop_req) break;
+    if (!pending_next) break;  // should not happen: the last chunk always stops
+    cur ^= 1;
+  }
+  return COND_OK;
+}
+
+// Orders the plan stream after the work the caller queued on its stream.
+int join_user_stream(cond_plan* p) {
+  if (!p->user_stream) return COND_OK;
+  hipEvent_t e;
+  CHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  CHK(hipEventRecord(e, p->user_stream));
+  CHK(hipStreamWaitEvent(p->stream, e, 0));
+  CHK(hipEventDestroy(e));
+  return COND_OK;
+}
+
+struct RouteResult {
+  double sigma = 0.0;
+  long long iters = 0;
+  int status = 0;
+  int flags = 0;
+  double ms = 0.0;
+};
+
+int run_route(cond_plan* p, int route, const cond_opts_t& o, const double* x0, double* trace,
+              double* xbest, RouteResult& rr) {
+  const AdamParams ap = params_of(o);
+  const long long total = o.max_iter + 1;  // the last pass only evaluates x_T
+  if (o.profile) {
+    // eager launches with an event pair around each kernel; poll every iteration
+    CHK(hipEventRecord(p->ev_start, p->stream));
+    launch_init(p->n, x0, p->x, p->m, p->v, p->parts_xx, p->grid, p->st, p->stream);
+    CHK(hipGetLastError());
+    p->profiling = true;
+    int st = COND_OK;
+    for (long long it = 0; it < total && st == COND_OK; ++it) {
+      enqueue_iteration(p, route, trace, xbest, ap);
+      if (hipMemcpyAsync(p->h_state, p->st, sizeof(RunState), hipMemcpyDeviceToHost,
+                         p->stream) != hipSuccess ||
+          hipStreamSynchronize(p->stream) != hipSuccess) {
+        st = fail(COND_EHIP, "profiled iteration failed");
+        break;
+      }
+      st = collect_profile(p);
+      if (p->h_state->stop_req) break;
+    }
+    p->profiling = false;
+    if (st) return st;
+  } else {
+    const int chunk = o.chunk > 0 ? o.chunk : (route == 0 ? 32 : 4);
+    hipGraphExec_t exec = nullptr;
+    int st = get_graph(p, route, chunk, trace, xbest, ap, &exec);
+    if (st) return st;
+    CHK(hipEventRecord(p->ev_start, p->stream));
+    launch_init(p->n, x0, p->x, p->m, p->v, p->parts_xx, p->grid, p->st, p->stream);
+    CHK(hipGetLastError());
+    if ((st = replay_until_stop(p, exec, chunk, total))) return st;
+  }
+  CHK(hipEventRecord(p->ev_stop, p->stream));
+  CHK(hipMemcpyAsync(p->h_state, p->st, sizeof(RunState), hipMemcpyDeviceToHost, p->stream));
+  CHK(hipStreamSynchronize(p->stream));
+  float ms = 0.f;
+  CHK(hipEventElapsedTime(&ms, p->ev_start, p->ev_stop));
+  const RunState& s = *p->h_state;
+  if (!s.stop_req) return fail(COND_EHIP, "run did not reach its stopping iteration");
+  rr.sigma = s.stop_req && s.done ? s.best : s.best_next;
+  rr.iters = s.iters;
+  rr.status = s.abort_wait ? COND_ETIMEOUT : s.status;
+  rr.flags = s.flags;
+  rr.ms = ms;
+  return COND_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cond_plan_create(const cond_csr_t* A, const cond_opts_t* o, cond_plan_t** out) {
+  if (!out) return fail(COND_EINVAL, "null output");
+  *out = nullptr;
+  int st = check_opts(o);
+  if (st) return st;
+  auto t0 = std::chrono::steady_clock::now();
+  std::unique_ptr<cond_plan> p(new (std::nothrow) cond_plan());
+  if (!p) return fail(COND_ENOMEM, "allocation failed");
+  try {
+    if ((st = canonical_copy(A, p->a))) return st;
+    transpose(p->a, p->at);
+    p->n = p->a.n;
+    p->opts = *o;
+    p->opts.col_perm = nullptr;
+    p->want_min = (o->sigma_min_method == COND_MIN_LU);
+    if (p->want_min) {
+      p->lu.reset(new cond_lu());
+      st = lu_factor(p->a, p->at, o->col_perm, o->pivot_tol, *p->lu);
+      if (st) return st;
+    }
+  } catch (const std::bad_alloc&) {
+    return fail(COND_ENOMEM, "host memory exhausted in set-up");
+  }
+  p->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  p->grid = grid_for(p->n);
+  plan_layout(p.get());
+  *out = p.release();
+  return COND_OK;
+}
+
+int cond_plan_workspace_bytes(const cond_plan_t* plan, size_t* bytes) {
+  if (!plan || !bytes) return fail(COND_EINVAL, "null argument");
+  *bytes = plan->need_bytes;
+  return COND_OK;
+}
+
+int cond_plan_bind(cond_plan_t* p, void* workspace, size_t bytes, void* stream) {
+  if (!p) return fail(COND_EINVAL, "null plan");
+  if (p->bound) return fail(COND_ESTATE, "plan already bound");
+  if (workspace && bytes < p->need_bytes) return fail(COND_ENOMEM, "workspace too small");
+  if (workspace && (reinterpret_cast<uintptr_t>(workspace) % kAlign))
+    return fail(COND_EINVAL, "workspace must be 256-byte aligned");
+  p->user_stream = static_cast<hipStream_t>(stream);
+  CHK(hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking));
+  CHK(hipEventCreate(&p->ev_start));
+  CHK(hipEventCreate(&p->ev_stop));
+  CHK(hipEventCreateWithFlags(&p->ev_a, hipEventDisableTiming));
+  CHK(hipEventCreateWithFlags(&p->ev_b, hipEventDisableTiming));
+  CHK(hipHostMalloc(reinterpret_cast<void**>(&p->h_state), 2 * sizeof(RunState), hipHostMallocDefault));
+  if (workspace) {
+    p->ws = static_cast<char*>(workspace);
+    p->ws_bytes = bytes;
+    p->own_ws = false;
+  } else {
+    CHK(hipMalloc(reinterpret_cast<void**>(&p->ws), p->need_bytes));
+    p->ws_bytes = p->need_bytes;
+    p->own_ws = true;
+  }
+  // order the uploads after whatever the caller queued on its stream
+  int st;
+  if ((st = join_user_stream(p))) return st;
+  const bool a64 = idx64_needed(p->a);
+  if ((st = upload_csr(p, p->a, p->o.a_rp, p->o.a_col, p->o.a_val, a64, p->dA))) return st;
+  if ((st = upload_csr(p, p->at, p->o.at_rp, p->o.at_col, p->o.at_val, a64, p->dAt))) return st;
+  if (p->want_min) {
+    const cond_lu& f = *p->lu;
+    if ((st = upload(p, p->o.u_diag, f.u_diag.data(), p->n * 8))) return st;
+    if ((st = upload(p, p->o.row_perm, f.row_perm.data(), p->n * 4))) return st;
+    if ((st = upload(p, p->o.col_perm, f.col_perm.data(), p->n * 4))) return st;
+    const double* dg = at_off<double>(p, p->o.u_diag);
+    if ((st = upload_tri(p, f.l_rows, p->o.l_rp, p->o.l_col, p->o.l_val, nullptr, 0, p->dL))) return st;
+    if ((st = upload_tri(p, f.u_rows, p->o.u_rp, p->o.u_col, p->o.u_val, dg, 1, p->dU))) return st;
+    if ((st = upload_tri(p, f.u_cols, p->o.ut_rp, p->o.ut_col, p->o.ut_val, dg, 0, p->dUt))) return st;
+    if ((st = upload_tri(p, f.l_cols, p->o.lt_rp, p->o.lt_col, p->o.lt_val, nullptr, 1, p->dLt))) return st;
+    p->d_row_perm = at_off<int>(p, p->o.row_perm);
+    p->d_col_perm = at_off<int>(p, p->o.col_perm);
+  }
+  double** vecs[10] = {&p->x, &p->m, &p->v, &p->d, &p->y, &p->w, &p->c, &p->z, &p->h, &p->wv};
+  const int nvec = p->want_min ? 10 : 6;
+  for (int k = 0; k < nvec; ++k) *vecs[k] = at_off<double>(p, p->o.vec[k]);
+  p->parts_x = at_off<double>(p, p->o.parts[0]);
+  p->parts_y = at_off<double>(p, p->o.parts[1]);
+  p->parts_xd = at_off<double>(p, p->o.parts[2]);
+  p->parts_xx = at_off<double>(p, p->o.parts[3]);
+  p->st = at_off<RunState>(p, p->o.st);
+  p->st_free = at_off<RunState>(p, p->o.st_free);
+  p->tickets = at_off<unsigned>(p, p->o.tickets);
+  CHK(hipMemsetAsync(p->st, 0, sizeof(RunState), p->stream));
+  CHK(hipMemsetAsync(p->st_free, 0, sizeof(RunState), p->stream));
+  CHK(hipMemsetAsync(p->tickets, 0, 64, p->stream));
+  CHK(hipStreamSynchronize(p->stream));
+  p->bound = true;
+  return COND_OK;
+}
+
+void cond_plan_destroy(cond_plan_t* p) {
+  if (!p) return;
+  if (p->stream) hipStreamSynchronize(p->stream);
+  for (auto& e : p->exec)
+    if (e) hipGraphExecDestroy(e);
+  if (p->own_ws && p->ws) hipFree(p->ws);
+  if (p->h_state) hipHostFree(p->h_state);
+  if (p->ev_start) hipEventDestroy(p->ev_start);
+  if (p->ev_stop) hipEventDestroy(p->ev_stop);
+  if (p->ev_a) hipEventDestroy(p->ev_a);
+  if (p->ev_b) hipEventDestroy(p->ev_b);
+  if (p->stream) hipStreamDestroy(p->stream);
+  delete p;
+}
+
+int cond_plan_run(cond_plan_t* p, const cond_opts_t* o, const double* x0_max, const double* x0_min,
+                  cond_result_t* out, double* trace_max, double* trace_min, double* x_best_max,
+                  double* x_best_min) {
+  if (!p || !out) return fail(COND_EINVAL, "null argument");
+  if (!p->bound) return fail(COND_ESTATE, "plan not bound");
+  const cond_opts_t& oo = o ? *o : p->opts;
+  int st = check_opts(&oo);
+  if (st) return st;
+  if (!x0_max) return fail(COND_EINVAL, "null start vector");
+  if (!x0_min) x0_min = x0_max;
+  std::memset(out, 0, sizeof(*out));
+  out->setup_ms = p->setup_ms;
+  if (p->want_min) {
+    out->nnz_l = p->lu->l_rows.nnz();
+    out->nnz_u = p->lu->u_rows.nnz() + p->n;
+  }
+  if ((st = join_user_stream(p))) return st;
+  if (oo.profile) {
+    std::fill(p->kms, p->kms + COND_K_COUNT, 0.0);
+    std::fill(p->kcnt, p->kcnt + COND_K_COUNT, 0LL);
+    std::fill(p->kbytes, p->kbytes + COND_K_COUNT, 0.0);
+  }
+  RouteResult rmax, rmin;
+  if ((st = run_route(p, 0, oo, x0_max, trace_max, x_best_max, rmax))) return st;
+  out->sigma_max = rmax.sigma;
+  out->iters_max = rmax.iters;
+  out->status_max = rmax.status;
+  out->ms_max = rmax.ms;
+  if (rmax.flags & COND_F_MAXITER) out->flags |= COND_F_MAXITER;
+  if (p->want_min && oo.sigma_min_method == COND_MIN_LU) {
+    if ((st = run_route(p, 1, oo, x0_min, trace_min, x_best_min, rmin))) return st;
+    out->sigma_min = 1.0 / rmin.sigma;  // the run maximises ||A^-1 x|| / ||x||
+    out->iters_min = rmin.iters;
+    out->status_min = rmin.status;
+    out->ms_min = rmin.ms;
+    if (rmin.flags & COND_F_MAXITER) out->flags |= COND_F_MAXITER;
+    out->kappa = out->sigma_max / out->sigma_min;
+    if (out->kappa >= 1.0 / 2.220446049250313e-16) out->flags |= COND_F_NUMSING;
+  }
+  if (out->status_max) return fail(out->status_max, "sigma_max run failed");
+  if (out->status_min) return fail(out->status_min, "sigma_min run failed");
+  return COND_OK;
+}
+
+int cond_plan_kernel_stats(const cond_plan_t* p, double* ms, int64_t* launches, double* bytes) {
+  if (!p || !ms || !launches) return fail(COND_EINVAL, "null argument");
+  for (int k = 0; k < COND_K_COUNT; ++k) {
+    ms[k] = p->kms[k];
+    launches[k] = p->kcnt[k];
+    if (bytes) bytes[k] = p->kcnt[k] ? p->kbytes[k] / static_cast<double>(p->kcnt[k]) : 0.0;
+  }
+  return COND_OK;
+}
+
+int cond_plan_spmv(cond_plan_t* p, int transpose, const double* x, double* y) {
+  if (!p || !x || !y) return fail(COND_EINVAL, "null argument");
+  if (!p->bound) return fail(COND_ESTATE, "plan not bound");
+  int st0 = join_user_stream(p);
+  if (st0) return st0;
+  launch_spmv(transpose ? p->dAt : p->dA, x, y, nullptr, p->grid, nullptr, p->stream);
+  CHK(hipGetLastError());
+  CHK(hipStreamSynchronize(p->stream));
+  return COND_OK;
+}
+
+int cond_plan_inverse_apply(cond_plan_t* p, const double* x, double* r, double* s) {
+  if (!p || !x || !r || !s) return fail(COND_EINVAL, "null argument");
+  if (!p->bound) return fail(COND_ESTATE, "plan not bound");
+  if (!p->want_min) return fail(COND_ESTATE, "plan has no LU (sigma_min_method = NONE)");
+  int st0 = join_user_stream(p);
+  if (st0) return st0;
+  hipStream_t st = p->stream;
+  CHK(hipMemsetAsync(p->st_free, 0, sizeof(RunState), st));
+  launch_zero_u32(p->tickets, 4, st);
+  launch_fill(p->n, p->c, kPending, st);
+  launch_fill(p->n, p->z, kPending, st);
+  launch_fill(p->n, p->h, kPending, st);
+  launch_fill(p->n, p->wv, kPending, st);
+  launch_trsv(p->dL, x, p->d_row_perm, p->c, nullptr, nullptr, p->tickets + 0, p->st_free, st);
+  launch_trsv(p->dU, p->c, nullptr, p->z, r, p->d_col_perm, p->tickets + 1, p->st_free, st);
+  launch_trsv(p->dUt, p->z, nullptr, p->h, nullptr, nullptr, p->tickets + 2, p->st_free, st);
+  launch_trsv(p->dLt, p->h, nullptr, p->wv, s, p->d_row_perm, p->tickets + 3, p->st_free, st);
+  CHK(hipGetLastError());
+  RunState hs;
+  CHK(hipMemcpyAsync(&hs, p->st_free, sizeof(RunState), hipMemcpyDeviceToHost, st));
+  CHK(hipStreamSynchronize(st));
+  if (hs.abort_wait) return fail(COND_ETIMEOUT, "triangular-solve wait timed out");
+  return COND_OK;
+}
+
+int cond_estimate(const cond_csr_t* A, const cond_opts_t* o, const double* x0_max,
+                  const double* x0_min, void* stream, cond_result_t* out) {
+  cond_plan_t* p = nullptr;
+  int st = cond_plan_create(A, o, &p);
+  if (st) return st;
+  st = cond_plan_bind(p, nullptr, 0, stream);
+  if (!st) st = cond_plan_run(p, o, x0_max, x0_min, out, nullptr, nullptr, nullptr, nullptr);
+  cond_plan_destroy(p);
+  return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,142 @@
+"""CPU checks of the C-ABI library: exported symbols and the host set-up steps.
+
+These call only the host-side entry points (no device is touched): the
+explicit transpose, the nested-dissection order and the sparse LU that the
+plan builds before any kernel runs. They are checked against the oracle's
+independent transpose and against mathematical properties of the factors.
+"""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import paper_2409_11515_amd as pa
+from paper_2409_11515_amd import _binding
+from oracle.csr import transpose_csr
+from synth import Csr, hydromech2d, scaled_banded, stokes2d, start_vector
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "condest.h")).read()
+    declared = set(re.findall(r"\b(cond_[a-z_0-9]+)\s*\(", hdr))
+    assert declared == set(_binding.EXPORTS)
+    L = _binding.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+    assert pa.version() >= 1
+
+
+def test_transpose_matches_oracle_bitwise():
+    a = hydromech2d(12, seed=3)
+    tr, tc, tv = pa.csr_transpose(a.n, a.rowptr, a.col, a.val)
+    orp, oc, ov = transpose_csr(a.n, a.rowptr, a.col, a.val)
+    np.testing.assert_array_equal(tr, orp)
+    np.testing.assert_array_equal(tc, oc)
+    np.testing.assert_array_equal(tv, ov)
+
+
+def test_transpose_empty_rows_and_unsorted_input():
+    d = np.array([[0, 0, 0, 0], [3.0, 0, 1.0, 0], [0, 0, 0, 0], [0, 2.0, 0, 5.0]])
+    rowptr = np.array([0, 0, 2, 2, 4])
+    col = np.array([2, 0, 3, 1])  # unsorted within rows
+    val = np.array([1.0, 3.0, 5.0, 2.0])
+    tr, tc, tv = pa.csr_transpose(4, rowptr, col, val)
+    t = sp.csr_matrix((tv, tc, tr), shape=(4, 4)).toarray()
+    np.testing.assert_array_equal(t, d.T)
+
+
+@pytest.mark.parametrize("bad", [
+    (2, [0, 1], [0], [1.0]),
+    (2, [0, 1, 1], [2], [1.0]),
+    (2, [0, 1, 2], [0, 1], [1.0, np.inf]),
+    (2, [0, 2, 1], [0, 1], [1.0, 1.0]),
+    (2, [0, 0, 0], [], []),
+    (0, [0], [], []),
+])
+def test_csr_check_rejects(bad):
+    n, rp, col, val = bad
+    rp = np.array(rp, np.int64)
+    if rp.size != n + 1:
+        # the binding sizes nnz from rowptr; pass a struct with a short rowptr on purpose
+        h = _binding.HostCsr(max(n, 1), np.append(rp, rp[-1]), col, val)
+        h.struct.n = n if n > 0 else 0
+        h.struct.nnz = 99
+        st = _binding.lib().cond_csr_check(C.byref(h.struct))
+        assert st == _binding.COND_EINVAL
+        return
+    with pytest.raises(pa.CondError) as e:
+        pa.csr_check(n, rp, col, val)
+    assert e.value.status == _binding.COND_EINVAL
+
+
+def test_nd_order_is_a_permutation():
+    a = hydromech2d(20, seed=1)
+    p = pa.order_nd(a.n, a.rowptr, a.col, a.val)
+    assert sorted(p.tolist()) == list(range(a.n))
+
+
+@pytest.mark.parametrize("mk", [
+    lambda: stokes2d(10, 10, seed=0),
+    lambda: scaled_banded(3000, seed=5),
+    lambda: hydromech2d(30, seed=2),
+])
+def test_lu_factors_reproduce_pa_q(mk):
+    a = mk()
+    lu = pa.LU(a.n, a.rowptr, a.col, a.val)
+    f = lu.export()
+    n = a.n
+    L = sp.csr_matrix((f["l_val"], f["l_col"], f["l_rowptr"]), shape=(n, n)) + sp.eye(n)
+    U = sp.csr_matrix((f["u_val"], f["u_col"], f["u_rowptr"]), shape=(n, n)) + sp.diags(f["u_diag"])
+    assert sp.triu(L, 1).nnz == 0 and sp.tril(U, -1).nnz == 0
+    assert sorted(f["row_perm"].tolist()) == list(range(n))
+    assert sorted(f["col_perm"].tolist()) == list(range(n))
+    A = a.to_scipy()
+    paq = A[f["row_perm"]][:, f["col_perm"]]
+    # componentwise: |PAQ - LU| <= c eps |L||U|, checked on random vectors
+    z = start_vector(n, 3)
+    lhs = np.abs(paq @ z - L @ (U @ z))
+    rhs = abs(L) @ (abs(U) @ np.abs(z))
+    assert np.max(lhs / np.maximum(rhs, 1e-300)) < 1e-12
+
+
+@pytest.mark.parametrize("trans", [False, True])
+def test_lu_host_solve_backward_error(trans):
+    a = hydromech2d(24, seed=4)
+    lu = pa.LU(a.n, a.rowptr, a.col, a.val)
+    A = a.to_scipy()
+    M = A.T if trans else A
+    x = start_vector(a.n, 8)
+    r = lu.solve(x, trans=trans)
+    be = np.max(np.abs(M @ r - x) / (abs(M) @ np.abs(r) + np.abs(x)))
+    assert be < 1e-9
+
+
+def test_lu_singular_matrix_reports_esingular():
+    d = np.eye(5)
+    d[3, 3] = 0.0
+    d[3, 1] = 0.0
+    a = Csr.from_scipy(sp.csr_matrix(d))
+    with pytest.raises(pa.CondError) as e:
+        pa.LU(a.n, a.rowptr, a.col, a.val)
+    assert e.value.status == _binding.COND_ESINGULAR
+
+
+def test_lu_rejects_bad_col_perm():
+    a = scaled_banded(20, seed=1)
+    with pytest.raises(pa.CondError) as e:
+        pa.LU(a.n, a.rowptr, a.col, a.val, col_perm=np.zeros(20, np.int32))
+    assert e.value.status == _binding.COND_EINVAL
+
+
+def test_plan_create_on_host_reports_workspace():
+    # plan_create does host work only; its workspace size must cover the data
+    a = hydromech2d(10, seed=1)
+    p = pa.Plan(a.n, a.rowptr, a.col, a.val)
+    assert p.workspace_bytes >= 12 * 2 * a.nnz + 8 * 10 * a.n
+    p.close()

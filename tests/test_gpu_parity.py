@@ -1,0 +1,236 @@
+"""GPU path against the oracle, element by element, through the C ABI.
+
+Bars: SpMV and A^T-SpMV within 1e-12 of |A||x| componentwise (bitwise on
+integer data); Algorithm 2's solves by componentwise backward error and
+against the oracle's SuperLU solves; kappa within 1e-3 of the oracle on the
+same seeded inputs (and within 1e-9 on closed forms); the first traced steps
+in lockstep with the oracle; bitwise run-to-run determinism.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import PAOptions, estimate_cond as oracle_estimate
+from oracle.csr import spmv as oracle_spmv, spmv_abs, transpose_csr
+from oracle.exact import kappa_blockdiag2
+from oracle.inverse import LUInverse
+from synth import Csr, diag_csr, hydromech2d, scaled_banded, start_vector, stokes2d
+from synth.matrices import block_diag_2x2
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2409_11515_amd as pa
+
+    pa._binding.lib()  # fails loudly if the library was not built
+    return torch
+
+
+def _plan(a, **kw):
+    import paper_2409_11515_amd as pa
+
+    return pa.Plan(a.n, a.rowptr, a.col, a.val, **kw).bind()
+
+
+def _dev(torch, x):
+    return torch.as_tensor(np.ascontiguousarray(x, np.float64), device="cuda")
+
+
+# ------------------------------------------------------------------ SpMV
+@pytest.mark.parametrize("side", [5, 40])
+def test_spmv_parity(torch_cuda, side):
+    torch = torch_cuda
+    a = hydromech2d(side, seed=7)
+    p = _plan(a, sigma_min_method=2)
+    x = start_vector(a.n, 5) * 10.0 ** np.random.default_rng(1).uniform(-5, 5, a.n)
+    y = p.spmv(_dev(torch, x)).cpu().numpy()
+    ref = oracle_spmv(a.rowptr, a.col, a.val, x)
+    bound = spmv_abs(a.rowptr, a.col, a.val, x)
+    assert np.all(np.abs(y - ref) <= 1e-12 * bound + 1e-300)
+    tr, tc, tv = transpose_csr(a.n, a.rowptr, a.col, a.val)
+    yt = p.spmv(_dev(torch, x), transpose=True).cpu().numpy()
+    reft = oracle_spmv(tr, tc, tv, x)
+    boundt = spmv_abs(tr, tc, tv, x)
+    assert np.all(np.abs(yt - reft) <= 1e-12 * boundt + 1e-300)
+    p.close()
+
+
+def test_spmv_bitwise_on_integers(torch_cuda):
+    torch = torch_cuda
+    rng = np.random.default_rng(4)
+    n = 5000
+    m = sp.random(n, n, density=0.002, random_state=3, format="csr") + sp.eye(n)
+    m.data = rng.integers(-(2**20), 2**20, m.nnz).astype(float)
+    a = Csr.from_scipy(m)
+    p = _plan(a, sigma_min_method=2)
+    x = rng.integers(-(2**20), 2**20, n).astype(float)
+    y = p.spmv(_dev(torch, x)).cpu().numpy()
+    exact = (m.astype(np.int64) @ x.astype(np.int64)).astype(float)
+    np.testing.assert_array_equal(y, exact)
+    yt = p.spmv(_dev(torch, x), transpose=True).cpu().numpy()
+    np.testing.assert_array_equal(yt, (m.T.astype(np.int64) @ x.astype(np.int64)).astype(float))
+    p.close()
+
+
+def test_spmv_ragged_rows(torch_cuda):
+    # rows from 0 to 150 entries: exercises empty rows and rows longer than a wave
+    torch = torch_cuda
+    rng = np.random.default_rng(9)
+    n = 777
+    lens = rng.integers(0, 151, n)
+    lens[::50] = 0
+    rows = np.repeat(np.arange(n), lens)
+    cols = rng.integers(0, n, rows.size)
+    m = sp.csr_matrix((rng.standard_normal(rows.size), (rows, cols)), shape=(n, n))
+    m = m + sp.eye(n) * 0.0 + sp.csr_matrix(([1.0], ([0], [0])), shape=(n, n))
+    a = Csr.from_scipy(m)
+    p = _plan(a, sigma_min_method=2)
+    x = rng.standard_normal(n)
+    y = p.spmv(_dev(torch, x)).cpu().numpy()
+    ref = oracle_spmv(a.rowptr, a.col, a.val, x)
+    assert np.all(np.abs(y - ref) <= 1e-12 * spmv_abs(a.rowptr, a.col, a.val, x) + 1e-300)
+    p.close()
+
+
+# -------------------------------------------------------- Algorithm 2 solves
+@pytest.mark.parametrize("mk", [lambda: stokes2d(10, 10, seed=0), lambda: hydromech2d(30, seed=3)])
+def test_inverse_apply_parity(torch_cuda, mk):
+    torch = torch_cuda
+    a = mk()
+    p = _plan(a)
+    x = start_vector(a.n, 2)
+    r, s = p.inverse_apply(_dev(torch, x))
+    r = r.cpu().numpy()
+    s = s.cpu().numpy()
+    A = a.to_scipy()
+    be_r = np.max(np.abs(A @ r - x) / (abs(A) @ np.abs(r) + np.abs(x)))
+    be_s = np.max(np.abs(A.T @ s - r) / (abs(A.T) @ np.abs(s) + np.abs(r)))
+    assert be_r < 1e-9 and be_s < 1e-9
+    inv = LUInverse(a.n, a.rowptr, a.col, a.val)
+    r_ref, s_ref = inv.apply(x)
+    # two different pivoted factorisations: agreement to the problem's sensitivity
+    assert np.linalg.norm(r - r_ref) <= 1e-6 * np.linalg.norm(r_ref)
+    assert np.linalg.norm(s - s_ref) <= 1e-6 * np.linalg.norm(s_ref)
+    p.close()
+
+
+# ------------------------------------------------------ end-to-end kappa
+def _both(torch, a, iters, seed=1, **kw):
+    x0 = start_vector(a.n, seed)
+    p = _plan(a)
+    g = p.run(_dev(torch, x0), max_iter=iters, trace=True, **kw)
+    p.close()
+    o = oracle_estimate(a.n, a.rowptr, a.col, a.val, x0,
+                        opts=PAOptions(max_iter=iters, stop_rtol=kw.get("stop_rtol", 0.0),
+                                       stop_window=kw.get("stop_window", 0)))
+    return g, o
+
+
+def test_diagonal_closed_form_gpu(torch_cuda):
+    rng = np.random.default_rng(100)
+    n = 40
+    d = rng.choice([-1.0, 1.0], n) * 10.0 ** rng.uniform(-12, 12, n)
+    a = diag_csr(d, rng.permutation(n), rng.permutation(n))
+    g, o = _both(torch_cuda, a, 4000)
+    assert g["sigma_max"] == pytest.approx(np.abs(d).max(), rel=1e-12)
+    assert g["sigma_min"] == pytest.approx(np.abs(d).min(), rel=1e-12)
+
+
+def test_block_diagonal_closed_form_gpu(torch_cuda):
+    rng = np.random.default_rng(11)
+    blocks = rng.standard_normal((20, 2, 2)) * 10.0 ** rng.uniform(-6, 6, (20, 1, 1))
+    blocks[:, 0, 1] *= 5.0
+    a = block_diag_2x2(blocks)
+    smax, smin, kap = kappa_blockdiag2(blocks)
+    g, o = _both(torch_cuda, a, 6000, seed=5)
+    assert g["kappa"] == pytest.approx(kap, rel=1e-8)
+
+
+def test_c1_stokes_parity_and_golden(torch_cuda):
+    with open(os.path.join(GOLDEN, "c1_stokes_10x10_seed0.json")) as f:
+        gold = json.load(f)
+    a = stokes2d(10, 10, seed=0)
+    g, o = _both(torch_cuda, a, 20000)
+    assert g["kappa"] == pytest.approx(o["kappa"], rel=1e-3)
+    assert g["kappa"] == pytest.approx(gold["kappa_svd"], rel=1e-3)
+    assert g["iters_max"] == 20000 and g["iters_min"] == 20000
+    # lockstep: the first 50 traced values agree far below the kappa bar
+    np.testing.assert_allclose(g["trace_max"][:50], o["trace_max"][:50], rtol=1e-10)
+    np.testing.assert_allclose(g["trace_min"][:50], o["trace_min"][:50], rtol=1e-8)
+
+
+@pytest.mark.parametrize("side,seed", [(13, 2), (31, 5)])
+def test_hm_parity(torch_cuda, side, seed):
+    a = hydromech2d(side, seed=seed)
+    g, o = _both(torch_cuda, a, 3000, seed=seed)
+    assert g["kappa"] == pytest.approx(o["kappa"], rel=1e-3)
+    assert g["kappa"] > 1e18
+    np.testing.assert_allclose(g["trace_max"][:50], o["trace_max"][:50], rtol=1e-10)
+
+
+def test_early_stop_same_iteration(torch_cuda):
+    a = hydromech2d(21, seed=4)
+    g, o = _both(torch_cuda, a, 5000, stop_rtol=1e-9, stop_window=50)
+    assert g["iters_max"] == o["iters_max"] and g["iters_min"] == o["iters_min"]
+    assert g["iters_max"] < 5000
+    assert g["kappa"] == pytest.approx(o["kappa"], rel=1e-3)
+
+
+def test_bitwise_determinism(torch_cuda):
+    torch = torch_cuda
+    a = hydromech2d(17, seed=6)
+    x0 = _dev(torch, start_vector(a.n, 3))
+    p = _plan(a)
+    r1 = p.run(x0, max_iter=500, trace=True)
+    r2 = p.run(x0, max_iter=500, trace=True)
+    p.close()
+    assert r1["kappa"] == r2["kappa"]
+    np.testing.assert_array_equal(r1["trace_max"], r2["trace_max"])
+    np.testing.assert_array_equal(r1["trace_min"], r2["trace_min"])
+
+
+def test_power_of_two_scaling_bitwise_gpu(torch_cuda):
+    torch = torch_cuda
+    a = scaled_banded(3000, seed=2, col_decades=4, row_decades=2)
+    b = Csr(a.n, a.rowptr, a.col, a.val * 2.0**-30)
+    x0 = _dev(torch, start_vector(a.n, 4))
+    pa_ = _plan(a, sigma_min_method=2)
+    pb = _plan(b, sigma_min_method=2)
+    ra = pa_.run(x0, max_iter=300, trace=True)
+    rb = pb.run(x0, max_iter=300, trace=True)
+    pa_.close()
+    pb.close()
+    assert rb["sigma_max"] == ra["sigma_max"] * 2.0**-30
+    np.testing.assert_array_equal(rb["trace_max"], ra["trace_max"] * 2.0**-30)
+
+
+def test_zero_start_is_a_numeric_error(torch_cuda):
+    import paper_2409_11515_amd as pa
+
+    torch = torch_cuda
+    a = hydromech2d(8, seed=1)
+    p = _plan(a)
+    with pytest.raises(pa.CondError) as e:
+        p.run(torch.zeros(a.n, dtype=torch.float64, device="cuda"), max_iter=10)
+    assert e.value.status == pa._binding.COND_ENUMERIC
+    p.close()
+
+
+def test_n_equals_one(torch_cuda):
+    torch = torch_cuda
+    a = diag_csr(np.array([-3.5]))
+    p = _plan(a)
+    r = p.run(_dev(torch, np.array([2.0])), max_iter=5)
+    p.close()
+    assert r["sigma_max"] == 3.5 and r["sigma_min"] == 3.5 and r["kappa"] == 1.0
