@@ -169,78 +169,160 @@ __global__ __launch_bounds__(kBlock) void sumsq_k(int n, const double* __restric
 }
 
 // ----------------------------------------------------------------- trsv
-// Sparse triangular solve, one wave per row, rows taken in chunks from a
-// ticket counter in dependency order (increasing rows for a lower factor,
-// decreasing for an upper one). Every dependency of a row therefore belongs
-// to a chunk handed out earlier -- to this wave, already finished, or to a
-// wave that is resident and itself only waits on earlier chunks -- so the
-// waits always end. A solved entry is published by one 64-bit atomic store;
-// until then it holds the kPending pattern, so the value is its own ready
-// flag. A wait that spins past kSpinLimit marks the run aborted and returns
-// NaN instead of hanging.
-constexpr int kChunkRows = 16;
-constexpr unsigned kSpinLimit = 1u << 21;
+// Sparse lower-triangular solve in solve order (upper factors arrive
+// reversed), one panel (at most 64 consecutive rows) per 1024-thread block.
+// Tickets hand panels out in order of their dependency level, so every panel
+// a block waits on was handed out earlier -- finished, or held by a resident
+// block that itself only waits on panels of lower level -- and every wait
+// ends.
+//
+// Phase 1: the 16 waves compute, for the panel's rows, the sum of the
+// entries whose columns lie in earlier panels (4 rows per wave, 64 lanes per
+// row, loads unrolled for memory-level parallelism), and scatter the
+// in-panel entries into a column-major 64x64 LDS block. Phase 2: wave 0
+// runs the in-panel forward substitution column by column (lane r owns row
+// r: one LDS read and one shuffle per column), then publishes the panel. A solved entry is
+// published by one 64-bit atomic store; until then it holds the kPending
+// pattern, so the value is its own ready flag. Waits back off exponentially
+// and give up after a bounded number of sleeps, marking the run aborted
+// (NaN results) instead of hanging.
+constexpr unsigned kSleepLimit = 1u << 26;  // sleep units (64 clocks each) per wait
+constexpr int kTrsvBlock = 1024;
+constexpr int kUnroll = 8;
 
-__device__ __forceinline__ double wait_value(const double* p, RunState* st) {
+__device__ __noinline__ double wait_pending(const double* p, RunState* st) {
   const unsigned long long* q = reinterpret_cast<const unsigned long long*>(p);
-  // cached read first; only a still-pending entry goes to the coherent level
-  unsigned long long bits =
-      __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-  if (bits != kPending) return __longlong_as_double(static_cast<long long>(bits));
-  unsigned spins = 0;
+  unsigned slept = 0, backoff = 1, polls = 0;
+  unsigned long long bits;
   for (;;) {
     bits = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (bits != kPending) break;
-    ++spins;
-    if ((spins & 255u) == 0u) {
+    if ((++polls & 63u) == 0u) {
       if (__hip_atomic_load(&st->abort_wait, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
         return __longlong_as_double(0x7FF8000000000000ll);
-      if (spins >= kSpinLimit) {
+      if (slept >= kSleepLimit) {
         __hip_atomic_store(&st->abort_wait, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return __longlong_as_double(0x7FF8000000000000ll);
       }
     }
-    __builtin_amdgcn_s_sleep(1);
+    for (unsigned k = 0; k < backoff; ++k) __builtin_amdgcn_s_sleep(1);
+    slept += backoff;
+    if (backoff < 32u) backoff <<= 1;
   }
   return __longlong_as_double(static_cast<long long>(bits));
 }
 
-template <bool UPPER, bool UNIT>
-__global__ __launch_bounds__(kBlock) void trsv_k(int n, const long long* __restrict__ rowptr,
-                                                 const int* __restrict__ col,
-                                                 const double* __restrict__ val,
-                                                 const double* __restrict__ diag,
-                                                 const double* __restrict__ rhs,
-                                                 const int* __restrict__ rhs_perm, double* out,
-                                                 double* __restrict__ scatter,
-                                                 const int* __restrict__ scatter_perm,
-                                                 unsigned* ticket, RunState* st) {
-  if (st->stop_req || st->abort_wait) return;
+// Cached read of a solved entry; a still-pending one is re-read at the
+// coherent level until it is published.
+__device__ __forceinline__ unsigned long long peek(const double* p) {
+  return __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+template <bool UNIT>
+__global__ __launch_bounds__(kTrsvBlock) void trsv_k(
+    int n, const long long* __restrict__ off_rp, const int* __restrict__ off_col,
+    const double* __restrict__ off_val, const long long* __restrict__ in_rp,
+    const int* __restrict__ in_col, const double* __restrict__ in_val,
+    const double* __restrict__ diag, int npanels, const int* __restrict__ pstart,
+    const int* __restrict__ order, const double* __restrict__ rhs,
+    const int* __restrict__ rhs_perm, double* out, double* __restrict__ scatter,
+    const int* __restrict__ scatter_perm, unsigned* ticket, RunState* st) {
+  __shared__ double m_sh[kPanel * kPanel];  // in-panel triangle, column-major: (r, c) at c*64 + r
+  __shared__ double t_sh[kPanel];
+  __shared__ unsigned panel_sh;
+  __shared__ int quit_sh;
+  // one read for the whole block: abort_wait may change while blocks start
+  if (threadIdx.x == 0)
+    quit_sh = st->stop_req ||
+              __hip_atomic_load(&st->abort_wait, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  if (quit_sh) return;
   const int lane = threadIdx.x & 63;
-  const unsigned nchunks = static_cast<unsigned>((static_cast<long long>(n) + kChunkRows - 1) / kChunkRows);
+  const int wave = threadIdx.x >> 6;
+  constexpr int kWaves = kTrsvBlock / 64;
+  constexpr int kRowsPerWave = kPanel / kWaves;
   for (;;) {
-    unsigned c = 0;
-    if (lane == 0) c = atomicAdd(ticket, 1u);
-    c = __shfl(c, 0, 64);
-    if (c >= nchunks) break;
-    for (int r = 0; r < kChunkRows; ++r) {
-      const long long k = static_cast<long long>(c) * kChunkRows + r;
-      if (k >= n) break;
-      const int i = UPPER ? static_cast<int>(n - 1 - k) : static_cast<int>(k);
-      const long long p0 = rowptr[i], p1 = rowptr[i + 1];
+    if (threadIdx.x == 0) panel_sh = atomicAdd(ticket, 1u);
+    for (int k = threadIdx.x; k < kPanel * kPanel; k += kTrsvBlock) m_sh[k] = 0.0;
+    __syncthreads();
+    const unsigned T = panel_sh;
+    if (T >= static_cast<unsigned>(npanels)) break;
+    const int P = order[T];
+    const long long lo = pstart[P];
+    const int cnt = pstart[P + 1] - pstart[P];
+    // wave 0 fetches what the in-panel solve needs while the others start
+    double b = 0.0, dg = 1.0;
+    if (wave == 0 && lane < cnt) {
+      const long long i = lo + lane;
+      b = rhs_perm ? rhs[rhs_perm[i]] : rhs[i];
+      if (!UNIT) dg = diag[i];
+    }
+    // ---- phase 1: off-panel sums and the in-panel triangle into LDS
+    long long rp[kRowsPerWave + 1];
+    long long ip[kRowsPerWave + 1];
+#pragma unroll
+    for (int k = 0; k < kRowsPerWave; ++k) {
+      const int r = wave + k * kWaves;
+      rp[k] = r < cnt ? off_rp[lo + r] : 0;
+      ip[k] = r < cnt ? in_rp[lo + r] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < kRowsPerWave; ++k) {
+      const int r = wave + k * kWaves;
+      if (r >= cnt) break;
+      const long long p0 = rp[k], p1 = off_rp[lo + r + 1];
+      const long long e0 = ip[k], e1 = in_rp[lo + r + 1];
+      // in-panel entries of row r (fewer than 64): one column-major slot each
+      for (long long e = e0 + lane; e < e1; e += 64) m_sh[in_col[e] * kPanel + r] = in_val[e];
       double acc = 0.0;
-      for (long long p = p0 + lane; p < p1; p += 64) acc += val[p] * wait_value(out + col[p], st);
+      for (long long base = p0; base < p1; base += 64 * kUnroll) {
+        int j[kUnroll];
+        double a[kUnroll];
+        unsigned long long bits[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const long long p = base + u * 64 + lane;
+          const bool act = p < p1;
+          j[u] = act ? off_col[p] : -1;
+          a[u] = act ? off_val[p] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) bits[u] = j[u] >= 0 ? peek(out + j[u]) : 0ull;
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          if (j[u] >= 0) {
+            const double xj = bits[u] != kPending
+                                  ? __longlong_as_double(static_cast<long long>(bits[u]))
+                                  : wait_pending(out + j[u], st);
+            acc += a[u] * xj;
+          }
+        }
+      }
       acc = wave_sum(acc);
-      if (lane == 0) {
-        const double b = rhs_perm ? rhs[rhs_perm[i]] : rhs[i];
-        double xi = b - acc;
-        if (!UNIT) xi = xi / diag[i];
+      if (lane == 0) t_sh[r] = acc;
+    }
+    __syncthreads();
+    // ---- phase 2: in-panel forward substitution, column by column; lane r owns row r
+    if (wave == 0) {
+      double acc = lane < cnt ? b - t_sh[lane] : 0.0;  // rhs minus everything solved so far
+      double mine = 0.0;
+      for (int s = 0; s < cnt; ++s) {
+        double xs = acc;
+        if (!UNIT) xs = xs / dg;
+        xs = __shfl(xs, s, 64);
+        if (lane == s) mine = xs;
+        if (lane > s) acc -= m_sh[s * kPanel + lane] * xs;
+      }
+      if (lane < cnt) {
+        const long long i = lo + lane;
         __hip_atomic_store(reinterpret_cast<unsigned long long*>(out + i),
-                           static_cast<unsigned long long>(__double_as_longlong(xi)),
+                           static_cast<unsigned long long>(__double_as_longlong(mine)),
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (scatter) scatter[scatter_perm[i]] = xi;
+        if (scatter) scatter[scatter_perm[i]] = mine;
       }
     }
+    __syncthreads();  // m_sh, t_sh and panel_sh are reused by the next panel
   }
 }
 
@@ -429,27 +511,18 @@ void launch_sumsq(int n, const double* z, double* parts, int grid, const RunStat
 void launch_trsv(const DevTri& t, const double* rhs, const int* rhs_perm, double* out,
                  double* scatter, const int* scatter_perm, unsigned* ticket, RunState* st,
                  hipStream_t s) {
-  const long long chunks = (static_cast<long long>(t.n) + kChunkRows - 1) / kChunkRows;
-  long long blocks = (chunks + (kBlock / 64) - 1) / (kBlock / 64);
-  if (blocks > 2048) blocks = 2048;
+  const long long panels = t.npanels;
+  long long blocks = panels < 512 ? panels : 512;
   if (blocks < 1) blocks = 1;
   const int g = static_cast<int>(blocks);
-  const bool unit = (t.diag == nullptr);
-  if (t.upper) {
-    if (unit)
-      trsv_k<true, true><<<g, kBlock, 0, s>>>(t.n, t.rowptr, t.col, t.val, t.diag, rhs, rhs_perm,
-                                               out, scatter, scatter_perm, ticket, st);
-    else
-      trsv_k<true, false><<<g, kBlock, 0, s>>>(t.n, t.rowptr, t.col, t.val, t.diag, rhs, rhs_perm,
-                                                out, scatter, scatter_perm, ticket, st);
-  } else {
-    if (unit)
-      trsv_k<false, true><<<g, kBlock, 0, s>>>(t.n, t.rowptr, t.col, t.val, t.diag, rhs, rhs_perm,
-                                                out, scatter, scatter_perm, ticket, st);
-    else
-      trsv_k<false, false><<<g, kBlock, 0, s>>>(t.n, t.rowptr, t.col, t.val, t.diag, rhs,
-                                                 rhs_perm, out, scatter, scatter_perm, ticket, st);
-  }
+  if (t.diag)
+    trsv_k<false><<<g, kTrsvBlock, 0, s>>>(t.n, t.off_rp, t.off_col, t.off_val, t.in_rp, t.in_col,
+                                           t.in_val, t.diag, t.npanels, t.pstart, t.order, rhs,
+                                           rhs_perm, out, scatter, scatter_perm, ticket, st);
+  else
+    trsv_k<true><<<g, kTrsvBlock, 0, s>>>(t.n, t.off_rp, t.off_col, t.off_val, t.in_rp, t.in_col,
+                                          t.in_val, t.diag, t.npanels, t.pstart, t.order, rhs,
+                                          rhs_perm, out, scatter, scatter_perm, ticket, st);
 }
 
 void launch_pass1(int n, const double* x, const double* w, double* m, double* v, double* d,

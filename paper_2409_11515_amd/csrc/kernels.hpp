@@ -64,14 +64,24 @@ struct DevCsr {
   int lpr = 8;  // lanes per row for the SpMV (power of two, 4..64)
 };
 
-// A strictly triangular factor for a row-oriented solve (int64 rowptr).
+// A lower-triangular factor in solve order, split into panels of at most 64
+// rows: the entries of a panel's rows with a column before the panel ("off")
+// and the ones inside it ("in", column stored relative to the panel start).
+// Upper factors are reversed on the host (row i -> n-1-i) so every solve is
+// a forward substitution.
+constexpr int kPanel = 64;
 struct DevTri {
   int n = 0;
-  const long long* rowptr = nullptr;
-  const int* col = nullptr;
-  const double* val = nullptr;
+  const long long* off_rp = nullptr;
+  const int* off_col = nullptr;
+  const double* off_val = nullptr;
+  const long long* in_rp = nullptr;
+  const int* in_col = nullptr;  // 0..63, column relative to the panel start
+  const double* in_val = nullptr;
   const double* diag = nullptr;  // nullptr: unit diagonal
-  int upper = 0;                 // 1: backward substitution (row i needs j > i)
+  int npanels = 0;
+  const int* pstart = nullptr;   // panel p holds rows [pstart[p], pstart[p+1]), at most 64
+  const int* order = nullptr;    // ticket t solves panel order[t] (dependency-level order)
 };
 
 int grid_for(int n);  // fixed grid size of the reduction kernels for length n

@@ -55,6 +55,102 @@ struct GraphKey {
   }
 };
 
+// A strictly lower-triangular factor in solve order, cut into panels of at
+// most 64 consecutive rows, each split into the entries left of the panel
+// and the entries inside it, plus the order in which panels are handed out.
+struct PanelCsr {
+  int32_t n = 0;
+  std::vector<int64_t> off_rp, in_rp;
+  std::vector<int32_t> off_col, in_col;
+  std::vector<double> off_val, in_val;
+  std::vector<int32_t> pstart;  // panel p holds rows [pstart[p], pstart[p+1])
+  std::vector<int32_t> order;   // panels sorted by dependency level, then index
+  int32_t levels = 0;
+};
+
+// Panel boundaries: a panel closes when it holds 64 rows, or -- once it holds
+// at least kMinPanelRows -- before a row that needs nothing inside it. Such a
+// row usually opens an independent subtree of the elimination order (a new
+// leaf of the nested dissection); cutting there keeps independent subtrees in
+// different panels, so they are solved in parallel instead of as a chain.
+constexpr int32_t kMinPanelRows = 8;
+
+std::vector<int32_t> cut_panels(const HostCsr& t) {
+  std::vector<int32_t> ps{0};
+  int32_t s = 0;
+  for (int32_t e = 1; e < t.n; ++e) {
+    bool needs_panel = false;
+    for (int64_t p = t.rowptr[e]; p < t.rowptr[e + 1] && !needs_panel; ++p)
+      needs_panel = t.col[p] >= s;
+    if (e - s >= kPanel || (!needs_panel && e - s >= kMinPanelRows)) {
+      ps.push_back(e);
+      s = e;
+    }
+  }
+  ps.push_back(t.n);
+  return ps;
+}
+
+PanelCsr split_panels(const HostCsr& t) {
+  PanelCsr s;
+  s.n = t.n;
+  s.pstart = cut_panels(t);
+  const int32_t np = static_cast<int32_t>(s.pstart.size()) - 1;
+  std::vector<int32_t> pid(t.n);
+  for (int32_t p = 0; p < np; ++p)
+    for (int32_t i = s.pstart[p]; i < s.pstart[p + 1]; ++i) pid[i] = p;
+  // level of a panel: one more than the deepest panel it reads from
+  std::vector<int32_t> level(np, 0);
+  for (int32_t i = 0; i < t.n; ++i)
+    for (int64_t p = t.rowptr[i]; p < t.rowptr[i + 1]; ++p) {
+      const int32_t q = pid[t.col[p]];
+      if (q != pid[i]) level[pid[i]] = std::max(level[pid[i]], level[q] + 1);
+    }
+  s.order.resize(np);
+  for (int32_t p = 0; p < np; ++p) s.order[p] = p;
+  std::stable_sort(s.order.begin(), s.order.end(),
+                   [&](int32_t a, int32_t b) { return level[a] < level[b]; });
+  s.levels = np ? 1 + *std::max_element(level.begin(), level.end()) : 0;
+  s.off_rp.assign(t.n + 1, 0);
+  s.in_rp.assign(t.n + 1, 0);
+  for (int32_t i = 0; i < t.n; ++i) {
+    const int32_t lo = s.pstart[pid[i]];
+    for (int64_t p = t.rowptr[i]; p < t.rowptr[i + 1]; ++p) {
+      const int32_t j = t.col[p];
+      if (j < lo) {
+        s.off_col.push_back(j);
+        s.off_val.push_back(t.val[p]);
+      } else {
+        s.in_col.push_back(j - lo);
+        s.in_val.push_back(t.val[p]);
+      }
+    }
+    s.off_rp[i + 1] = static_cast<int64_t>(s.off_col.size());
+    s.in_rp[i + 1] = static_cast<int64_t>(s.in_col.size());
+  }
+  return s;
+}
+
+// Row i -> n-1-i and column j -> n-1-j: an upper factor becomes lower.
+HostCsr reverse_order(const HostCsr& u) {
+  HostCsr r;
+  const int32_t n = u.n;
+  r.n = n;
+  r.rowptr.assign(n + 1, 0);
+  r.col.reserve(u.nnz());
+  r.val.reserve(u.nnz());
+  for (int32_t k = 0; k < n; ++k) {
+    const int32_t i = n - 1 - k;
+    // walking row i backwards keeps the reversed columns increasing
+    for (int64_t p = u.rowptr[i + 1]; p-- > u.rowptr[i];) {
+      r.col.push_back(n - 1 - u.col[p]);
+      r.val.push_back(u.val[p]);
+    }
+    r.rowptr[k + 1] = static_cast<int64_t>(r.col.size());
+  }
+  return r;
+}
+
 int choose_lpr(double mean_nnz_per_row) {
   int l = 4;
   while (l < 64 && l < mean_nnz_per_row) l <<= 1;
@@ -79,9 +175,16 @@ struct cond_plan {
   size_t ws_bytes = 0;
   bool own_ws = false;
   DevCsr dA, dAt;
+  // the four solves of Algorithm 2, each a forward substitution in its own
+  // order: L (pivot order), U reversed, U^T (pivot order), L^T reversed
+  PanelCsr pL, pU, pUt, pLt;
+  std::vector<double> udiag_rev;
+  std::vector<int32_t> rev, scat_s, scat_r;
   DevTri dL, dU, dUt, dLt;
-  int* d_row_perm = nullptr;
-  int* d_col_perm = nullptr;
+  int* d_row_perm = nullptr;  // L rhs gather: x[row_perm[k]]
+  int* d_rev = nullptr;       // n-1-k
+  int* d_scat_s = nullptr;    // s[row_perm[n-1-k]] = result of the reversed L^T solve
+  int* d_scat_r = nullptr;    // r[col_perm[n-1-k]] = result of the reversed U solve
   double *x = nullptr, *m = nullptr, *v = nullptr, *d = nullptr, *y = nullptr, *w = nullptr;
   double *c = nullptr, *z = nullptr, *h = nullptr, *wv = nullptr;
   double *parts_x = nullptr, *parts_y = nullptr, *parts_xd = nullptr, *parts_xx = nullptr;
@@ -107,8 +210,8 @@ struct cond_plan {
   // offsets into the workspace
   struct {
     size_t a_rp, a_col, a_val, at_rp, at_col, at_val;
-    size_t l_rp, l_col, l_val, u_rp, u_col, u_val, ut_rp, ut_col, ut_val, lt_rp, lt_col, lt_val;
-    size_t u_diag, row_perm, col_perm;
+    size_t tri[4][8];
+    size_t u_diag, u_diag_rev, row_perm, rev, scat_s, scat_r;
     size_t vec[10];
     size_t parts[4];
     size_t st, st_free, tickets;
@@ -131,22 +234,24 @@ void plan_layout(cond_plan* p) {
   p->o.at_col = L.take(p->at.nnz() * 4);
   p->o.at_val = L.take(p->at.nnz() * 8);
   if (p->want_min) {
-    const cond_lu& f = *p->lu;
-    p->o.l_rp = L.take((n + 1) * 8);
-    p->o.l_col = L.take(f.l_rows.nnz() * 4);
-    p->o.l_val = L.take(f.l_rows.nnz() * 8);
-    p->o.u_rp = L.take((n + 1) * 8);
-    p->o.u_col = L.take(f.u_rows.nnz() * 4);
-    p->o.u_val = L.take(f.u_rows.nnz() * 8);
-    p->o.ut_rp = L.take((n + 1) * 8);
-    p->o.ut_col = L.take(f.u_cols.nnz() * 4);
-    p->o.ut_val = L.take(f.u_cols.nnz() * 8);
-    p->o.lt_rp = L.take((n + 1) * 8);
-    p->o.lt_col = L.take(f.l_cols.nnz() * 4);
-    p->o.lt_val = L.take(f.l_cols.nnz() * 8);
+    const PanelCsr* tris[4] = {&p->pL, &p->pU, &p->pUt, &p->pLt};
+    for (int f = 0; f < 4; ++f) {
+      const PanelCsr& t = *tris[f];
+      p->o.tri[f][0] = L.take((n + 1) * 8);
+      p->o.tri[f][1] = L.take(t.off_col.size() * 4);
+      p->o.tri[f][2] = L.take(t.off_val.size() * 8);
+      p->o.tri[f][3] = L.take((n + 1) * 8);
+      p->o.tri[f][4] = L.take(t.in_col.size() * 4);
+      p->o.tri[f][5] = L.take(t.in_val.size() * 8);
+      p->o.tri[f][6] = L.take(t.pstart.size() * 4);
+      p->o.tri[f][7] = L.take(t.order.size() * 4);
+    }
     p->o.u_diag = L.take(n * 8);
+    p->o.u_diag_rev = L.take(n * 8);
     p->o.row_perm = L.take(n * 4);
-    p->o.col_perm = L.take(n * 4);
+    p->o.rev = L.take(n * 4);
+    p->o.scat_s = L.take(n * 4);
+    p->o.scat_r = L.take(n * 4);
   }
   const int nvec = p->want_min ? 10 : 6;
   for (int k = 0; k < nvec; ++k) p->o.vec[k] = L.take(n * 8);
@@ -192,18 +297,28 @@ int upload_csr(cond_plan* p, const HostCsr& a, size_t rp, size_t col, size_t val
   return COND_OK;
 }
 
-int upload_tri(cond_plan* p, const HostCsr& t, size_t rp, size_t col, size_t val,
-               const double* diag_dev, int upper, DevTri& out) {
+int upload_tri(cond_plan* p, const PanelCsr& t, const size_t* off, const double* diag_dev,
+               DevTri& out) {
   int st;
-  if ((st = upload(p, rp, t.rowptr.data(), (t.n + 1) * 8))) return st;
-  if ((st = upload(p, col, t.col.data(), t.nnz() * 4))) return st;
-  if ((st = upload(p, val, t.val.data(), t.nnz() * 8))) return st;
+  if ((st = upload(p, off[0], t.off_rp.data(), (t.n + 1) * 8))) return st;
+  if ((st = upload(p, off[1], t.off_col.data(), t.off_col.size() * 4))) return st;
+  if ((st = upload(p, off[2], t.off_val.data(), t.off_val.size() * 8))) return st;
+  if ((st = upload(p, off[3], t.in_rp.data(), (t.n + 1) * 8))) return st;
+  if ((st = upload(p, off[4], t.in_col.data(), t.in_col.size() * 4))) return st;
+  if ((st = upload(p, off[5], t.in_val.data(), t.in_val.size() * 8))) return st;
+  if ((st = upload(p, off[6], t.pstart.data(), t.pstart.size() * 4))) return st;
+  if ((st = upload(p, off[7], t.order.data(), t.order.size() * 4))) return st;
   out.n = t.n;
-  out.rowptr = at_off<long long>(p, rp);
-  out.col = at_off<int>(p, col);
-  out.val = at_off<double>(p, val);
+  out.off_rp = at_off<long long>(p, off[0]);
+  out.off_col = at_off<int>(p, off[1]);
+  out.off_val = at_off<double>(p, off[2]);
+  out.in_rp = at_off<long long>(p, off[3]);
+  out.in_col = at_off<int>(p, off[4]);
+  out.in_val = at_off<double>(p, off[5]);
   out.diag = diag_dev;
-  out.upper = upper;
+  out.npanels = static_cast<int>(t.order.size());
+  out.pstart = at_off<int>(p, off[6]);
+  out.order = at_off<int>(p, off[7]);
   return COND_OK;
 }
 
@@ -279,18 +394,18 @@ void enqueue_iteration(cond_plan* p, int route, double* trace, double* xbest, co
     double* resets[4] = {p->c, p->z, p->h, p->wv};
     { Prof pr(p, COND_K_NORMALISE, 48.0 * dn);
       launch_normalise(n, p->x, p->parts_xx, g, p->parts_x, p->st, resets, 4, p->tickets, 4, s); }
-    // r = A^-1 x: L c = P x, U z = c (r = Q z; ||r|| = ||z||)
+    // r = A^-1 x: L c = P x, U z = c (r = Q z; ||r|| = ||z||); z is kept reversed
     { Prof pr(p, COND_K_TRSV_L, 12.0 * nl + rp + 28.0 * dn);
       launch_trsv(p->dL, p->x, p->d_row_perm, p->c, nullptr, nullptr, p->tickets + 0, p->st, s); }
-    { Prof pr(p, COND_K_TRSV_U, 12.0 * nu + rp + 32.0 * dn);
-      launch_trsv(p->dU, p->c, nullptr, p->z, nullptr, nullptr, p->tickets + 1, p->st, s); }
+    { Prof pr(p, COND_K_TRSV_U, 12.0 * nu + rp + 36.0 * dn);
+      launch_trsv(p->dU, p->c, p->d_rev, p->z, nullptr, nullptr, p->tickets + 1, p->st, s); }
     { Prof pr(p, COND_K_SUMSQ, 8.0 * dn);
       launch_sumsq(n, p->z, p->parts_y, g, p->st, s); }
-    // s = A^-T r: U^T h = Q^T r = z, L^T wv = h, s = P^T wv
-    { Prof pr(p, COND_K_TRSV_UT, 12.0 * nu + rp + 32.0 * dn);
-      launch_trsv(p->dUt, p->z, nullptr, p->h, nullptr, nullptr, p->tickets + 2, p->st, s); }
-    { Prof pr(p, COND_K_TRSV_LT, 12.0 * nl + rp + 36.0 * dn);
-      launch_trsv(p->dLt, p->h, nullptr, p->wv, p->w, p->d_row_perm, p->tickets + 3, p->st, s); }
+    // s = A^-T r: U^T h = Q^T r = z, L^T wv = h, s = P^T wv (wv kept reversed)
+    { Prof pr(p, COND_K_TRSV_UT, 12.0 * nu + rp + 36.0 * dn);
+      launch_trsv(p->dUt, p->z, p->d_rev, p->h, nullptr, nullptr, p->tickets + 2, p->st, s); }
+    { Prof pr(p, COND_K_TRSV_LT, 12.0 * nl + rp + 40.0 * dn);
+      launch_trsv(p->dLt, p->h, p->d_rev, p->wv, p->w, p->d_scat_s, p->tickets + 3, p->st, s); }
   }
   { Prof pr(p, COND_K_ADAM1, 56.0 * dn);
     launch_pass1(n, p->x, p->w, p->m, p->v, p->d, xbest, p->parts_x, p->parts_y, g, p->parts_xd,
@@ -464,6 +579,22 @@ int cond_plan_create(const cond_csr_t* A, const cond_opts_t* o, cond_plan_t** ou
       p->lu.reset(new cond_lu());
       st = lu_factor(p->a, p->at, o->col_perm, o->pivot_tol, *p->lu);
       if (st) return st;
+      const cond_lu& f = *p->lu;
+      const int32_t n = f.n;
+      p->pL = split_panels(f.l_rows);
+      p->pU = split_panels(reverse_order(f.u_rows));
+      p->pUt = split_panels(f.u_cols);
+      p->pLt = split_panels(reverse_order(f.l_cols));
+      p->udiag_rev.resize(n);
+      p->rev.resize(n);
+      p->scat_s.resize(n);
+      p->scat_r.resize(n);
+      for (int32_t k = 0; k < n; ++k) {
+        p->udiag_rev[k] = f.u_diag[n - 1 - k];
+        p->rev[k] = n - 1 - k;
+        p->scat_s[k] = f.row_perm[n - 1 - k];
+        p->scat_r[k] = f.col_perm[n - 1 - k];
+      }
     }
   } catch (const std::bad_alloc&) {
     return fail(COND_ENOMEM, "host memory exhausted in set-up");
@@ -512,15 +643,21 @@ int cond_plan_bind(cond_plan_t* p, void* workspace, size_t bytes, void* stream) 
   if (p->want_min) {
     const cond_lu& f = *p->lu;
     if ((st = upload(p, p->o.u_diag, f.u_diag.data(), p->n * 8))) return st;
+    if ((st = upload(p, p->o.u_diag_rev, p->udiag_rev.data(), p->n * 8))) return st;
     if ((st = upload(p, p->o.row_perm, f.row_perm.data(), p->n * 4))) return st;
-    if ((st = upload(p, p->o.col_perm, f.col_perm.data(), p->n * 4))) return st;
+    if ((st = upload(p, p->o.rev, p->rev.data(), p->n * 4))) return st;
+    if ((st = upload(p, p->o.scat_s, p->scat_s.data(), p->n * 4))) return st;
+    if ((st = upload(p, p->o.scat_r, p->scat_r.data(), p->n * 4))) return st;
     const double* dg = at_off<double>(p, p->o.u_diag);
-    if ((st = upload_tri(p, f.l_rows, p->o.l_rp, p->o.l_col, p->o.l_val, nullptr, 0, p->dL))) return st;
-    if ((st = upload_tri(p, f.u_rows, p->o.u_rp, p->o.u_col, p->o.u_val, dg, 1, p->dU))) return st;
-    if ((st = upload_tri(p, f.u_cols, p->o.ut_rp, p->o.ut_col, p->o.ut_val, dg, 0, p->dUt))) return st;
-    if ((st = upload_tri(p, f.l_cols, p->o.lt_rp, p->o.lt_col, p->o.lt_val, nullptr, 1, p->dLt))) return st;
+    const double* dgr = at_off<double>(p, p->o.u_diag_rev);
+    if ((st = upload_tri(p, p->pL, p->o.tri[0], nullptr, p->dL))) return st;
+    if ((st = upload_tri(p, p->pU, p->o.tri[1], dgr, p->dU))) return st;
+    if ((st = upload_tri(p, p->pUt, p->o.tri[2], dg, p->dUt))) return st;
+    if ((st = upload_tri(p, p->pLt, p->o.tri[3], nullptr, p->dLt))) return st;
     p->d_row_perm = at_off<int>(p, p->o.row_perm);
-    p->d_col_perm = at_off<int>(p, p->o.col_perm);
+    p->d_rev = at_off<int>(p, p->o.rev);
+    p->d_scat_s = at_off<int>(p, p->o.scat_s);
+    p->d_scat_r = at_off<int>(p, p->o.scat_r);
   }
   double** vecs[10] = {&p->x, &p->m, &p->v, &p->d, &p->y, &p->w, &p->c, &p->z, &p->h, &p->wv};
   const int nvec = p->want_min ? 10 : 6;
@@ -634,9 +771,9 @@ int cond_plan_inverse_apply(cond_plan_t* p, const double* x, double* r, double* 
   launch_fill(p->n, p->h, kPending, st);
   launch_fill(p->n, p->wv, kPending, st);
   launch_trsv(p->dL, x, p->d_row_perm, p->c, nullptr, nullptr, p->tickets + 0, p->st_free, st);
-  launch_trsv(p->dU, p->c, nullptr, p->z, r, p->d_col_perm, p->tickets + 1, p->st_free, st);
-  launch_trsv(p->dUt, p->z, nullptr, p->h, nullptr, nullptr, p->tickets + 2, p->st_free, st);
-  launch_trsv(p->dLt, p->h, nullptr, p->wv, s, p->d_row_perm, p->tickets + 3, p->st_free, st);
+  launch_trsv(p->dU, p->c, p->d_rev, p->z, r, p->d_scat_r, p->tickets + 1, p->st_free, st);
+  launch_trsv(p->dUt, p->z, p->d_rev, p->h, nullptr, nullptr, p->tickets + 2, p->st_free, st);
+  launch_trsv(p->dLt, p->h, p->d_rev, p->wv, s, p->d_scat_s, p->tickets + 3, p->st_free, st);
   CHK(hipGetLastError());
   RunState hs;
   CHK(hipMemcpyAsync(&hs, p->st_free, sizeof(RunState), hipMemcpyDeviceToHost, st));
