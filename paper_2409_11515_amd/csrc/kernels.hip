@@ -170,25 +170,30 @@ __global__ __launch_bounds__(kBlock) void sumsq_k(int n, const double* __restric
 
 // ----------------------------------------------------------------- trsv
 // Sparse lower-triangular solve in solve order (upper factors arrive
-// reversed), one panel (at most 64 consecutive rows) per 1024-thread block.
-// Tickets hand panels out in order of their dependency level, so every panel
-// a block waits on was handed out earlier -- finished, or held by a resident
-// block that itself only waits on panels of lower level -- and every wait
+// reversed). Work items ("tasks") are handed out by a ticket counter in the
+// order the host prepared: by dependency level of their panel (at most 64
+// consecutive rows). A task is a whole panel, or -- for a panel with many
+// entries left of it -- one slice of those entries, or the finish step of
+// such a panel. Every task a block waits on was handed out earlier: panels
+// of lower level, or the slices of its own panel; those are finished, or
+// held by resident blocks that only wait on lower levels, so every wait
 // ends.
 //
-// Phase 1: the 16 waves compute, for the panel's rows, the sum of the
-// entries whose columns lie in earlier panels (4 rows per wave, 64 lanes per
-// row, loads unrolled for memory-level parallelism), and scatter the
-// in-panel entries into a column-major 64x64 LDS block. Phase 2: wave 0
-// runs the in-panel forward substitution column by column (lane r owns row
-// r: one LDS read and one shuffle per column), then publishes the panel. A solved entry is
-// published by one 64-bit atomic store; until then it holds the kPending
-// pattern, so the value is its own ready flag. Waits back off exponentially
-// and give up after a bounded number of sleeps, marking the run aborted
-// (NaN results) instead of hanging.
+// Off-panel sums: each wave takes 4 rows at once, 16 lanes per row, loads
+// unrolled for memory-level parallelism. A slice task stores its partial
+// sums into fixed slots; the finish task adds the slices in slice order, so
+// the result does not depend on timing. In-panel part: the triangle is
+// staged in LDS column-major and wave 0 runs the forward substitution column
+// by column, lane r owning row r.
+//
+// Solved values and slice partials are published by one 64-bit atomic store
+// each; until then a slot holds the kPending pattern, so the value is its
+// own ready flag. Waits back off exponentially and give up after a bounded
+// number of sleeps, marking the run aborted (NaN results) instead of hanging.
 constexpr unsigned kSleepLimit = 1u << 26;  // sleep units (64 clocks each) per wait
 constexpr int kTrsvBlock = 1024;
 constexpr int kUnroll = 8;
+constexpr int kLanesPerRow = 16;
 
 __device__ __noinline__ double wait_pending(const double* p, RunState* st) {
   const unsigned long long* q = reinterpret_cast<const unsigned long long*>(p);
@@ -207,30 +212,79 @@ __device__ __noinline__ double wait_pending(const double* p, RunState* st) {
     }
     for (unsigned k = 0; k < backoff; ++k) __builtin_amdgcn_s_sleep(1);
     slept += backoff;
-    if (backoff < 32u) backoff <<= 1;
+    if (backoff < 16u) backoff <<= 1;
   }
   return __longlong_as_double(static_cast<long long>(bits));
 }
 
-// Cached read of a solved entry; a still-pending one is re-read at the
+// Cached read of a published slot; a still-pending one is re-read at the
 // coherent level until it is published.
-__device__ __forceinline__ unsigned long long peek(const double* p) {
-  return __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_WORKGROUP);
+__device__ __forceinline__ double ready_value(const double* p, RunState* st) {
+  const unsigned long long bits = __hip_atomic_load(
+      reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  return bits != kPending ? __longlong_as_double(static_cast<long long>(bits)) : wait_pending(p, st);
+}
+
+__device__ __forceinline__ void publish(double* p, double v) {
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p),
+                     static_cast<unsigned long long>(__double_as_longlong(v)), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(b), l);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), l);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+
+// Sum of off-panel entries [p0, p1) of one row against the solved values,
+// by the 16 lanes of a row group (sub = 0..15); every lane of the group gets it.
+__device__ __forceinline__ double row_sum(long long p0, long long p1, int sub,
+                                          const int* __restrict__ col,
+                                          const double* __restrict__ val, const double* out,
+                                          RunState* st) {
+  double acc = 0.0;
+  for (long long base = p0; base < p1; base += kLanesPerRow * kUnroll) {
+    int j[kUnroll];
+    double a[kUnroll];
+    unsigned long long bits[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const long long p = base + u * kLanesPerRow + sub;
+      const bool act = p < p1;
+      j[u] = act ? col[p] : -1;
+      a[u] = act ? val[p] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+      bits[u] = j[u] >= 0 ? __hip_atomic_load(reinterpret_cast<const unsigned long long*>(out + j[u]),
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)
+                          : 0ull;
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      if (j[u] >= 0) {
+        const double xj = bits[u] != kPending
+                              ? __longlong_as_double(static_cast<long long>(bits[u]))
+                              : wait_pending(out + j[u], st);
+        acc += a[u] * xj;
+      }
+    }
+  }
+#pragma unroll
+  for (int off = kLanesPerRow / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kLanesPerRow);
+  return acc;
 }
 
 template <bool UNIT>
-__global__ __launch_bounds__(kTrsvBlock) void trsv_k(
-    int n, const long long* __restrict__ off_rp, const int* __restrict__ off_col,
-    const double* __restrict__ off_val, const long long* __restrict__ in_rp,
-    const int* __restrict__ in_col, const double* __restrict__ in_val,
-    const double* __restrict__ diag, int npanels, const int* __restrict__ pstart,
-    const int* __restrict__ order, const double* __restrict__ rhs,
-    const int* __restrict__ rhs_perm, double* out, double* __restrict__ scatter,
-    const int* __restrict__ scatter_perm, unsigned* ticket, RunState* st) {
+__global__ __launch_bounds__(kTrsvBlock) void trsv_k(TrsvArgs t, const double* __restrict__ rhs,
+                                                     const int* __restrict__ rhs_perm, double* out,
+                                                     double* __restrict__ scatter,
+                                                     const int* __restrict__ scatter_perm,
+                                                     unsigned* ticket, RunState* st) {
   __shared__ double m_sh[kPanel * kPanel];  // in-panel triangle, column-major: (r, c) at c*64 + r
   __shared__ double t_sh[kPanel];
-  __shared__ unsigned panel_sh;
+  __shared__ unsigned task_sh;
   __shared__ int quit_sh;
   // one read for the whole block: abort_wait may change while blocks start
   if (threadIdx.x == 0)
@@ -240,89 +294,79 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_k(
   if (quit_sh) return;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  constexpr int kWaves = kTrsvBlock / 64;
-  constexpr int kRowsPerWave = kPanel / kWaves;
+  const int sub = lane & (kLanesPerRow - 1);
+  const int r = wave * (64 / kLanesPerRow) + lane / kLanesPerRow;  // this group's row, 0..63
   for (;;) {
-    if (threadIdx.x == 0) panel_sh = atomicAdd(ticket, 1u);
+    if (threadIdx.x == 0) task_sh = atomicAdd(ticket, 1u);
+    __syncthreads();
+    const unsigned T = task_sh;
+    if (T >= static_cast<unsigned>(t.ntasks)) break;
+    const int P = t.task_panel[T];
+    const int kind = t.task_kind[T];  // -1 whole panel, 0..S-1 slice, S finish
+    const long long lo = t.pstart[P];
+    const int cnt = t.pstart[P + 1] - t.pstart[P];
+    const int S = t.panel_split[P];
+    double* slots = t.partials + static_cast<long long>(t.panel_slot[P]) * kPanel;
+    if (kind >= 0 && kind < S) {
+      // ---- slice task: partial off-panel sums over one slice of every row
+      if (r < cnt) {
+        const long long p0 = t.off_rp[lo + r], p1 = t.off_rp[lo + r + 1];
+        const long long len = p1 - p0;
+        const double part = row_sum(p0 + len * kind / S, p0 + len * (kind + 1) / S, sub,
+                                    t.off_col, t.off_val, out, st);
+        if (sub == 0) publish(slots + static_cast<long long>(kind) * kPanel + r, part);
+      }
+      __syncthreads();  // task_sh is reused
+      continue;
+    }
     for (int k = threadIdx.x; k < kPanel * kPanel; k += kTrsvBlock) m_sh[k] = 0.0;
     __syncthreads();
-    const unsigned T = panel_sh;
-    if (T >= static_cast<unsigned>(npanels)) break;
-    const int P = order[T];
-    const long long lo = pstart[P];
-    const int cnt = pstart[P + 1] - pstart[P];
-    // wave 0 fetches what the in-panel solve needs while the others start
-    double b = 0.0, dg = 1.0;
+    double b = 0.0, dinv = 1.0;
     if (wave == 0 && lane < cnt) {
       const long long i = lo + lane;
       b = rhs_perm ? rhs[rhs_perm[i]] : rhs[i];
-      if (!UNIT) dg = diag[i];
+      if (!UNIT) dinv = 1.0 / t.diag[i];
     }
-    // ---- phase 1: off-panel sums and the in-panel triangle into LDS
-    long long rp[kRowsPerWave + 1];
-    long long ip[kRowsPerWave + 1];
-#pragma unroll
-    for (int k = 0; k < kRowsPerWave; ++k) {
-      const int r = wave + k * kWaves;
-      rp[k] = r < cnt ? off_rp[lo + r] : 0;
-      ip[k] = r < cnt ? in_rp[lo + r] : 0;
-    }
-#pragma unroll
-    for (int k = 0; k < kRowsPerWave; ++k) {
-      const int r = wave + k * kWaves;
-      if (r >= cnt) break;
-      const long long p0 = rp[k], p1 = off_rp[lo + r + 1];
-      const long long e0 = ip[k], e1 = in_rp[lo + r + 1];
-      // in-panel entries of row r (fewer than 64): one column-major slot each
-      for (long long e = e0 + lane; e < e1; e += 64) m_sh[in_col[e] * kPanel + r] = in_val[e];
-      double acc = 0.0;
-      for (long long base = p0; base < p1; base += 64 * kUnroll) {
-        int j[kUnroll];
-        double a[kUnroll];
-        unsigned long long bits[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          const long long p = base + u * 64 + lane;
-          const bool act = p < p1;
-          j[u] = act ? off_col[p] : -1;
-          a[u] = act ? off_val[p] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) bits[u] = j[u] >= 0 ? peek(out + j[u]) : 0ull;
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          if (j[u] >= 0) {
-            const double xj = bits[u] != kPending
-                                  ? __longlong_as_double(static_cast<long long>(bits[u]))
-                                  : wait_pending(out + j[u], st);
-            acc += a[u] * xj;
-          }
-        }
+    if (r < cnt) {
+      // in-panel entries of row r into LDS
+      const long long e0 = t.in_rp[lo + r], e1 = t.in_rp[lo + r + 1];
+      for (long long e = e0 + sub; e < e1; e += kLanesPerRow)
+        m_sh[t.in_col[e] * kPanel + r] = t.in_val[e];
+      double acc;
+      if (kind < 0) {
+        acc = row_sum(t.off_rp[lo + r], t.off_rp[lo + r + 1], sub, t.off_col, t.off_val, out, st);
+      } else {
+        // finish: add the slices in order, then re-arm their slots for the next solve
+        acc = 0.0;
+        for (int k = 0; k < S; ++k) acc += ready_value(slots + static_cast<long long>(k) * kPanel + r, st);
+        if (sub == 0)
+          for (int k = 0; k < S; ++k)
+            __hip_atomic_store(reinterpret_cast<unsigned long long*>(slots) +
+                                   static_cast<long long>(k) * kPanel + r,
+                               kPending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
-      acc = wave_sum(acc);
-      if (lane == 0) t_sh[r] = acc;
+      if (sub == 0) t_sh[r] = acc;
     }
     __syncthreads();
-    // ---- phase 2: in-panel forward substitution, column by column; lane r owns row r
+    // ---- in-panel forward substitution, column by column; lane r owns row r
     if (wave == 0) {
-      double acc = lane < cnt ? b - t_sh[lane] : 0.0;  // rhs minus everything solved so far
+      double acc = lane < cnt ? b - t_sh[lane] : 0.0;
       double mine = 0.0;
+      double mnext = m_sh[lane];
       for (int s = 0; s < cnt; ++s) {
-        double xs = acc;
-        if (!UNIT) xs = xs / dg;
-        xs = __shfl(xs, s, 64);
+        const double mcol = mnext;
+        if (s + 1 < cnt) mnext = m_sh[(s + 1) * kPanel + lane];
+        const double xs = readlane_d(UNIT ? acc : acc * dinv, s);
         if (lane == s) mine = xs;
-        if (lane > s) acc -= m_sh[s * kPanel + lane] * xs;
+        if (lane > s) acc -= mcol * xs;
       }
       if (lane < cnt) {
         const long long i = lo + lane;
-        __hip_atomic_store(reinterpret_cast<unsigned long long*>(out + i),
-                           static_cast<unsigned long long>(__double_as_longlong(mine)),
-                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        publish(out + i, mine);
         if (scatter) scatter[scatter_perm[i]] = mine;
       }
     }
-    __syncthreads();  // m_sh, t_sh and panel_sh are reused by the next panel
+    __syncthreads();  // m_sh, t_sh and task_sh are reused by the next task
   }
 }
 
@@ -511,18 +555,13 @@ void launch_sumsq(int n, const double* z, double* parts, int grid, const RunStat
 void launch_trsv(const DevTri& t, const double* rhs, const int* rhs_perm, double* out,
                  double* scatter, const int* scatter_perm, unsigned* ticket, RunState* st,
                  hipStream_t s) {
-  const long long panels = t.npanels;
-  long long blocks = panels < 512 ? panels : 512;
+  long long blocks = t.ntasks < 512 ? t.ntasks : 512;
   if (blocks < 1) blocks = 1;
   const int g = static_cast<int>(blocks);
   if (t.diag)
-    trsv_k<false><<<g, kTrsvBlock, 0, s>>>(t.n, t.off_rp, t.off_col, t.off_val, t.in_rp, t.in_col,
-                                           t.in_val, t.diag, t.npanels, t.pstart, t.order, rhs,
-                                           rhs_perm, out, scatter, scatter_perm, ticket, st);
+    trsv_k<false><<<g, kTrsvBlock, 0, s>>>(t, rhs, rhs_perm, out, scatter, scatter_perm, ticket, st);
   else
-    trsv_k<true><<<g, kTrsvBlock, 0, s>>>(t.n, t.off_rp, t.off_col, t.off_val, t.in_rp, t.in_col,
-                                          t.in_val, t.diag, t.npanels, t.pstart, t.order, rhs,
-                                          rhs_perm, out, scatter, scatter_perm, ticket, st);
+    trsv_k<true><<<g, kTrsvBlock, 0, s>>>(t, rhs, rhs_perm, out, scatter, scatter_perm, ticket, st);
 }
 
 void launch_pass1(int n, const double* x, const double* w, double* m, double* v, double* d,

@@ -64,11 +64,14 @@ struct DevCsr {
   int lpr = 8;  // lanes per row for the SpMV (power of two, 4..64)
 };
 
-// A lower-triangular factor in solve order, split into panels of at most 64
-// rows: the entries of a panel's rows with a column before the panel ("off")
-// and the ones inside it ("in", column stored relative to the panel start).
-// Upper factors are reversed on the host (row i -> n-1-i) so every solve is
-// a forward substitution.
+// A lower-triangular factor in solve order (upper factors are reversed on the
+// host, row i -> n-1-i, so every solve is a forward substitution), cut into
+// panels of at most 64 consecutive rows. Per row, the entries with a column
+// before the row's panel ("off") and inside it ("in", column relative to the
+// panel start). The solve is a list of tasks in dependency-level order:
+// task t works on panel task_panel[t]; task_kind[t] = -1 for the whole panel,
+// 0..S-1 for slice k of its off-panel entries, S for the step that adds the
+// slices and finishes the panel (S = panel_split[panel]).
 constexpr int kPanel = 64;
 struct DevTri {
   int n = 0;
@@ -76,13 +79,18 @@ struct DevTri {
   const int* off_col = nullptr;
   const double* off_val = nullptr;
   const long long* in_rp = nullptr;
-  const int* in_col = nullptr;  // 0..63, column relative to the panel start
+  const int* in_col = nullptr;
   const double* in_val = nullptr;
   const double* diag = nullptr;  // nullptr: unit diagonal
-  int npanels = 0;
-  const int* pstart = nullptr;   // panel p holds rows [pstart[p], pstart[p+1]), at most 64
-  const int* order = nullptr;    // ticket t solves panel order[t] (dependency-level order)
+  const int* pstart = nullptr;   // panel p holds rows [pstart[p], pstart[p+1])
+  const int* panel_split = nullptr;
+  const int* panel_slot = nullptr;  // first partial-sum slot (64 doubles each) of a split panel
+  double* partials = nullptr;       // kPending when idle
+  int ntasks = 0;
+  const int* task_panel = nullptr;
+  const int* task_kind = nullptr;
 };
+using TrsvArgs = DevTri;
 
 int grid_for(int n);  // fixed grid size of the reduction kernels for length n
 

@@ -64,9 +64,16 @@ struct PanelCsr {
   std::vector<int32_t> off_col, in_col;
   std::vector<double> off_val, in_val;
   std::vector<int32_t> pstart;  // panel p holds rows [pstart[p], pstart[p+1])
-  std::vector<int32_t> order;   // panels sorted by dependency level, then index
+  std::vector<int32_t> panel_split, panel_slot;  // slices per panel, first slot of a split panel
+  std::vector<int32_t> task_panel, task_kind;    // tasks in dependency-level order
   int32_t levels = 0;
+  int32_t nslots = 0;
 };
+
+// A panel whose rows hold more off-panel entries than this is cut into
+// slices (at most kMaxSlices) that separate blocks sum in parallel.
+constexpr int64_t kSliceEntries = 16384;
+constexpr int32_t kMaxSlices = 64;
 
 // Panel boundaries: a panel closes when it holds 64 rows, or -- once it holds
 // at least kMinPanelRows -- before a row that needs nothing inside it. Such a
@@ -106,9 +113,9 @@ PanelCsr split_panels(const HostCsr& t) {
       const int32_t q = pid[t.col[p]];
       if (q != pid[i]) level[pid[i]] = std::max(level[pid[i]], level[q] + 1);
     }
-  s.order.resize(np);
-  for (int32_t p = 0; p < np; ++p) s.order[p] = p;
-  std::stable_sort(s.order.begin(), s.order.end(),
+  std::vector<int32_t> order(np);
+  for (int32_t p = 0; p < np; ++p) order[p] = p;
+  std::stable_sort(order.begin(), order.end(),
                    [&](int32_t a, int32_t b) { return level[a] < level[b]; });
   s.levels = np ? 1 + *std::max_element(level.begin(), level.end()) : 0;
   s.off_rp.assign(t.n + 1, 0);
@@ -127,6 +134,26 @@ PanelCsr split_panels(const HostCsr& t) {
     }
     s.off_rp[i + 1] = static_cast<int64_t>(s.off_col.size());
     s.in_rp[i + 1] = static_cast<int64_t>(s.in_col.size());
+  }
+  // tasks: whole panels, or slices followed by their finish step
+  s.panel_split.assign(np, 1);
+  s.panel_slot.assign(np, 0);
+  for (int32_t p : order) {
+    const int64_t work = s.off_rp[s.pstart[p + 1]] - s.off_rp[s.pstart[p]];
+    const int32_t S = static_cast<int32_t>(
+        std::min<int64_t>(kMaxSlices, (work + kSliceEntries - 1) / kSliceEntries));
+    if (S <= 1) {
+      s.task_panel.push_back(p);
+      s.task_kind.push_back(-1);
+      continue;
+    }
+    s.panel_split[p] = S;
+    s.panel_slot[p] = s.nslots;
+    s.nslots += S;
+    for (int32_t k = 0; k <= S; ++k) {
+      s.task_panel.push_back(p);
+      s.task_kind.push_back(k);
+    }
   }
   return s;
 }
@@ -210,7 +237,7 @@ struct cond_plan {
   // offsets into the workspace
   struct {
     size_t a_rp, a_col, a_val, at_rp, at_col, at_val;
-    size_t tri[4][8];
+    size_t tri[4][12];
     size_t u_diag, u_diag_rev, row_perm, rev, scat_s, scat_r;
     size_t vec[10];
     size_t parts[4];
@@ -244,7 +271,11 @@ void plan_layout(cond_plan* p) {
       p->o.tri[f][4] = L.take(t.in_col.size() * 4);
       p->o.tri[f][5] = L.take(t.in_val.size() * 8);
       p->o.tri[f][6] = L.take(t.pstart.size() * 4);
-      p->o.tri[f][7] = L.take(t.order.size() * 4);
+      p->o.tri[f][7] = L.take(t.panel_split.size() * 4);
+      p->o.tri[f][8] = L.take(t.panel_slot.size() * 4);
+      p->o.tri[f][9] = L.take(static_cast<size_t>(t.nslots) * kPanel * 8);
+      p->o.tri[f][10] = L.take(t.task_panel.size() * 4);
+      p->o.tri[f][11] = L.take(t.task_kind.size() * 4);
     }
     p->o.u_diag = L.take(n * 8);
     p->o.u_diag_rev = L.take(n * 8);
@@ -307,7 +338,11 @@ int upload_tri(cond_plan* p, const PanelCsr& t, const size_t* off, const double*
   if ((st = upload(p, off[4], t.in_col.data(), t.in_col.size() * 4))) return st;
   if ((st = upload(p, off[5], t.in_val.data(), t.in_val.size() * 8))) return st;
   if ((st = upload(p, off[6], t.pstart.data(), t.pstart.size() * 4))) return st;
-  if ((st = upload(p, off[7], t.order.data(), t.order.size() * 4))) return st;
+  if ((st = upload(p, off[7], t.panel_split.data(), t.panel_split.size() * 4))) return st;
+  if ((st = upload(p, off[8], t.panel_slot.data(), t.panel_slot.size() * 4))) return st;
+  if ((st = upload(p, off[10], t.task_panel.data(), t.task_panel.size() * 4))) return st;
+  if ((st = upload(p, off[11], t.task_kind.data(), t.task_kind.size() * 4))) return st;
+  if (t.nslots > 0) launch_fill(t.nslots * kPanel, at_off<double>(p, off[9]), kPending, p->stream);
   out.n = t.n;
   out.off_rp = at_off<long long>(p, off[0]);
   out.off_col = at_off<int>(p, off[1]);
@@ -316,9 +351,13 @@ int upload_tri(cond_plan* p, const PanelCsr& t, const size_t* off, const double*
   out.in_col = at_off<int>(p, off[4]);
   out.in_val = at_off<double>(p, off[5]);
   out.diag = diag_dev;
-  out.npanels = static_cast<int>(t.order.size());
   out.pstart = at_off<int>(p, off[6]);
-  out.order = at_off<int>(p, off[7]);
+  out.panel_split = at_off<int>(p, off[7]);
+  out.panel_slot = at_off<int>(p, off[8]);
+  out.partials = at_off<double>(p, off[9]);
+  out.ntasks = static_cast<int>(t.task_panel.size());
+  out.task_panel = at_off<int>(p, off[10]);
+  out.task_kind = at_off<int>(p, off[11]);
   return COND_OK;
 }
 
