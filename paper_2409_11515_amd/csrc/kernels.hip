@@ -152,6 +152,66 @@ __global__ __launch_bounds__(kBlock) void spmv_k(int n, const IT* __restrict__ r
   }
 }
 
+// ---------------------------------------------------------- spmv (stream)
+// y = A x by row tiles: the host cuts the rows into tiles of at most 256 rows
+// and kStreamCap entries (a longer row is a tile of its own). A block streams
+// a tile's entries with fully coalesced loads of col/val, gathers x and
+// parks the products in LDS, then thread t adds up the products of row t.
+// A tile holding one long row is summed by the whole block. Each block owns
+// a contiguous range of tiles; partial sums of y.y are written per block.
+constexpr int kStreamCap = 2048;
+constexpr int kTileRows = 256;
+
+template <typename IT>
+__global__ __launch_bounds__(kBlock) void spmv_stream_k(
+    int ntiles, const int* __restrict__ tiles, const IT* __restrict__ rowptr,
+    const int* __restrict__ col, const double* __restrict__ val, const double* __restrict__ x,
+    double* __restrict__ y, double* __restrict__ parts, const RunState* st) {
+  if (st && st->stop_req) return;
+  __shared__ double prod[kStreamCap];
+  __shared__ IT rp_sh[kTileRows + 1];
+  const int lb = logical_block();
+  long long t0, t1;
+  block_range(ntiles, lb, t0, t1);
+  double sq = 0.0;
+  for (long long t = t0; t < t1; ++t) {
+    const int ra = tiles[t], rb = tiles[t + 1];
+    const int cnt = rb - ra;
+    for (int k = threadIdx.x; k <= cnt; k += kBlock) rp_sh[k] = rowptr[ra + k];
+    __syncthreads();
+    const IT e0 = rp_sh[0];
+    const IT ne = rp_sh[cnt] - e0;
+    if (ne <= kStreamCap) {
+#pragma unroll 4
+      for (int e = threadIdx.x; e < static_cast<int>(ne); e += kBlock)
+        prod[e] = val[e0 + e] * x[col[e0 + e]];
+      __syncthreads();
+      if (threadIdx.x < cnt) {
+        const int a = static_cast<int>(rp_sh[threadIdx.x] - e0);
+        const int b = static_cast<int>(rp_sh[threadIdx.x + 1] - e0);
+        double s = 0.0;
+        for (int e = a; e < b; ++e) s += prod[e];
+        y[ra + threadIdx.x] = s;
+        sq += s * s;
+      }
+    } else {
+      // one long row: every thread takes a strided share, then a block sum
+      double acc = 0.0;
+      for (IT e = e0 + threadIdx.x; e < e0 + ne; e += kBlock) acc += val[e] * x[col[e]];
+      acc = block_sum(acc);
+      if (threadIdx.x == 0) {
+        y[ra] = acc;
+        sq += acc * acc;
+      }
+    }
+    __syncthreads();  // rp_sh and prod are reused by the next tile
+  }
+  if (parts) {
+    const double s = block_sum(sq);
+    if (threadIdx.x == 0) parts[lb] = s;
+  }
+}
+
 // ---------------------------------------------------------------- sumsq
 __global__ __launch_bounds__(kBlock) void sumsq_k(int n, const double* __restrict__ z,
                                                   double* __restrict__ parts, const RunState* st) {
@@ -541,6 +601,15 @@ void launch_normalise(int n, double* x, const double* parts_xx, int grid, double
 
 void launch_spmv(const DevCsr& a, const double* x, double* y, double* parts_y, int grid,
                  const RunState* st, hipStream_t s) {
+  if (a.tiles) {
+    if (a.idx64)
+      spmv_stream_k<long long><<<grid, kBlock, 0, s>>>(
+          a.ntiles, a.tiles, static_cast<const long long*>(a.rowptr), a.col, a.val, x, y, parts_y, st);
+    else
+      spmv_stream_k<int><<<grid, kBlock, 0, s>>>(a.ntiles, a.tiles, static_cast<const int*>(a.rowptr),
+                                                 a.col, a.val, x, y, parts_y, st);
+    return;
+  }
   if (a.idx64)
     spmv_dispatch<long long>(a, x, y, parts_y, grid, st, s);
   else

@@ -61,8 +61,16 @@ struct DevCsr {
   int idx64 = 0;
   const int* col = nullptr;
   const double* val = nullptr;
-  int lpr = 8;  // lanes per row for the SpMV (power of two, 4..64)
+  int lpr = 8;  // lanes per row for the vector-CSR SpMV (power of two, 4..64)
+  // row tiles for the streaming SpMV (nullptr: vector CSR): tile t holds rows
+  // [tiles[t], tiles[t+1]), at most 256 rows and 2048 entries unless one row
+  const int* tiles = nullptr;
+  int ntiles = 0;
 };
+
+// Row tiles for the streaming SpMV (see DevCsr::tiles).
+constexpr int kTileRowsHost = 256;
+constexpr long long kTileEntriesHost = 2048;
 
 // A lower-triangular factor in solve order (upper factors are reversed on the
 // host, row i -> n-1-i, so every solve is a forward substitution), cut into

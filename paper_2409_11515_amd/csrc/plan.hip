@@ -178,6 +178,20 @@ HostCsr reverse_order(const HostCsr& u) {
   return r;
 }
 
+// Row tiles for the streaming SpMV: consecutive rows, at most kTileRowsHost
+// rows and kTileEntriesHost entries per tile; a longer row is a tile alone.
+std::vector<int32_t> make_tiles(const HostCsr& a) {
+  std::vector<int32_t> t{0};
+  int32_t s = 0;
+  for (int32_t i = 0; i < a.n; ++i)
+    if (i > s && (i + 1 - s > kTileRowsHost || a.rowptr[i + 1] - a.rowptr[s] > kTileEntriesHost)) {
+      t.push_back(i);
+      s = i;
+    }
+  t.push_back(a.n);
+  return t;
+}
+
 int choose_lpr(double mean_nnz_per_row) {
   int l = 4;
   while (l < 64 && l < mean_nnz_per_row) l <<= 1;
@@ -190,6 +204,7 @@ struct cond_plan {
   int32_t n = 0;
   cond_opts_t opts{};
   HostCsr a, at;
+  std::vector<int32_t> tiles_a, tiles_at;  // row tiles of the streaming SpMV
   std::unique_ptr<cond_lu> lu;
   bool want_min = false;
   double setup_ms = 0.0;
@@ -236,7 +251,7 @@ struct cond_plan {
   size_t need_bytes = 0;
   // offsets into the workspace
   struct {
-    size_t a_rp, a_col, a_val, at_rp, at_col, at_val;
+    size_t a_rp, a_col, a_val, at_rp, at_col, at_val, a_tiles, at_tiles;
     size_t tri[4][12];
     size_t u_diag, u_diag_rev, row_perm, rev, scat_s, scat_r;
     size_t vec[10];
@@ -260,6 +275,8 @@ void plan_layout(cond_plan* p) {
   p->o.at_rp = L.take((n + 1) * ri);
   p->o.at_col = L.take(p->at.nnz() * 4);
   p->o.at_val = L.take(p->at.nnz() * 8);
+  p->o.a_tiles = L.take(p->tiles_a.size() * 4);
+  p->o.at_tiles = L.take(p->tiles_at.size() * 4);
   if (p->want_min) {
     const PanelCsr* tris[4] = {&p->pL, &p->pU, &p->pUt, &p->pLt};
     for (int f = 0; f < 4; ++f) {
@@ -305,7 +322,7 @@ int upload(cond_plan* p, size_t off, const void* src, size_t bytes) {
 }
 
 int upload_csr(cond_plan* p, const HostCsr& a, size_t rp, size_t col, size_t val, bool idx64,
-               DevCsr& out) {
+               const std::vector<int32_t>& tiles, size_t tiles_off, DevCsr& out) {
   const size_t n = a.n;
   int st;
   if (idx64) {
@@ -325,6 +342,9 @@ int upload_csr(cond_plan* p, const HostCsr& a, size_t rp, size_t col, size_t val
   out.col = at_off<int>(p, col);
   out.val = at_off<double>(p, val);
   out.lpr = choose_lpr(static_cast<double>(a.nnz()) / std::max(1, a.n));
+  if ((st = upload(p, tiles_off, tiles.data(), tiles.size() * 4))) return st;
+  out.tiles = at_off<int>(p, tiles_off);
+  out.ntiles = static_cast<int>(tiles.size()) - 1;
   return COND_OK;
 }
 
@@ -610,6 +630,8 @@ int cond_plan_create(const cond_csr_t* A, const cond_opts_t* o, cond_plan_t** ou
   try {
     if ((st = canonical_copy(A, p->a))) return st;
     transpose(p->a, p->at);
+    p->tiles_a = make_tiles(p->a);
+    p->tiles_at = make_tiles(p->at);
     p->n = p->a.n;
     p->opts = *o;
     p->opts.col_perm = nullptr;
@@ -677,8 +699,12 @@ int cond_plan_bind(cond_plan_t* p, void* workspace, size_t bytes, void* stream) 
   int st;
   if ((st = join_user_stream(p))) return st;
   const bool a64 = idx64_needed(p->a);
-  if ((st = upload_csr(p, p->a, p->o.a_rp, p->o.a_col, p->o.a_val, a64, p->dA))) return st;
-  if ((st = upload_csr(p, p->at, p->o.at_rp, p->o.at_col, p->o.at_val, a64, p->dAt))) return st;
+  if ((st = upload_csr(p, p->a, p->o.a_rp, p->o.a_col, p->o.a_val, a64, p->tiles_a,
+                       p->o.a_tiles, p->dA)))
+    return st;
+  if ((st = upload_csr(p, p->at, p->o.at_rp, p->o.at_col, p->o.at_val, a64, p->tiles_at,
+                       p->o.at_tiles, p->dAt)))
+    return st;
   if (p->want_min) {
     const cond_lu& f = *p->lu;
     if ((st = upload(p, p->o.u_diag, f.u_diag.data(), p->n * 8))) return st;

@@ -103,6 +103,31 @@ def test_spmv_ragged_rows(torch_cuda):
     p.close()
 
 
+def test_spmv_long_rows_and_tiles(torch_cuda):
+    # rows longer than one streaming tile (2048 entries) next to short ones,
+    # and a dense column, so A^T has a long row as well
+    torch = torch_cuda
+    rng = np.random.default_rng(12)
+    n = 9000
+    m = sp.random(n, n, density=0.0005, random_state=5, format="lil")
+    m[17, :] = rng.standard_normal(n)  # 9000-entry row
+    m[4000, ::2] = rng.standard_normal((n + 1) // 2)
+    m[:, 5] = rng.standard_normal((n, 1))  # dense column -> long row of A^T
+    m = m.tocsr() + sp.eye(n)
+    a = Csr.from_scipy(m)
+    p = _plan(a, sigma_min_method=2)
+    x = rng.standard_normal(n)
+    for tr in (False, True):
+        y = p.spmv(_dev(torch, x), transpose=tr).cpu().numpy()
+        if tr:
+            rp, c, v = transpose_csr(a.n, a.rowptr, a.col, a.val)
+        else:
+            rp, c, v = a.rowptr, a.col, a.val
+        ref = oracle_spmv(rp, c, v, x)
+        assert np.all(np.abs(y - ref) <= 1e-12 * spmv_abs(rp, c, v, x) + 1e-300)
+    p.close()
+
+
 # -------------------------------------------------------- Algorithm 2 solves
 @pytest.mark.parametrize("mk", [lambda: stokes2d(10, 10, seed=0), lambda: hydromech2d(30, seed=3)])
 def test_inverse_apply_parity(torch_cuda, mk):
