@@ -208,6 +208,38 @@ int cond_plan_kernel_stats(const cond_plan_t* plan, double* ms, int64_t* launche
 int cond_plan_spmv(cond_plan_t* plan, int transpose, const double* x, double* y);
 int cond_plan_inverse_apply(cond_plan_t* plan, const double* x, double* r, double* s);
 
+/* ---------------------------------------------------- batched multi-start
+ * Many matrices of uneven size, 8 starts each, in one launch per phase of
+ * the sigma_max run (Algorithm 1 with M = A for every (matrix, start) pair;
+ * the arithmetic of each pair is the plain method's, only the order of the
+ * additions inside its global sums differs). The matrices are concatenated
+ * block-diagonally: matrix m owns global rows [row0[m], row0[m+1]), and the
+ * 8 starts of a row are interleaved, element (i, k) at index 8*i + k.
+ *
+ * cond_batch_create: host set-up (validation, A^T of every matrix, the
+ * concatenation). cond_batch_info: row0 (count+1 entries, host), workspace
+ * size, and after bind the tile schedule in use. cond_batch_bind: takes the
+ * workspace as cond_plan_bind does, uploads, and picks the row-tile size and
+ * grid by timing the A-product for each candidate on this batch (an
+ * autotuner), unless tile_rows and grid are both given (> 0), which fixes the
+ * schedule and makes runs reproducible bit for bit across processes.
+ * cond_batch_run: x0 is a device array of (row0[count]) * 8 doubles; results
+ * on the host: sigma_max[count] = the largest best over a matrix's starts
+ * (each start gives a lower bound), pair_best / pair_iters / pair_status
+ * [count * 8] per (matrix, start) (any of them may be NULL); trace (device,
+ * count * 8 * max_iter, optional) receives each pair's running best per
+ * update; x_best (device, optional) the best iterates; ms the device time. */
+typedef struct cond_batch cond_batch_t;
+int cond_batch_create(const cond_csr_t* As, int32_t count, const cond_opts_t* o, cond_batch_t** b);
+int cond_batch_info(const cond_batch_t* b, int64_t* row0, size_t* workspace_bytes,
+                    int32_t* tile_rows, int32_t* grid);
+int cond_batch_bind(cond_batch_t* b, void* workspace, size_t bytes, void* stream,
+                    int32_t tile_rows, int32_t grid);
+int cond_batch_run(cond_batch_t* b, const cond_opts_t* o, const double* x0, double* sigma_max,
+                   double* pair_best, int64_t* pair_iters, int32_t* pair_status, double* trace,
+                   double* x_best, double* ms);
+void cond_batch_destroy(cond_batch_t* b);
+
 /* create + bind (library-owned memory) + run + destroy. */
 int cond_estimate(const cond_csr_t* A, const cond_opts_t* o, const double* x0_max,
                   const double* x0_min, void* stream, cond_result_t* out);

@@ -29,7 +29,8 @@ from ._binding import (  # noqa: F401
     make_opts,
 )
 
-__all__ = ["csr_check", "csr_transpose", "order_nd", "LU", "Plan", "estimate_cond", "CondError"]
+__all__ = ["csr_check", "csr_transpose", "order_nd", "LU", "Plan", "Batch", "interleave_starts",
+           "estimate_cond", "CondError"]
 
 
 def version() -> int:
@@ -213,6 +214,87 @@ class Plan:
 
     def __del__(self):
         self.close()
+
+
+class Batch:
+    """Batched multi-start sigma_max run over many matrices (8 starts each).
+
+    ``Batch([(n, rowptr, col, val), ...], **opts).bind()`` concatenates the
+    matrices block-diagonally; ``run(x0)`` takes a CUDA float64 tensor of
+    ``rows * 8`` entries (row i, start k at index 8*i + k; see ``row0``).
+    """
+
+    K = 8
+
+    def __init__(self, mats, **opts):
+        from ._binding import CsrT
+
+        self._h = C.c_void_p()
+        self.opts = make_opts(**opts)
+        self._keep = [HostCsr(*m) for m in mats]
+        arr = (CsrT * len(self._keep))(*[h.struct for h in self._keep])
+        check(lib().cond_batch_create(C.cast(arr, C.c_void_p), len(self._keep), C.byref(self.opts),
+                                      C.byref(self._h)), "batch_create")
+        self.count = len(self._keep)
+        self.row0 = np.zeros(self.count + 1, np.int64)
+        sz = C.c_size_t()
+        check(lib().cond_batch_info(self._h, self.row0.ctypes.data, C.byref(sz), None, None),
+              "batch_info")
+        self.workspace_bytes = sz.value
+        self.workspace = None
+
+    def bind(self, device="cuda", stream=None, tile_rows=0, grid=0):
+        import torch
+
+        self.workspace = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=device)
+        ptr = (self.workspace.data_ptr() + 255) // 256 * 256
+        check(lib().cond_batch_bind(self._h, ptr, self.workspace_bytes, _stream_ptr(torch, stream),
+                                    int(tile_rows), int(grid)), "batch_bind")
+        tr = C.c_int32()
+        gr = C.c_int32()
+        check(lib().cond_batch_info(self._h, None, None, C.byref(tr), C.byref(gr)), "batch_info")
+        self.tile_rows, self.grid = tr.value, gr.value
+        return self
+
+    def run(self, x0, trace=False, **opts) -> dict:
+        import torch
+
+        o = make_opts(**{**{f: getattr(self.opts, f) for f, _ in self.opts._fields_
+                            if f != "col_perm"}, **opts})
+        npairs = self.count * self.K
+        smax = np.zeros(self.count)
+        best = np.zeros(npairs)
+        iters = np.zeros(npairs, np.int64)
+        status = np.zeros(npairs, np.int32)
+        tr = torch.zeros(npairs * int(o.max_iter), dtype=torch.float64,
+                         device=x0.device) if trace else None
+        ms = C.c_double()
+        st = lib().cond_batch_run(self._h, C.byref(o), x0.data_ptr(), smax.ctypes.data,
+                                  best.ctypes.data, iters.ctypes.data, status.ctypes.data,
+                                  None if tr is None else tr.data_ptr(), None, C.byref(ms))
+        out = dict(sigma_max=smax, pair_best=best.reshape(self.count, self.K),
+                   pair_iters=iters.reshape(self.count, self.K),
+                   pair_status=status.reshape(self.count, self.K), ms=ms.value, status=st)
+        if trace:
+            out["trace"] = tr.view(self.count, self.K, int(o.max_iter)).cpu().numpy()
+        check(st, "batch_run")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().cond_batch_destroy(self._h)
+            self._h = C.c_void_p()
+        self.workspace = None
+
+    def __del__(self):
+        self.close()
+
+
+def interleave_starts(starts_per_matrix) -> np.ndarray:
+    """Per matrix an array of shape (8, n_m) (start k in row k) -> one float64
+    vector in the batch layout: global row i, start k at index 8*i + k."""
+    return np.ascontiguousarray(np.concatenate(
+        [np.asarray(s, np.float64).T.reshape(-1) for s in starts_per_matrix]))
 
 
 def estimate_cond(n, rowptr, col, val, x0_max, x0_min=None, stream=None, **opts) -> dict:

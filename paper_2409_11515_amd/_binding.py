@@ -65,8 +65,11 @@ EXPORTS = (
     "cond_csr_transpose", "cond_order_nd", "cond_lu_factor", "cond_lu_destroy", "cond_lu_info",
     "cond_lu_export", "cond_lu_solve_host", "cond_plan_create", "cond_plan_workspace_bytes",
     "cond_plan_bind", "cond_plan_destroy", "cond_plan_run", "cond_plan_spmv",
-    "cond_plan_inverse_apply", "cond_estimate", "cond_plan_kernel_stats",
+    "cond_plan_inverse_apply", "cond_estimate", "cond_plan_kernel_stats", "cond_batch_create",
+    "cond_batch_info", "cond_batch_bind", "cond_batch_run", "cond_batch_destroy",
 )
+
+BATCH_K = 8
 
 KERNEL_NAMES = ("normalise", "spmv_A", "spmv_At", "sumsq", "trsv_L", "trsv_U", "trsv_Ut",
                 "trsv_Lt", "adam_pass1", "adam_pass2")
@@ -107,6 +110,13 @@ def lib():
     L.cond_plan_inverse_apply.argtypes = [vp, vp, vp, vp]
     L.cond_estimate.argtypes = [C.POINTER(CsrT), C.POINTER(OptsT), vp, vp, vp, C.POINTER(ResultT)]
     L.cond_plan_kernel_stats.argtypes = [vp, vp, vp, vp]
+    L.cond_batch_create.argtypes = [vp, i32, C.POINTER(OptsT), C.POINTER(vp)]
+    L.cond_batch_info.argtypes = [vp, vp, C.POINTER(C.c_size_t), C.POINTER(i32), C.POINTER(i32)]
+    L.cond_batch_bind.argtypes = [vp, vp, C.c_size_t, vp, i32, i32]
+    L.cond_batch_run.argtypes = [vp, C.POINTER(OptsT), vp, vp, vp, vp, vp, vp, vp,
+                                 C.POINTER(dbl)]
+    L.cond_batch_destroy.argtypes = [vp]
+    L.cond_batch_destroy.restype = None
     for name in EXPORTS:
         getattr(L, name)  # raises AttributeError if a declared symbol is missing
     _lib = L

@@ -1,0 +1,60 @@
+// Batched multi-start Projected Adam: device structures shared by the
+// batch kernels and the batch plan.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace condest {
+
+constexpr int kBatchK = 8;  // starts per matrix, interleaved x[i*K + k]
+
+// Per (matrix, start) state of Algorithm 1. Written only by the per-matrix
+// reduction kernel (one thread per pair) and read by the element kernels.
+struct BatchPair {
+  double best;      // best sigma over evaluated iterates
+  double ckpt;      // best at the last stop-window boundary
+  double nrm;       // ||x|| before normalisation
+  double nx2, ny2;  // x.x and ||M x||^2 of the current iterate
+  double xd;        // x . dx
+  long long iters;  // final T once stopped
+  int improved;     // the current iterate is the new best
+  int stopped;
+  int status;
+  int flags;
+};
+
+struct BatchGlobal {
+  long long t_done;
+  double b1t, b2t;
+};
+
+struct BatchArgs {
+  int nmat = 0;
+  int ntiles = 0;
+  const long long* tiles = nullptr;  // tile t = rows [tiles[t], tiles[t+1]) of one matrix
+  const int* tile_mat = nullptr;     // matrix of tile t
+  const int* mat_tile0 = nullptr;    // tiles of matrix m: [mat_tile0[m], mat_tile0[m+1])
+  const int* a_rowptr = nullptr;     // block-diagonal A (global row and column indices)
+  const int* a_col = nullptr;
+  const double* a_val = nullptr;
+  const int* at_rowptr = nullptr;  // block-diagonal A^T
+  const int* at_col = nullptr;
+  const double* at_val = nullptr;
+  double *x = nullptr, *m = nullptr, *v = nullptr, *d = nullptr, *y = nullptr, *w = nullptr;
+  double* xbest = nullptr;
+  double *parts_x = nullptr, *parts_y = nullptr, *parts_xd = nullptr, *parts_xx = nullptr;
+  BatchPair* pairs = nullptr;
+  BatchGlobal* g = nullptr;
+  double* trace = nullptr;  // [pair][max_iter] or nullptr
+};
+
+void batch_launch_init(const BatchArgs& a, const double* x0, int grid, hipStream_t s);
+void batch_launch_reduce(const BatchArgs& a, int mode, const AdamParams& p, hipStream_t s);
+void batch_launch_normalise(const BatchArgs& a, int grid, hipStream_t s);
+void batch_launch_spmm(const BatchArgs& a, int transpose, int grid, hipStream_t s);
+void batch_launch_pass1(const BatchArgs& a, const AdamParams& p, int grid, hipStream_t s);
+void batch_launch_pass2(const BatchArgs& a, const AdamParams& p, int grid, hipStream_t s);
+
+}  // namespace condest

@@ -1,0 +1,351 @@
+// Batched, multi-start Projected Adam (sigma_max run) for gfx950.
+//
+// A batch is many matrices of uneven size, each with K starts. The matrices
+// are concatenated block-diagonally (matrix m owns rows [row0[m], row0[m+1]))
+// and the K starts of a row are interleaved: x[i*K + k]. One launch per phase
+// then covers every matrix and every start, and one read of a matrix entry
+// serves all K starts. The arithmetic of every (matrix, start) pair is the
+// plain method's Algorithm 1; only the order of additions inside the global
+// sums differs.
+//
+// Rows are cut into tiles that never cross a matrix boundary. Each tile
+// writes K partial sums into its own slots; a per-matrix reduction kernel
+// (one block per matrix) adds a matrix's tile partials in tile order, so the
+// scalars are deterministic. The same kernel runs the per-pair bookkeeping of
+// Algorithm 1: evaluation of the previous iterate, best tracking, the stop
+// rule, retirement of a finished pair.
+
+#include "batch.hpp"
+#include "condest.h"
+
+namespace condest {
+
+namespace {
+
+constexpr int kB = 256;
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ double bsum(double v) {
+  __shared__ double red[kB / 64];
+  v = wsum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = red[0];
+#pragma unroll
+  for (int k = 1; k < kB / 64; ++k) r += red[k];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ void tile_range(int ntiles, long long& t0, long long& t1) {
+  const int b = blockIdx.x, g = gridDim.x;
+  const int lb = (g % 8 == 0) ? (b % 8) * (g / 8) + b / 8 : b;
+  t0 = static_cast<long long>(ntiles) * lb / g;
+  t1 = static_cast<long long>(ntiles) * (lb + 1) / g;
+}
+
+// Per-tile partial sums of K values, lane k of each 8-lane group owning start
+// k (K == 8). Reduces the block's per-start accumulators into slot rows.
+template <int K>
+__device__ __forceinline__ void tile_partials(double acc, int tile, double* parts) {
+  // lanes with the same (lane % K) hold the same start: add them up
+  __shared__ double red[kB];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x < K) {
+    double s = 0.0;
+    for (int t = threadIdx.x; t < kB; t += K) s += red[t];
+    parts[static_cast<long long>(tile) * K + threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------ init
+template <int K>
+__global__ __launch_bounds__(kB) void b_init_k(BatchArgs a, const double* __restrict__ x0) {
+  long long t0, t1;
+  tile_range(a.ntiles, t0, t1);
+  const int k = threadIdx.x % K;
+  for (long long t = t0; t < t1; ++t) {
+    const long long r0 = a.tiles[t], r1 = a.tiles[t + 1];
+    double acc = 0.0;
+    for (long long e = r0 * K + threadIdx.x; e < r1 * K; e += kB) {
+      const double xi = x0[e];
+      a.x[e] = xi;
+      a.m[e] = 0.0;
+      a.v[e] = 0.0;
+      acc += xi * xi;
+    }
+    tile_partials<K>(acc, static_cast<int>(t), a.parts_xx);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.g->t_done = 0;
+    a.g->b1t = 1.0;
+    a.g->b2t = 1.0;
+  }
+}
+
+// --------------------------------------------------------- per-matrix reduce
+// mode 0: after pass 2 (or init): nrm[p] = sqrt(sum ||x||^2)
+// mode 1: after spmv(A): evaluation, best tracking, stop rule (needs x.x, y.y)
+// mode 2: after pass 1: xd[p] = sum x.dx
+template <int K>
+__global__ __launch_bounds__(kB) void b_reduce_k(BatchArgs a, int mode, AdamParams p) {
+  const int mat = blockIdx.x;
+  const int t0 = a.mat_tile0[mat], t1 = a.mat_tile0[mat + 1];
+  __shared__ double sh[K][3];
+  const double* src0 = mode == 0 ? a.parts_xx : (mode == 1 ? a.parts_x : a.parts_xd);
+  for (int src = 0; src < (mode == 1 ? 2 : 1); ++src) {
+    const double* parts = src == 0 ? src0 : a.parts_y;
+    // thread layout: K starts x (kB / K) strided tiles, then a fixed-order combine
+    const int k = threadIdx.x % K, lane_t = threadIdx.x / K;
+    double acc = 0.0;
+    for (int t = t0 + lane_t; t < t1; t += kB / K) acc += parts[static_cast<long long>(t) * K + k];
+    __shared__ double red[kB];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < K) {
+      double s = 0.0;
+      for (int u = threadIdx.x; u < kB; u += K) s += red[u];
+      sh[threadIdx.x][src] = s;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x >= K) return;
+  const int k = threadIdx.x;
+  const long long pr = static_cast<long long>(mat) * K + k;  // pair index
+  BatchPair& q = a.pairs[pr];
+  if (mode == 0) {
+    q.nrm = sqrt(sh[k][0]);
+    return;
+  }
+  if (mode == 2) {
+    q.xd = sh[k][0];
+    return;
+  }
+  // mode 1: the evaluation and bookkeeping of Algorithm 1 for this pair
+  if (q.stopped) {
+    q.improved = 0;
+    return;
+  }
+  const long long t = a.g->t_done + 1;
+  const double nx2 = sh[k][0], ny2 = sh[k][1];
+  q.nx2 = nx2;
+  q.ny2 = ny2;
+  q.improved = 0;
+  if (!(nx2 > 0.0) || !(ny2 > 0.0) || !isfinite(nx2) || !isfinite(ny2)) {
+    q.stopped = 1;
+    q.status = COND_ENUMERIC;
+    q.iters = t - 1;
+    return;
+  }
+  if (t >= 2) {
+    const double sigma = sqrt(ny2 / nx2);
+    if (sigma > q.best) {
+      q.best = sigma;
+      q.improved = 1;
+    }
+    const long long T = t - 1;
+    if (a.trace) a.trace[pr * p.max_iter + (T - 1)] = q.best;
+    if (T >= p.max_iter) {
+      q.stopped = 1;
+      q.iters = T;
+      q.flags |= static_cast<int>(COND_F_MAXITER);
+    } else if (p.stop_window > 0 && p.stop_rtol > 0.0 && T % p.stop_window == 0) {
+      if (T >= 2 * p.stop_window && q.best - q.ckpt <= p.stop_rtol * q.best) {
+        q.stopped = 1;
+        q.iters = T;
+      }
+      q.ckpt = q.best;
+    }
+  }
+}
+
+// --------------------------------------------------------------- normalise
+template <int K>
+__global__ __launch_bounds__(kB) void b_normalise_k(BatchArgs a) {
+#pragma clang fp contract(off)
+  long long t0, t1;
+  tile_range(a.ntiles, t0, t1);
+  const int k = threadIdx.x % K;
+  for (long long t = t0; t < t1; ++t) {
+    const int mat = a.tile_mat[t];
+    const BatchPair& q = a.pairs[static_cast<long long>(mat) * K + k];
+    const long long r0 = a.tiles[t], r1 = a.tiles[t + 1];
+    double acc = 0.0;
+    if (!q.stopped) {
+      const double nrm = q.nrm;
+      for (long long e = r0 * K + threadIdx.x; e < r1 * K; e += kB) {
+        const double xi = a.x[e] / nrm;
+        a.x[e] = xi;
+        acc += xi * xi;
+      }
+    }
+    tile_partials<K>(acc, static_cast<int>(t), a.parts_x);
+  }
+}
+
+// -------------------------------------------------------------------- spmm
+// Y = M X for K interleaved starts. Each tile is walked in chunks of 32 rows:
+// thread t handles (entry t/K, start t%K), so the K threads of an entry read
+// the same col/val (one transaction) and 64 contiguous bytes of X, and all
+// products of the chunk are in flight at once; they are parked in LDS and
+// thread (row, start) adds up its row. Starts that have stopped are skipped,
+// and a tile whose matrix has no running start is skipped entirely.
+constexpr int kChunkRowsB = kB / 8;  // 32 rows x 8 starts
+constexpr int kChunkCap = 256;       // entries staged per chunk
+
+template <int K>
+__global__ __launch_bounds__(kB) void b_spmm_k(BatchArgs a, const int* __restrict__ rowptr,
+                                               const int* __restrict__ col,
+                                               const double* __restrict__ val,
+                                               const double* __restrict__ x, double* __restrict__ y,
+                                               double* __restrict__ parts) {
+  __shared__ double prod[kChunkCap * K];
+  __shared__ int rp_sh[kChunkRowsB + 1];
+  __shared__ int run_sh[K];
+  long long t0, t1;
+  tile_range(a.ntiles, t0, t1);
+  const int k = threadIdx.x % K;
+  const int rl = threadIdx.x / K;  // row of this thread inside a chunk
+  for (long long t = t0; t < t1; ++t) {
+    const int mat = a.tile_mat[t];
+    if (threadIdx.x < K) run_sh[threadIdx.x] = !a.pairs[static_cast<long long>(mat) * K + threadIdx.x].stopped;
+    __syncthreads();
+    int any = 0;
+#pragma unroll
+    for (int u = 0; u < K; ++u) any |= run_sh[u];
+    const bool mine = run_sh[k] != 0;
+    const long long r0 = a.tiles[t], r1 = a.tiles[t + 1];
+    double sq = 0.0;
+    if (any) {
+      for (long long c0 = r0; c0 < r1; c0 += kChunkRowsB) {
+        const int cnt = static_cast<int>(r1 - c0 < kChunkRowsB ? r1 - c0 : kChunkRowsB);
+        if (threadIdx.x <= cnt) rp_sh[threadIdx.x] = rowptr[c0 + threadIdx.x];
+        __syncthreads();
+        const int e0 = rp_sh[0], ne = rp_sh[cnt] - e0;
+        if (ne <= kChunkCap) {
+          for (int idx = threadIdx.x; idx < ne * K; idx += kB) {
+            const int e = e0 + idx / K;
+            if (mine) prod[idx] = val[e] * x[static_cast<long long>(col[e]) * K + k];
+          }
+          __syncthreads();
+          if (rl < cnt && mine) {
+            const int a0 = rp_sh[rl] - e0, a1 = rp_sh[rl + 1] - e0;
+            double acc = 0.0;
+            for (int e = a0; e < a1; ++e) acc += prod[e * K + k];
+            y[(c0 + rl) * K + k] = acc;
+            sq += acc * acc;
+          }
+        } else if (rl < cnt && mine) {
+          // a chunk with long rows: each (row, start) thread walks its row
+          const int p0 = rp_sh[rl], p1 = rp_sh[rl + 1];
+          double acc = 0.0;
+          for (int q = p0; q < p1; ++q) acc += val[q] * x[static_cast<long long>(col[q]) * K + k];
+          y[(c0 + rl) * K + k] = acc;
+          sq += acc * acc;
+        }
+        __syncthreads();  // rp_sh and prod are reused
+      }
+    }
+    if (parts) tile_partials<K>(sq, static_cast<int>(t), parts);
+  }
+}
+
+// ----------------------------------------------------------------- pass 1
+template <int K>
+__global__ __launch_bounds__(kB) void b_pass1_k(BatchArgs a, AdamParams p) {
+#pragma clang fp contract(off)
+  long long t0, t1;
+  tile_range(a.ntiles, t0, t1);
+  const int k = threadIdx.x % K;
+  const double b1 = p.beta1, b2 = p.beta2;
+  const double b1t = a.g->b1t * b1, b2t = a.g->b2t * b2;
+  for (long long t = t0; t < t1; ++t) {
+    const int mat = a.tile_mat[t];
+    const BatchPair& q = a.pairs[static_cast<long long>(mat) * K + k];
+    const long long r0 = a.tiles[t], r1 = a.tiles[t + 1];
+    double acc = 0.0;
+    if (q.improved && a.xbest)
+      for (long long e = r0 * K + threadIdx.x; e < r1 * K; e += kB) a.xbest[e] = a.x[e];
+    if (!q.stopped) {
+      const double nx2 = q.nx2, ny2 = q.ny2;
+      for (long long e = r0 * K + threadIdx.x; e < r1 * K; e += kB) {
+        const double xi = a.x[e];
+        const double g = xi / nx2 - a.w[e] / ny2;
+        const double mi = b1 * a.m[e] + (1.0 - b1) * g;
+        const double vi = b2 * a.v[e] + (1.0 - b2) * (g * g);
+        const double mh = mi / (1.0 - b1t);
+        const double vh = vi / (1.0 - b2t);
+        const double di = p.alpha * mh / (sqrt(vh) + p.eps);
+        a.m[e] = mi;
+        a.v[e] = vi;
+        a.d[e] = di;
+        acc += xi * di;
+      }
+    }
+    tile_partials<K>(acc, static_cast<int>(t), a.parts_xd);
+  }
+}
+
+// ----------------------------------------------------------------- pass 2
+template <int K>
+__global__ __launch_bounds__(kB) void b_pass2_k(BatchArgs a, AdamParams p) {
+#pragma clang fp contract(off)
+  long long t0, t1;
+  tile_range(a.ntiles, t0, t1);
+  const int k = threadIdx.x % K;
+  for (long long t = t0; t < t1; ++t) {
+    const int mat = a.tile_mat[t];
+    const BatchPair& q = a.pairs[static_cast<long long>(mat) * K + k];
+    const long long r0 = a.tiles[t], r1 = a.tiles[t + 1];
+    double acc = 0.0;
+    if (!q.stopped) {
+      const double xd = q.xd;
+      for (long long e = r0 * K + threadIdx.x; e < r1 * K; e += kB) {
+        const double xi = a.x[e];
+        const double dd = a.d[e] - xd * xi;
+        const double xn = xi - dd;
+        a.x[e] = xn;
+        acc += xn * xn;
+      }
+    }
+    tile_partials<K>(acc, static_cast<int>(t), a.parts_xx);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.g->t_done = a.g->t_done + 1;
+    a.g->b1t = a.g->b1t * p.beta1;
+    a.g->b2t = a.g->b2t * p.beta2;
+  }
+}
+
+}  // namespace
+
+void batch_launch_init(const BatchArgs& a, const double* x0, int grid, hipStream_t s) {
+  b_init_k<kBatchK><<<grid, kB, 0, s>>>(a, x0);
+}
+void batch_launch_reduce(const BatchArgs& a, int mode, const AdamParams& p, hipStream_t s) {
+  b_reduce_k<kBatchK><<<a.nmat, kB, 0, s>>>(a, mode, p);
+}
+void batch_launch_normalise(const BatchArgs& a, int grid, hipStream_t s) {
+  b_normalise_k<kBatchK><<<grid, kB, 0, s>>>(a);
+}
+void batch_launch_spmm(const BatchArgs& a, int transpose, int grid, hipStream_t s) {
+  if (transpose)
+    b_spmm_k<kBatchK><<<grid, kB, 0, s>>>(a, a.at_rowptr, a.at_col, a.at_val, a.y, a.w, nullptr);
+  else
+    b_spmm_k<kBatchK><<<grid, kB, 0, s>>>(a, a.a_rowptr, a.a_col, a.a_val, a.x, a.y, a.parts_y);
+}
+void batch_launch_pass1(const BatchArgs& a, const AdamParams& p, int grid, hipStream_t s) {
+  b_pass1_k<kBatchK><<<grid, kB, 0, s>>>(a, p);
+}
+void batch_launch_pass2(const BatchArgs& a, const AdamParams& p, int grid, hipStream_t s) {
+  b_pass2_k<kBatchK><<<grid, kB, 0, s>>>(a, p);
+}
+
+}  // namespace condest

@@ -140,3 +140,23 @@ def test_plan_create_on_host_reports_workspace():
     p = pa.Plan(a.n, a.rowptr, a.col, a.val)
     assert p.workspace_bytes >= 12 * 2 * a.nnz + 8 * 10 * a.n
     p.close()
+
+
+def test_batch_create_on_host():
+    # batch set-up is host work: concatenation and workspace sizing
+    mats = [hydromech2d(s, seed=s) for s in (5, 7, 6)]
+    b = pa.Batch([(m.n, m.rowptr, m.col, m.val) for m in mats])
+    assert list(b.row0) == [0, mats[0].n, mats[0].n + mats[1].n, sum(m.n for m in mats)]
+    assert b.workspace_bytes >= 8 * 8 * 7 * b.row0[-1]
+    b.close()
+
+
+def test_interleave_starts_layout():
+    s0 = np.arange(16.0).reshape(8, 2)
+    s1 = 100 + np.arange(24.0).reshape(8, 3)
+    v = pa.interleave_starts([s0, s1])
+    # global row 0 = matrix 0 row 0: starts 0..7 are s0[:, 0]
+    np.testing.assert_array_equal(v[:8], s0[:, 0])
+    np.testing.assert_array_equal(v[8:16], s0[:, 1])
+    np.testing.assert_array_equal(v[16:24], s1[:, 0])
+    assert v.size == 8 * 5

@@ -1,0 +1,102 @@
+"""Batched multi-start sigma_max run against the plain run and the oracle.
+
+Every (matrix, start) pair of a batch runs the plain method's Algorithm 1;
+only the order of additions inside its global sums differs. So each pair's
+best sigma must equal the plain run's from the same start to rounding, its
+trace must follow the plain trace, and stopping pairs must stop at the same
+update as the oracle.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import PAOptions
+from oracle.estimate import forward_apply
+from oracle.padam import projected_adam
+from synth import hm_batch_specs, hydromech2d, start_block
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2409_11515_amd as pa
+
+    pa._binding.lib()
+    return torch
+
+
+def _batch_inputs(sides, seed=3):
+    mats = [hydromech2d(s, seed=seed + i) for i, s in enumerate(sides)]
+    starts = [start_block(m.n, 8, 1000 + i) for i, m in enumerate(mats)]
+    return mats, starts
+
+
+def test_batch_matches_plain_runs(torch_cuda):
+    import paper_2409_11515_amd as pa
+
+    torch = torch_cuda
+    mats, starts = _batch_inputs([5, 9, 13, 7])
+    b = pa.Batch([(m.n, m.rowptr, m.col, m.val) for m in mats]).bind(tile_rows=32, grid=1024)
+    x0 = torch.as_tensor(pa.interleave_starts(starts), device="cuda")
+    r = b.run(x0, max_iter=300, trace=True)
+    b.close()
+    for i, m in enumerate(mats):
+        p = pa.Plan(m.n, m.rowptr, m.col, m.val, sigma_min_method=pa.COND_MIN_NONE).bind()
+        for k in range(8):
+            g = p.run(torch.as_tensor(starts[i][k], device="cuda"), max_iter=300, trace=True)
+            assert r["pair_best"][i, k] == pytest.approx(g["sigma_max"], rel=1e-10)
+            np.testing.assert_allclose(r["trace"][i, k, :50], g["trace_max"][:50], rtol=1e-11)
+        p.close()
+        assert r["sigma_max"][i] == r["pair_best"][i].max()
+    assert np.all(r["pair_iters"] == 300)
+
+
+def test_batch_stop_rule_matches_oracle(torch_cuda):
+    import paper_2409_11515_amd as pa
+
+    torch = torch_cuda
+    mats, starts = _batch_inputs([11, 6])
+    b = pa.Batch([(m.n, m.rowptr, m.col, m.val) for m in mats]).bind(tile_rows=64, grid=1024)
+    x0 = torch.as_tensor(pa.interleave_starts(starts), device="cuda")
+    opts = dict(max_iter=4000, stop_rtol=1e-9, stop_window=50)
+    r = b.run(x0, **opts)
+    b.close()
+    for i, m in enumerate(mats):
+        apply, evaluate = forward_apply(m.n, m.rowptr, m.col, m.val)
+        for k in (0, 5):
+            o = projected_adam(apply, evaluate, starts[i][k], PAOptions(**opts))
+            assert r["pair_iters"][i, k] == o.iters
+            assert r["pair_best"][i, k] == pytest.approx(o.sigma, rel=1e-9)
+
+
+def test_batch_uneven_sizes_and_determinism(torch_cuda):
+    import paper_2409_11515_amd as pa
+
+    torch = torch_cuda
+    specs = hm_batch_specs(count=6, side_range=(5, 40), seed_sides=7, seed_base=8)
+    mats = [hydromech2d(s, log_eta=le, log_k=lk) for s, le, lk in specs]
+    starts = [start_block(m.n, 8, 50 + i) for i, m in enumerate(mats)]
+    b = pa.Batch([(m.n, m.rowptr, m.col, m.val) for m in mats]).bind(tile_rows=128, grid=2048)
+    x0 = torch.as_tensor(pa.interleave_starts(starts), device="cuda")
+    r1 = b.run(x0, max_iter=500)
+    r2 = b.run(x0, max_iter=500)
+    np.testing.assert_array_equal(r1["pair_best"], r2["pair_best"])
+    # against the oracle for one start of every matrix
+    for i, m in enumerate(mats):
+        apply, evaluate = forward_apply(m.n, m.rowptr, m.col, m.val)
+        o = projected_adam(apply, evaluate, starts[i][3], PAOptions(max_iter=500))
+        assert r1["pair_best"][i, 3] == pytest.approx(o.sigma, rel=1e-9)
+    b.close()
+
+
+def test_batch_autotuner_picks_a_candidate(torch_cuda):
+    import paper_2409_11515_amd as pa
+
+    mats, _ = _batch_inputs([8, 12])
+    b = pa.Batch([(m.n, m.rowptr, m.col, m.val) for m in mats]).bind()
+    assert b.tile_rows in (32, 64, 128, 256) and b.grid in (1024, 2048, 4096)
+    b.close()
