@@ -148,7 +148,7 @@ class _Triplets:
 
 
 def _balance_and_scale(a, kinds, small_kinds, rng, big_decades=(10.0, 13.0),
-                       small_decades=(-5.0, -2.0), sweeps: int = 3):
+                       small_decades=(-5.0, -2.0), sweeps: int = 3, position=None):
     """Unit choice per unknown type, then an explicit column scaling.
 
     ``kinds[i]`` is the unknown type of column i and the equation type of row
@@ -157,7 +157,9 @@ def _balance_and_scale(a, kinds, small_kinds, rng, big_decades=(10.0, 13.0),
     median row / column norm of that type), a change of units that removes
     the between-type imbalance of the raw SI coefficients. Then every column
     is normalised and multiplied by 10**U(big_decades) or, for the types in
-    ``small_kinds``, 10**U(small_decades). The result is A = B D with
+    ``small_kinds``, 10**U(small_decades), or -- when ``position`` (one value in
+    [0, 1] per column) is given -- to that place inside its cluster's range.
+    The result is A = B D with
     kappa(B) set by the physics (viscosity and permeability contrasts, grid
     size) and the extra ill-conditioning carried by the column scaling D, the
     structure the paper reports for its systems: column norms in two clusters
@@ -180,8 +182,12 @@ def _balance_and_scale(a, kinds, small_kinds, rng, big_decades=(10.0, 13.0),
         a = sp.diags(1.0 / rs) @ a
     cn = np.sqrt(np.asarray(a.multiply(a).sum(axis=0)).ravel())
     small = np.isin(kinds, np.asarray(list(small_kinds)))
-    dec = np.where(small, rng.uniform(small_decades[0], small_decades[1], kinds.size),
-                   rng.uniform(big_decades[0], big_decades[1], kinds.size))
+    if position is None:  # seeded random place inside each cluster
+        dec = np.where(small, rng.uniform(small_decades[0], small_decades[1], kinds.size),
+                       rng.uniform(big_decades[0], big_decades[1], kinds.size))
+    else:
+        dec = np.where(small, small_decades[0] + (small_decades[1] - small_decades[0]) * position,
+                       big_decades[0] + (big_decades[1] - big_decades[0]) * position)
     return sp.csr_matrix(a @ sp.diags(10.0 ** dec / cn))
 
 # ---------------------------------------------------------- tiny Stokes (C1)
@@ -331,7 +337,8 @@ def hm_fields(side: int, seed: int, eta_range=(18.0, 24.0), perm_range=(-20.0, -
 
 def hydromech2d(side: int, seed: int | None = None, log_eta=None, log_k=None, consts=None,
                 pressure_scale: float | None = None, flux_scale: float = 1.0, raw: bool = False,
-                big_decades=(11.0, 14.0), small_decades=(-6.0, -3.0)) -> Csr:
+                big_decades=(11.5, 14.5), small_decades=(-5.0, -2.0), eta_range=(18.0, 24.0),
+                perm_range=(-20.0, -12.0)) -> Csr:
     """Six-field hydro-mechanical staggered-grid matrix on side x side nodes.
 
     Ordering is node-major: unknown (i, j, f) -> 6*(i*side + j) + f with
@@ -353,8 +360,9 @@ def hydromech2d(side: int, seed: int | None = None, log_eta=None, log_k=None, co
 
     Unless ``raw``, the SI system then goes through ``_balance_and_scale`` with
     the two Darcy-flux fields (qx, qy: one third of the columns, as in the
-    paper's column-norm distribution) in the small cluster; the column scales
-    are seeded from ``seed + 1`` (or 1 when the fields are passed in).
+    paper's column-norm distribution) in the small cluster; each column's place
+    inside its cluster follows the local log-permeability (flux columns) or
+    log-viscosity (the others), so the matrix depends on the fields only.
     """
     k = side
     if k < 4:
@@ -363,7 +371,7 @@ def hydromech2d(side: int, seed: int | None = None, log_eta=None, log_k=None, co
     if consts:
         cst.update(consts)
     if log_eta is None or log_k is None:
-        le, lk = hm_fields(side, 0 if seed is None else seed)
+        le, lk = hm_fields(side, 0 if seed is None else seed, eta_range, perm_range)
         log_eta = le if log_eta is None else log_eta
         log_k = lk if log_k is None else log_k
     log_eta = np.asarray(log_eta, dtype=np.float64)
@@ -495,8 +503,21 @@ def hydromech2d(side: int, seed: int | None = None, log_eta=None, log_k=None, co
     if raw:
         return a
     kinds = np.arange(n, dtype=np.int64) % 6
-    srng = np.random.default_rng((0 if seed is None else seed) + 1)
-    b = _balance_and_scale(a.to_scipy(), kinds, (QX, QY), srng, big_decades, small_decades)
+    # Column scales follow the local coefficients (a choice of units per
+    # unknown proportional to the local material): a flux column's place in
+    # the small cluster is its node's log-permeability, every other column's
+    # place in the large cluster its node's log-viscosity. The matrix is then
+    # a function of the two fields alone.
+    padk = np.pad(log_k, 1, mode="edge")
+    node_k = 0.25 * (padk[:-1, :-1] + padk[1:, :-1] + padk[:-1, 1:] + padk[1:, 1:])
+    pade = np.pad(log_eta, 1, mode="edge")
+    node_e = 0.25 * (pade[:-1, :-1] + pade[1:, :-1] + pade[:-1, 1:] + pade[1:, 1:])
+    pos_k = np.clip((node_k - perm_range[0]) / (perm_range[1] - perm_range[0]), 0.0, 1.0)
+    pos_e = np.clip((node_e - eta_range[0]) / (eta_range[1] - eta_range[0]), 0.0, 1.0)
+    position = np.where(np.isin(kinds, (QX, QY)), np.repeat(pos_k.ravel(), 6),
+                        np.repeat(pos_e.ravel(), 6))
+    b = _balance_and_scale(a.to_scipy(), kinds, (QX, QY), None, big_decades, small_decades,
+                           position=position)
     return Csr.from_scipy(b, meta)
 
 
