@@ -240,6 +240,55 @@ int cond_batch_run(cond_batch_t* b, const cond_opts_t* o, const double* x0, doub
                    double* x_best, double* ms);
 void cond_batch_destroy(cond_batch_t* b);
 
+/* ------------------------------------------------------ learned warm start
+ * A start vector for the sigma_min run (Algorithm 2) predicted from the two
+ * coefficient fields of a hydro-mechanical grid by a small CNN: four 3x3
+ * zero-padded convolutions, 2 -> 64 -> 64 -> 64 -> 6 channels, ReLU after the
+ * first three. bfloat16 weights and activations, float32 accumulation on the
+ * matrix cores; float32 master weights trained by Adam on the loss
+ * l = 1 - (p.u)^2 / ((p.p)(u.u)) against minimisers u found by plain runs.
+ * The paper has no such network; a start only changes how many updates the
+ * run needs, never what it computes, and callers keep a random start beside
+ * it (the larger lower bound wins).
+ *
+ * Parameters: one float32 vector of cond_cnn_param_count() values, layer by
+ * layer, W[ky][kx][ci][co] then b[co]. Fields: device float64 array
+ * [batch][2][side-1][side-1] of per-cell log10 viscosity and log10
+ * permeability. Start vectors: device float64 [batch][6 side^2] in the
+ * matrix's node-major order 6 (i side + j) + f. Labels: device float32 in the
+ * same layout. Every sample of a call has the same side.
+ *
+ * cond_cnn_create: device buffers for up to max_batch samples of side up to
+ * max_side, with the training buffers if train != 0; all work goes on
+ * `stream` (0 = the null stream) and every call returns after its work has
+ * finished. cond_cnn_set_params uploads parameters (host) and resets Adam.
+ * cond_cnn_predict writes x0. cond_cnn_gradients writes the gradient of the
+ * batch's mean loss (host float32, param_count values, may be NULL) and the
+ * per-sample losses (host, batch values, may be NULL). cond_cnn_train_step
+ * does the same forward and backward, then one Adam step (beta1 0.9, beta2
+ * 0.999, eps 1e-8) with rate lr; mean_loss (host, may be NULL) receives the
+ * batch's mean loss before the step. cond_cnn_activation copies layer
+ * `layer`'s stored activation of the last call (0 = input, 1..3 = hidden
+ * outputs, channels padded to 8, 64, 64, 64, as float32 [batch][side][side]
+ * [channels]; 4 = the float32 output padded to 16 channels) to host memory.
+ * Errors: COND_EINVAL for sizes beyond those given at create or NULL
+ * required pointers, COND_ESTATE for training calls on a network created
+ * without training buffers, COND_EHIP for runtime failures. */
+typedef struct cond_cnn cond_cnn_t;
+int cond_cnn_param_count(void);
+int cond_cnn_create(int32_t max_batch, int32_t max_side, int32_t train, void* stream,
+                    cond_cnn_t** out);
+int cond_cnn_set_params(cond_cnn_t* net, const float* params);
+int cond_cnn_get_params(const cond_cnn_t* net, float* params);
+int cond_cnn_predict(cond_cnn_t* net, const double* fields, int32_t batch, int32_t side, double* x0);
+int cond_cnn_gradients(cond_cnn_t* net, const double* fields, const float* labels, int32_t batch,
+                       int32_t side, float* grad, float* losses);
+int cond_cnn_train_step(cond_cnn_t* net, const double* fields, const float* labels, int32_t batch,
+                        int32_t side, float lr, float* mean_loss);
+int cond_cnn_activation(const cond_cnn_t* net, int32_t layer, int32_t batch, int32_t side,
+                        float* host);
+void cond_cnn_destroy(cond_cnn_t* net);
+
 /* create + bind (library-owned memory) + run + destroy. */
 int cond_estimate(const cond_csr_t* A, const cond_opts_t* o, const double* x0_max,
                   const double* x0_min, void* stream, cond_result_t* out);

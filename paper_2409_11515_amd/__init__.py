@@ -29,7 +29,7 @@ from ._binding import (  # noqa: F401
     make_opts,
 )
 
-__all__ = ["csr_check", "csr_transpose", "order_nd", "LU", "Plan", "Batch", "interleave_starts",
+__all__ = ["csr_check", "csr_transpose", "order_nd", "LU", "Plan", "Batch", "CNN", "interleave_starts",
            "estimate_cond", "CondError"]
 
 
@@ -309,3 +309,82 @@ def estimate_cond(n, rowptr, col, val, x0_max, x0_min=None, stream=None, **opts)
                              _stream_ptr(torch, stream), C.byref(res))
     check(st, "estimate")
     return {f: getattr(res, f) for f, _ in ResultT._fields_}
+
+
+class CNN:
+    """The warm-start network on the device (``cond_cnn_*``).
+
+    ``CNN(max_batch, max_side, train=True)``; ``set_params(vec)`` takes the
+    float32 parameter vector (layer by layer, W[ky][kx][ci][co] then b[co]);
+    ``predict(fields)`` maps a CUDA float64 tensor [batch, 2, side-1, side-1]
+    of per-cell (log10 eta, log10 k) to start vectors [batch, 6 side^2];
+    ``gradients`` / ``train_step`` take float32 labels in that layout.
+    """
+
+    def __init__(self, max_batch, max_side, train=True, stream=None):
+        import torch
+
+        self._h = C.c_void_p()
+        self.max_batch, self.max_side = int(max_batch), int(max_side)
+        self.param_count = lib().cond_cnn_param_count()
+        check(lib().cond_cnn_create(self.max_batch, self.max_side, 1 if train else 0,
+                                    _stream_ptr(torch, stream), C.byref(self._h)), "cnn_create")
+
+    def set_params(self, vec):
+        v = np.ascontiguousarray(vec, np.float32)
+        if v.size != self.param_count:
+            raise ValueError(f"expected {self.param_count} parameters, got {v.size}")
+        check(lib().cond_cnn_set_params(self._h, v.ctypes.data), "cnn_set_params")
+        return self
+
+    def get_params(self) -> np.ndarray:
+        v = np.zeros(self.param_count, np.float32)
+        check(lib().cond_cnn_get_params(self._h, v.ctypes.data), "cnn_get_params")
+        return v
+
+    @staticmethod
+    def _shape(fields):
+        import torch
+
+        if fields.dtype != torch.float64 or fields.dim() != 4 or fields.shape[1] != 2 \
+                or fields.shape[2] != fields.shape[3] or not fields.is_contiguous():
+            raise ValueError("fields must be a contiguous float64 tensor [batch, 2, s-1, s-1]")
+        return int(fields.shape[0]), int(fields.shape[2]) + 1
+
+    def predict(self, fields):
+        import torch
+
+        b, s = self._shape(fields)
+        x0 = torch.empty(b, 6 * s * s, dtype=torch.float64, device=fields.device)
+        check(lib().cond_cnn_predict(self._h, fields.data_ptr(), b, s, x0.data_ptr()), "cnn_predict")
+        return x0
+
+    def gradients(self, fields, labels):
+        b, s = self._shape(fields)
+        g = np.zeros(self.param_count, np.float32)
+        losses = np.zeros(b, np.float32)
+        check(lib().cond_cnn_gradients(self._h, fields.data_ptr(), labels.data_ptr(), b, s,
+                                       g.ctypes.data, losses.ctypes.data), "cnn_gradients")
+        return g, losses
+
+    def train_step(self, fields, labels, lr) -> float:
+        b, s = self._shape(fields)
+        ml = C.c_float()
+        check(lib().cond_cnn_train_step(self._h, fields.data_ptr(), labels.data_ptr(), b, s,
+                                        float(lr), C.byref(ml)), "cnn_train_step")
+        return ml.value
+
+    def activation(self, layer, batch, side) -> np.ndarray:
+        ch = (8, 64, 64, 64, 16)[layer]
+        a = np.zeros((batch, side, side, ch), np.float32)
+        check(lib().cond_cnn_activation(self._h, int(layer), int(batch), int(side), a.ctypes.data),
+              "cnn_activation")
+        return a
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().cond_cnn_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        self.close()

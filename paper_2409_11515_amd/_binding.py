@@ -67,6 +67,9 @@ EXPORTS = (
     "cond_plan_bind", "cond_plan_destroy", "cond_plan_run", "cond_plan_spmv",
     "cond_plan_inverse_apply", "cond_estimate", "cond_plan_kernel_stats", "cond_batch_create",
     "cond_batch_info", "cond_batch_bind", "cond_batch_run", "cond_batch_destroy",
+    "cond_cnn_param_count", "cond_cnn_create", "cond_cnn_set_params", "cond_cnn_get_params",
+    "cond_cnn_predict", "cond_cnn_gradients", "cond_cnn_train_step", "cond_cnn_activation",
+    "cond_cnn_destroy",
 )
 
 BATCH_K = 8
@@ -117,6 +120,16 @@ def lib():
                                  C.POINTER(dbl)]
     L.cond_batch_destroy.argtypes = [vp]
     L.cond_batch_destroy.restype = None
+    L.cond_cnn_param_count.argtypes = []
+    L.cond_cnn_create.argtypes = [i32, i32, i32, vp, C.POINTER(vp)]
+    L.cond_cnn_set_params.argtypes = [vp, vp]
+    L.cond_cnn_get_params.argtypes = [vp, vp]
+    L.cond_cnn_predict.argtypes = [vp, vp, i32, i32, vp]
+    L.cond_cnn_gradients.argtypes = [vp, vp, vp, i32, i32, vp, vp]
+    L.cond_cnn_train_step.argtypes = [vp, vp, vp, i32, i32, C.c_float, C.POINTER(C.c_float)]
+    L.cond_cnn_activation.argtypes = [vp, i32, i32, i32, vp]
+    L.cond_cnn_destroy.argtypes = [vp]
+    L.cond_cnn_destroy.restype = None
     for name in EXPORTS:
         getattr(L, name)  # raises AttributeError if a declared symbol is missing
     _lib = L
