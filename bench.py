@@ -1,6 +1,7 @@
 """Benchmark: time-to-kappa of the Projected Adam estimator on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload hm201|hm1001|stokes10]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+                    [--workload hm201|hm1001|stokes10|c4batch|c5warm]
 
 One step = one full estimate of kappa_2 for one matrix: the sigma_max run
 (SpMV with A and A^T, global norms, fused Adam moment update and projection)
@@ -45,7 +46,128 @@ WORKLOADS = {
                      min_route=True),
     # 64 matrices, sides U{51..401}, perturbed copies of one base field, 8 starts each
     "c4batch": dict(kind="batch", count=64, side_range=(51, 401), min_route=False),
+    # learned warm start: trained on small grids, tested on held-out 201x201 systems
+    "c5warm": dict(kind="warm", train_side=25, test_side=201, min_route=True),
 }
+
+
+def bench_warm(w, args):
+    """Warm-started vs plain sigma_min runs on held-out systems.
+
+    Training: plain sigma_min runs label the maximisers of ||A^-1 x||/||x|| on
+    seeded training matrices (seeds 10000+), the network is fitted on the
+    device. Test: held-out seeds 20000+; per matrix one sigma_max run, the
+    plain (random-start) sigma_min run, and the warm-started run with its
+    random-start check and fallback; every run stops by the same rule."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import torch
+
+    import paper_2409_11515_amd as pa
+    from paper_2409_11515_amd.warmstart import WarmStart, label
+    from synth import hm_fields, hydromech2d, start_vector
+
+    opts = dict(max_iter=args.max_iter, stop_rtol=args.stop_rtol, stop_window=args.stop_window)
+    lab_opts = dict(max_iter=4000, stop_rtol=1e-7, stop_window=50)
+    ts, ntr = w["train_side"], args.train_count
+    t0 = time.perf_counter()
+
+    def build(seed, side):
+        le, lk = hm_fields(side, seed)
+        a = hydromech2d(side, log_eta=le, log_k=lk)
+        return a, np.stack([le, lk]), pa.Plan(a.n, a.rowptr, a.col, a.val)
+
+    fields, labels = [], []
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        for i, (a, f, plan) in enumerate(ex.map(lambda s: build(s, ts), range(10000, 10000 + ntr))):
+            plan.bind()
+            u, _ = label(plan, torch.as_tensor(start_vector(a.n, 10000 + i), device="cuda"),
+                         **lab_opts)
+            plan.close()
+            fields.append(f)
+            labels.append(u)
+            if (i + 1) % 100 == 0:
+                print(f"[bench] labelled {i + 1}/{ntr} ({time.perf_counter() - t0:.0f}s)",
+                      file=sys.stderr, flush=True)
+    label_s = time.perf_counter() - t0
+    ws = WarmStart(16, w["test_side"], seed=0)
+    t0 = time.perf_counter()
+    hist = ws.fit(torch.as_tensor(np.asarray(fields), device="cuda").contiguous(),
+                  torch.stack(labels).contiguous(), epochs=args.epochs, batch=16, lr=2e-3,
+                  lr_final=1e-4)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    print(f"[bench] trained {args.epochs} epochs in {train_s:.1f}s, loss {hist[0]:.3f} -> "
+          f"{hist[-1]:.3f}", file=sys.stderr, flush=True)
+
+    side = w["test_side"]
+    rows = []
+    fwd_ms = []
+    with ThreadPoolExecutor(max_workers=min(8, args.test_count)) as ex:
+        futs = [ex.submit(build, s, side) for s in range(20000, 20000 + args.test_count)]
+        for i, fu in enumerate(futs):
+            a, f, plan = fu.result()
+            plan.bind()
+            seed = 20000 + i
+            xr = torch.as_tensor(start_vector(a.n, seed + 7), device="cuda")
+            ft = torch.as_tensor(f[None], device="cuda").contiguous()
+            ws.predict(ft)  # first call warms the kernels
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            ws.predict(ft)
+            e1.record()
+            torch.cuda.synchronize()
+            fwd_ms.append(e0.elapsed_time(e1))
+            cold = plan.run(xr, xr, **opts)
+            warm = ws.run(plan, ft, xr, **opts)
+            k_cold = cold["kappa"]
+            k_warm = cold["sigma_max"] / warm["sigma_min"]
+            rows.append(dict(seed=seed, cold_iters=cold["iters_min"], cold_ms=cold["ms_min"],
+                             warm_iters=warm["iters_warm"], warm_total_iters=warm["iters_total"],
+                             warm_ms=warm["ms_min"], fallback=warm["fallback"],
+                             kappa_plain=k_cold, kappa_warm=k_warm,
+                             kappa_rel_diff=abs(k_warm - k_cold) / k_cold,
+                             sigma_max_ms=cold["ms_max"]))
+            plan.close()
+            print(f"[bench] test {i + 1}/{args.test_count}: cold {cold['iters_min']} updates "
+                  f"{cold['ms_min']:.0f} ms, warm {warm['iters_warm']}+check "
+                  f"{warm['ms_min']:.0f} ms, fallback {warm['fallback']}, "
+                  f"kappa diff {rows[-1]['kappa_rel_diff']:.1e}", file=sys.stderr, flush=True)
+    ws.close()
+    cold_ms = np.array([r["cold_ms"] for r in rows])
+    warm_ms = np.array([r["warm_ms"] for r in rows])
+    smax_ms = np.array([r["sigma_max_ms"] for r in rows])
+    # forward pass: 2 * 9 * sum(cin * cout) FLOP per node with the true channel counts
+    flops = 2 * 9 * (2 * 64 + 64 * 64 + 64 * 64 + 64 * 6) * side * side
+    fwd = float(np.median(fwd_ms))
+    out = {
+        "metric": "time-to-kappa (1e-3 rel) per matrix, warm-started vs plain",
+        "value": float(np.mean(smax_ms + warm_ms)) / 1e3 + fwd / 1e3, "unit": "s", "n_gpus": 1,
+        "steps": len(rows), "warmup": 0,
+        "ms_per_step": float(np.mean(smax_ms + warm_ms)) + fwd, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64 (network bf16/f32)",
+        "data": "synthetic",
+        "config": {"workload": f"c5warm: held-out {side}x{side} hydro-mechanical systems "
+                               f"(seeds 20000+), network trained on {ntr} {ts}x{ts} systems",
+                   "epochs": args.epochs, "stop_rtol": args.stop_rtol,
+                   "stop_window": args.stop_window, "parallelism": "single GPU"},
+        "plain_s": float(np.mean(smax_ms + cold_ms)) / 1e3,
+        "speedup_sigma_min": float(np.sum(cold_ms) / np.sum(warm_ms)),
+        "fallback_rate": float(np.mean([r["fallback"] for r in rows])),
+        "kappa_rel_diff_max": float(max(r["kappa_rel_diff"] for r in rows)),
+        "updates_median": {"plain": float(np.median([r["cold_iters"] for r in rows])),
+                           "warm": float(np.median([r["warm_iters"] for r in rows])),
+                           "warm_with_check": float(np.median([r["warm_total_iters"]
+                                                               for r in rows]))},
+        "forward": {"ms": fwd, "gflop": flops / 1e9,
+                    "tflops": flops / (fwd * 1e-3) / 1e12},
+        "roofline": {"bound": "mfma", "achieved": flops / (fwd * 1e-3) / 1e12, "peak": 2500.0,
+                     "unit": "TFLOP/s", "frac": flops / (fwd * 1e-3) / 1e12 / 2500.0,
+                     "traffic": None, "kernel": "cnn forward (prep + 4 convs + output)"},
+        "label_s": label_s, "train_s": train_s, "loss": [hist[0], hist[-1]],
+        "tests": rows,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def bench_batch(w, args):
@@ -192,6 +314,9 @@ def main():
     ap.add_argument("--stop-rtol", type=float, default=1e-6)
     ap.add_argument("--stop-window", type=int, default=25)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--train-count", type=int, default=600, help="c5warm: training matrices")
+    ap.add_argument("--test-count", type=int, default=8, help="c5warm: held-out matrices")
+    ap.add_argument("--epochs", type=int, default=200, help="c5warm: training epochs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -206,6 +331,9 @@ def main():
     w = WORKLOADS[args.workload]
     if w["kind"] == "batch":
         bench_batch(w, args)
+        return
+    if w["kind"] == "warm":
+        bench_warm(w, args)
         return
     t0 = time.perf_counter()
     a = make_matrix(w)

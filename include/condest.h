@@ -170,7 +170,9 @@ void cond_plan_destroy(cond_plan_t* plan);
 
 /* Run both Projected Adam passes and assemble kappa. x0_max, x0_min: device
  * start vectors of length n (any non-zero scale; normalised inside; x0_min
- * may equal x0_max). trace_max / trace_min: optional device arrays of length
+ * may equal x0_max; x0_min = NULL uses x0_max). x0_max = NULL with x0_min
+ * given runs the sigma_min pass alone (sigma_max, iters_max and kappa are
+ * then 0); both NULL is COND_EINVAL. trace_max / trace_min: optional device arrays of length
  * o->max_iter receiving best-sigma after each evaluated iterate (trace[t-1] =
  * best over x_1..x_t; for the sigma_min run the values are ||A^-1 x||, i.e.
  * 1/sigma_min estimates). x_best_max / x_best_min: optional device outputs

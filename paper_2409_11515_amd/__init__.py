@@ -150,14 +150,14 @@ class Plan:
         import torch
 
         o = make_opts(**{**self._opts_dict(), **opts})
-        dev = x0_max.device
+        dev = (x0_max if x0_max is not None else x0_min).device
         T = int(o.max_iter)
         tmax = torch.zeros(T, dtype=torch.float64, device=dev) if trace else None
         tmin = torch.zeros(T, dtype=torch.float64, device=dev) if trace else None
         bmax = torch.zeros(self.n, dtype=torch.float64, device=dev) if x_best else None
         bmin = torch.zeros(self.n, dtype=torch.float64, device=dev) if x_best else None
         res = ResultT()
-        st = lib().cond_plan_run(self._h, C.byref(o), x0_max.data_ptr(),
+        st = lib().cond_plan_run(self._h, C.byref(o), None if x0_max is None else x0_max.data_ptr(),
                                  None if x0_min is None else x0_min.data_ptr(), C.byref(res),
                                  None if tmax is None else tmax.data_ptr(),
                                  None if tmin is None else tmin.data_ptr(),
@@ -213,7 +213,10 @@ class Plan:
         self.workspace = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: the library may already be gone
+            pass
 
 
 class Batch:
@@ -287,7 +290,10 @@ class Batch:
         self.workspace = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: the library may already be gone
+            pass
 
 
 def interleave_starts(starts_per_matrix) -> np.ndarray:
@@ -387,4 +393,7 @@ class CNN:
             self._h = C.c_void_p()
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: the library may already be gone
+            pass

@@ -765,7 +765,8 @@ int cond_plan_run(cond_plan_t* p, const cond_opts_t* o, const double* x0_max, co
   const cond_opts_t& oo = o ? *o : p->opts;
   int st = check_opts(&oo);
   if (st) return st;
-  if (!x0_max) return fail(COND_EINVAL, "null start vector");
+  if (!x0_max && !x0_min) return fail(COND_EINVAL, "null start vector");
+  const bool run_max = x0_max != nullptr;
   if (!x0_min) x0_min = x0_max;
   std::memset(out, 0, sizeof(*out));
   out->setup_ms = p->setup_ms;
@@ -780,12 +781,16 @@ int cond_plan_run(cond_plan_t* p, const cond_opts_t* o, const double* x0_max, co
     std::fill(p->kbytes, p->kbytes + COND_K_COUNT, 0.0);
   }
   RouteResult rmax, rmin;
-  if ((st = run_route(p, 0, oo, x0_max, trace_max, x_best_max, rmax))) return st;
-  out->sigma_max = rmax.sigma;
-  out->iters_max = rmax.iters;
-  out->status_max = rmax.status;
-  out->ms_max = rmax.ms;
-  if (rmax.flags & COND_F_MAXITER) out->flags |= COND_F_MAXITER;
+  if (run_max) {
+    if ((st = run_route(p, 0, oo, x0_max, trace_max, x_best_max, rmax))) return st;
+    out->sigma_max = rmax.sigma;
+    out->iters_max = rmax.iters;
+    out->status_max = rmax.status;
+    out->ms_max = rmax.ms;
+    if (rmax.flags & COND_F_MAXITER) out->flags |= COND_F_MAXITER;
+  } else if (!(p->want_min && oo.sigma_min_method == COND_MIN_LU)) {
+    return fail(COND_EINVAL, "null sigma_max start and no sigma_min run");
+  }
   if (p->want_min && oo.sigma_min_method == COND_MIN_LU) {
     if ((st = run_route(p, 1, oo, x0_min, trace_min, x_best_min, rmin))) return st;
     out->sigma_min = 1.0 / rmin.sigma;  // the run maximises ||A^-1 x|| / ||x||
@@ -793,8 +798,10 @@ int cond_plan_run(cond_plan_t* p, const cond_opts_t* o, const double* x0_max, co
     out->status_min = rmin.status;
     out->ms_min = rmin.ms;
     if (rmin.flags & COND_F_MAXITER) out->flags |= COND_F_MAXITER;
-    out->kappa = out->sigma_max / out->sigma_min;
-    if (out->kappa >= 1.0 / 2.220446049250313e-16) out->flags |= COND_F_NUMSING;
+    if (run_max) {
+      out->kappa = out->sigma_max / out->sigma_min;
+      if (out->kappa >= 1.0 / 2.220446049250313e-16) out->flags |= COND_F_NUMSING;
+    }
   }
   if (out->status_max) return fail(out->status_max, "sigma_max run failed");
   if (out->status_min) return fail(out->status_min, "sigma_min run failed");

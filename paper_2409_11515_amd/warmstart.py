@@ -8,9 +8,9 @@ changes nothing else. ``WarmStart`` wraps the ``cond_cnn_*`` network:
   the maximisers u, the network's targets;
 * ``fit``: Adam on the sign- and scale-invariant loss 1 - (p.u)^2/(|p|^2|u|^2);
 * ``run``: predicts x0 from the coefficient fields, runs the sigma_min
-  iteration from it and, as the fallback, from a random start too, and keeps
-  the larger ||A^-1 x|| / ||x|| (both are lower bounds of ||A^-1||, so the
-  larger is never worse).
+  iteration from it, gives a random start as many updates, and falls back to
+  the random start when that one reached the larger ||A^-1 x|| / ||x||
+  (both are lower bounds of ||A^-1||, so the larger is never worse).
 
 Every step runs in the library's kernels; this module only moves arguments.
 """
@@ -74,22 +74,29 @@ class WarmStart:
     def predict(self, fields):
         return self.net.predict(fields)
 
-    def run(self, plan: Plan, fields, x0_random, x0_max=None, **opts) -> dict:
-        """sigma_min from the predicted start and from x0_random; the result
-        with the larger best (smaller sigma_min) wins. fields: [1, 2, s-1, s-1]."""
+    def run(self, plan: Plan, fields, x0_random, **opts) -> dict:
+        """The sigma_min run from the predicted start, with a random start as
+        the fallback. fields: CUDA float64 [1, 2, s-1, s-1].
+
+        1. Run from the predicted start until the stop rule (or max_iter).
+        2. Give the random start the same number of updates (the check).
+        3. If the check reached a larger ||A^-1 x|| / ||x||, the prediction was
+           worse than chance: run the random start to the stop rule and keep
+           that result (the fallback).
+        Returns sigma_min, the updates and device milliseconds spent in all
+        runs together, and whether the fallback was taken."""
         x_warm = self.predict(fields)[0]
-        x_max = x0_random if x0_max is None else x0_max
-        warm = plan.run(x_max, x_warm, **opts)
-        cold = plan.run(x_max, x0_random, **opts)
-        out = dict(warm)
-        out["fallback"] = cold["sigma_min"] < warm["sigma_min"]
-        if out["fallback"]:
-            out.update({k: cold[k] for k in ("sigma_min", "iters_min", "status_min")})
-        out["kappa"] = out["sigma_max"] / out["sigma_min"]
-        out["iters_min_warm"] = warm["iters_min"]
-        out["iters_min_cold"] = cold["iters_min"]
-        out["ms_min_warm"] = warm["ms_min"]
-        out["ms_min_cold"] = cold["ms_min"]
+        warm = plan.run(None, x_warm, **opts)
+        t = max(1, int(warm["iters_min"]))
+        check = plan.run(None, x0_random, **{**opts, "max_iter": t})
+        out = dict(sigma_min=warm["sigma_min"], iters_warm=t, iters_total=t + check["iters_min"],
+                   ms_min=warm["ms_min"] + check["ms_min"], fallback=False,
+                   status_min=warm["status_min"])
+        if check["sigma_min"] < warm["sigma_min"]:
+            cold = plan.run(None, x0_random, **opts)
+            out.update(sigma_min=cold["sigma_min"], fallback=True, status_min=cold["status_min"],
+                       iters_total=out["iters_total"] + cold["iters_min"],
+                       ms_min=out["ms_min"] + cold["ms_min"])
         return out
 
     def close(self):
