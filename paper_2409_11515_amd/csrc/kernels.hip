@@ -255,6 +255,8 @@ constexpr int kTrsvBlock = 1024;
 constexpr int kUnroll = 8;
 constexpr int kLanesPerRow = 16;
 
+constexpr unsigned kMaxBackoff = 4u;        // sleep units between polls, at most
+
 __device__ __noinline__ double wait_pending(const double* p, RunState* st) {
   const unsigned long long* q = reinterpret_cast<const unsigned long long*>(p);
   unsigned slept = 0, backoff = 1, polls = 0;
@@ -272,7 +274,7 @@ __device__ __noinline__ double wait_pending(const double* p, RunState* st) {
     }
     for (unsigned k = 0; k < backoff; ++k) __builtin_amdgcn_s_sleep(1);
     slept += backoff;
-    if (backoff < 16u) backoff <<= 1;
+    if (backoff < kMaxBackoff) backoff <<= 1;
   }
   return __longlong_as_double(static_cast<long long>(bits));
 }
@@ -336,14 +338,81 @@ __device__ __forceinline__ double row_sum(long long p0, long long p1, int sub,
   return acc;
 }
 
+// Sums of up to NR rows of a row group at once (ranges [p0[j], p1[j]), empty
+// for absent rows), with the loads of all NR rows in flight together
+// (kUnroll / (2 NR) entries of each row per lane, within the register budget
+// of 1024-thread blocks).
+template <int NR>
+__device__ __forceinline__ void row_sums(const long long* p0, const long long* p1, int sub,
+                                         const int* __restrict__ col,
+                                         const double* __restrict__ val, const double* out,
+                                         RunState* st, double* acc) {
+  constexpr int U = kUnroll / NR / 2 > 0 ? kUnroll / NR / 2 : 1;
+  long long len = 0;
+#pragma unroll
+  for (int j = 0; j < NR; ++j) {
+    acc[j] = 0.0;
+    len = p1[j] - p0[j] > len ? p1[j] - p0[j] : len;
+  }
+  for (long long b = 0; b < len; b += kLanesPerRow * U) {
+    int jc[NR][U];
+    double a[NR][U];
+    unsigned long long bits[NR][U];
+#pragma unroll
+    for (int j = 0; j < NR; ++j)
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const long long p = p0[j] + b + u * kLanesPerRow + sub;
+        const bool act = p < p1[j];
+        jc[j][u] = act ? col[p] : -1;
+        a[j][u] = act ? val[p] : 0.0;
+      }
+#pragma unroll
+    for (int j = 0; j < NR; ++j)
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        bits[j][u] = jc[j][u] >= 0
+                         ? __hip_atomic_load(reinterpret_cast<const unsigned long long*>(out + jc[j][u]),
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)
+                         : 0ull;
+#pragma unroll
+    for (int j = 0; j < NR; ++j)
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (jc[j][u] >= 0) {
+          const double xj = bits[j][u] != kPending
+                                ? __longlong_as_double(static_cast<long long>(bits[j][u]))
+                                : wait_pending(out + jc[j][u], st);
+          acc[j] += a[j][u] * xj;
+        }
+  }
+#pragma unroll
+  for (int j = 0; j < NR; ++j)
+#pragma unroll
+    for (int off = kLanesPerRow / 2; off > 0; off >>= 1) acc[j] += __shfl_xor(acc[j], off, kLanesPerRow);
+}
+
+// A panel of up to kPanelRows rows is solved by one block as kSubPanels
+// sub-panels of 64 rows. Everything that does not depend on solved values --
+// the right-hand side, each sub-panel's triangle (into LDS) and the entries of
+// the second sub-panel on the first (into registers) -- is loaded before the
+// first wait, so that once the panel's inputs are published only the
+// off-panel sums, the short LDS steps and the substitutions remain.
+constexpr int kSubPanels = kPanelRows / kPanel;
+static_assert(kSubPanels == 1 || kSubPanels == 2, "one or two sub-panels per panel");
+constexpr int kLocalPerLane = kPanel / kLanesPerRow;  // entries of a row on the first sub-panel
+
 template <bool UNIT>
 __global__ __launch_bounds__(kTrsvBlock) void trsv_k(TrsvArgs t, const double* __restrict__ rhs,
                                                      const int* __restrict__ rhs_perm, double* out,
                                                      double* __restrict__ scatter,
                                                      const int* __restrict__ scatter_perm,
                                                      unsigned* ticket, RunState* st) {
-  __shared__ double m_sh[kPanel * kPanel];  // in-panel triangle, column-major: (r, c) at c*64 + r
-  __shared__ double t_sh[kPanel];
+  // sub-panel triangles, column-major: (r, c) of sub-panel k at [k][c*64 + r]
+  __shared__ double m_sh[kSubPanels][kPanel * kPanel];
+  __shared__ double t_sh[kPanelRows];  // off-panel sums (then minus the first sub-panel)
+  __shared__ double b_sh[kPanelRows];  // right-hand side of the panel's rows
+  __shared__ double x_sh[kPanel];      // solved values of the first sub-panel
   __shared__ unsigned task_sh;
   __shared__ int quit_sh;
   // one read for the whole block: abort_wait may change while blocks start
@@ -355,7 +424,7 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_k(TrsvArgs t, const double* _
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int sub = lane & (kLanesPerRow - 1);
-  const int r = wave * (64 / kLanesPerRow) + lane / kLanesPerRow;  // this group's row, 0..63
+  const int g = wave * (64 / kLanesPerRow) + lane / kLanesPerRow;  // this group's row, 0..63
   for (;;) {
     if (threadIdx.x == 0) task_sh = atomicAdd(ticket, 1u);
     __syncthreads();
@@ -366,67 +435,160 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_k(TrsvArgs t, const double* _
     const long long lo = t.pstart[P];
     const int cnt = t.pstart[P + 1] - t.pstart[P];
     const int S = t.panel_split[P];
-    double* slots = t.partials + static_cast<long long>(t.panel_slot[P]) * kPanel;
+    double* slots = t.partials + static_cast<long long>(t.panel_slot[P]) * kPanelRows;
+    long long q0[kSubPanels], q1[kSubPanels];  // the group's rows g + 64 j: off-panel ranges
+#pragma unroll
+    for (int j = 0; j < kSubPanels; ++j) {
+      const int r = g + kPanel * j;
+      q0[j] = r < cnt ? t.off_rp[lo + r] : 0;
+      q1[j] = r < cnt ? t.off_rp[lo + r + 1] : 0;
+    }
     if (kind >= 0 && kind < S) {
       // ---- slice task: partial off-panel sums over one slice of every row
-      if (r < cnt) {
-        const long long p0 = t.off_rp[lo + r], p1 = t.off_rp[lo + r + 1];
-        const long long len = p1 - p0;
-        const double part = row_sum(p0 + len * kind / S, p0 + len * (kind + 1) / S, sub,
-                                    t.off_col, t.off_val, out, st);
-        if (sub == 0) publish(slots + static_cast<long long>(kind) * kPanel + r, part);
+#pragma unroll
+      for (int j = 0; j < kSubPanels; ++j) {
+        const long long len = q1[j] - q0[j];
+        q1[j] = q0[j] + len * (kind + 1) / S;
+        q0[j] = q0[j] + len * kind / S;
+      }
+      double part[kSubPanels];
+      if (kSubPanels == 1 || cnt <= kPanel)
+        part[0] = row_sum(q0[0], q1[0], sub, t.off_col, t.off_val, out, st);
+      else
+        row_sums<kSubPanels>(q0, q1, sub, t.off_col, t.off_val, out, st, part);
+#pragma unroll
+      for (int j = 0; j < kSubPanels; ++j) {
+        const int r = g + kPanel * j;
+        if (r < cnt && sub == 0) publish(slots + static_cast<long long>(kind) * kPanelRows + r, part[j]);
       }
       __syncthreads();  // task_sh is reused
       continue;
     }
-    for (int k = threadIdx.x; k < kPanel * kPanel; k += kTrsvBlock) m_sh[k] = 0.0;
+    // ---- everything that needs no solved value
+    for (int e = threadIdx.x; e < kSubPanels * kPanel * kPanel; e += kTrsvBlock) (&m_sh[0][0])[e] = 0.0;
     __syncthreads();
-    double b = 0.0, dinv = 1.0;
-    if (wave == 0 && lane < cnt) {
-      const long long i = lo + lane;
-      b = rhs_perm ? rhs[rhs_perm[i]] : rhs[i];
-      if (!UNIT) dinv = 1.0 / t.diag[i];
+    int lc[kLocalPerLane];
+    double lv[kLocalPerLane];
+#pragma unroll
+    for (int u = 0; u < kLocalPerLane; ++u) {
+      lc[u] = 0;
+      lv[u] = 0.0;
     }
-    if (r < cnt) {
-      // in-panel entries of row r into LDS
-      const long long e0 = t.in_rp[lo + r], e1 = t.in_rp[lo + r + 1];
-      for (long long e = e0 + sub; e < e1; e += kLanesPerRow)
-        m_sh[t.in_col[e] * kPanel + r] = t.in_val[e];
-      double acc;
-      if (kind < 0) {
-        acc = row_sum(t.off_rp[lo + r], t.off_rp[lo + r + 1], sub, t.off_col, t.off_val, out, st);
-      } else {
-        // finish: add the slices in order, then re-arm their slots for the next solve
-        acc = 0.0;
-        for (int k = 0; k < S; ++k) acc += ready_value(slots + static_cast<long long>(k) * kPanel + r, st);
-        if (sub == 0)
-          for (int k = 0; k < S; ++k)
-            __hip_atomic_store(reinterpret_cast<unsigned long long*>(slots) +
-                                   static_cast<long long>(k) * kPanel + r,
-                               kPending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+    for (int j = 0; j < kSubPanels; ++j) {
+      const int r = g + kPanel * j;
+      if (r < cnt) {
+        if (sub == 0) b_sh[r] = rhs_perm ? rhs[rhs_perm[lo + r]] : rhs[lo + r];
+        const long long e0 = t.in_rp[lo + r], em = t.in_split[lo + r], e1 = t.in_rp[lo + r + 1];
+        if (j > 0) {  // entries on the first sub-panel: at most 64, four per lane
+#pragma unroll
+          for (int u = 0; u < kLocalPerLane; ++u) {
+            const long long e = e0 + u * kLanesPerRow + sub;
+            lc[u] = e < em ? t.in_col[e] : 0;
+            lv[u] = e < em ? t.in_val[e] : 0.0;
+          }
+        }
+        // the sub-panel's own triangle: at most 63 entries, four per lane
+        int c[4];
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const long long e = em + u * kLanesPerRow + sub;
+          c[u] = e < e1 ? t.in_col[e] - kPanel * j : -1;
+          v[u] = e < e1 ? t.in_val[e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (c[u] >= 0) m_sh[j][c[u] * kPanel + g] = v[u];
       }
-      if (sub == 0) t_sh[r] = acc;
     }
+    // ---- off-panel sums of every row (these wait for the panel's inputs)
+    double sums[kSubPanels];
+    if (kind < 0) {
+      if (kSubPanels == 1 || cnt <= kPanel)
+        sums[0] = row_sum(q0[0], q1[0], sub, t.off_col, t.off_val, out, st);
+      else
+        row_sums<kSubPanels>(q0, q1, sub, t.off_col, t.off_val, out, st, sums);
+    } else {
+      // finish: the 16 lanes of a row read its slice partials together (lane
+      // sub takes slices sub, sub + 16, ...), add them in that fixed order,
+      // then re-arm the slots they read for the next solve
+#pragma unroll
+      for (int j = 0; j < kSubPanels; ++j) {
+        const int r = g + kPanel * j;
+        double acc = 0.0;
+        if (r < cnt) {
+          constexpr int kSlotsPerLane = kMaxSlicesDev / kLanesPerRow;
+          unsigned long long bits[kSlotsPerLane];
+          unsigned long long* sp = reinterpret_cast<unsigned long long*>(slots) + r;
+#pragma unroll
+          for (int u = 0; u < kSlotsPerLane; ++u) {
+            const int k = sub + u * kLanesPerRow;
+            bits[u] = k < S ? __hip_atomic_load(sp + static_cast<long long>(k) * kPanelRows,
+                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                            : 0ull;
+          }
+#pragma unroll
+          for (int u = 0; u < kSlotsPerLane; ++u) {
+            const int k = sub + u * kLanesPerRow;
+            if (k < S) {
+              const double* q = slots + static_cast<long long>(k) * kPanelRows + r;
+              acc += bits[u] != kPending ? __longlong_as_double(static_cast<long long>(bits[u]))
+                                         : wait_pending(q, st);
+              __hip_atomic_store(sp + static_cast<long long>(k) * kPanelRows, kPending,
+                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+          }
+        }
+#pragma unroll
+        for (int off = kLanesPerRow / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kLanesPerRow);
+        sums[j] = acc;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kSubPanels; ++j)
+      if (g + kPanel * j < cnt && sub == 0) t_sh[g + kPanel * j] = sums[j];
     __syncthreads();
-    // ---- in-panel forward substitution, column by column; lane r owns row r
-    if (wave == 0) {
-      double acc = lane < cnt ? b - t_sh[lane] : 0.0;
-      double mine = 0.0;
-      double mnext = m_sh[lane];
-      for (int s = 0; s < cnt; ++s) {
-        const double mcol = mnext;
-        if (s + 1 < cnt) mnext = m_sh[(s + 1) * kPanel + lane];
-        const double xs = readlane_d(UNIT ? acc : acc * dinv, s);
-        if (lane == s) mine = xs;
-        if (lane > s) acc -= mcol * xs;
+    // ---- the sub-panels in order: forward substitution, lane l owns row k0 + l
+#pragma unroll
+    for (int j = 0; j < kSubPanels; ++j) {
+      const int k0 = kPanel * j;
+      if (k0 >= cnt) break;
+      const int ck = cnt - k0 < kPanel ? cnt - k0 : kPanel;
+      if (j > 0) {
+        // minus the entries on the first sub-panel, now solved
+        double acc = 0.0;
+#pragma unroll
+        for (int u = 0; u < kLocalPerLane; ++u) acc += lv[u] * x_sh[lc[u]];
+#pragma unroll
+        for (int off = kLanesPerRow / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kLanesPerRow);
+        if (g < ck && sub == 0) t_sh[k0 + g] += acc;
+        __syncthreads();
       }
-      if (lane < cnt) {
-        const long long i = lo + lane;
-        publish(out + i, mine);
-        if (scatter) scatter[scatter_perm[i]] = mine;
+      if (wave == 0) {
+        double acc = 0.0, dinv = 1.0;
+        if (lane < ck) {
+          acc = b_sh[k0 + lane] - t_sh[k0 + lane];
+          if (!UNIT) dinv = 1.0 / t.diag[lo + k0 + lane];
+        }
+        double mine = 0.0;
+        double mnext = m_sh[j][lane];
+        for (int s = 0; s < ck; ++s) {
+          const double mcol = mnext;
+          if (s + 1 < ck) mnext = m_sh[j][(s + 1) * kPanel + lane];
+          const double xs = readlane_d(UNIT ? acc : acc * dinv, s);
+          if (lane == s) mine = xs;
+          if (lane > s) acc -= mcol * xs;
+        }
+        if (lane < ck) {
+          const long long i = lo + k0 + lane;
+          if (j == 0) x_sh[lane] = mine;
+          publish(out + i, mine);
+          if (scatter) scatter[scatter_perm[i]] = mine;
+        }
       }
+      __syncthreads();  // x_sh feeds the next sub-panel; LDS and task_sh are reused
     }
-    __syncthreads();  // m_sh, t_sh and task_sh are reused by the next task
   }
 }
 

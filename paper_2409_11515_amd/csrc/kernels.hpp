@@ -80,19 +80,22 @@ constexpr long long kTileEntriesHost = 2048;
 // task t works on panel task_panel[t]; task_kind[t] = -1 for the whole panel,
 // 0..S-1 for slice k of its off-panel entries, S for the step that adds the
 // slices and finishes the panel (S = panel_split[panel]).
-constexpr int kPanel = 64;
+constexpr int kPanel = 64;       // rows of a sub-panel: one wave solves its triangle
+constexpr int kMaxSlicesDev = 64;  // most slices a heavy panel is cut into
+constexpr int kPanelRows = 128;  // rows of a panel: its sub-panels are solved in order by one block
 struct DevTri {
   int n = 0;
   const long long* off_rp = nullptr;
   const int* off_col = nullptr;
   const double* off_val = nullptr;
   const long long* in_rp = nullptr;
-  const int* in_col = nullptr;
+  const long long* in_split = nullptr;  // per row: first in-panel entry inside its own sub-panel
+  const int* in_col = nullptr;          // in-panel columns, relative to the panel's first row
   const double* in_val = nullptr;
   const double* diag = nullptr;  // nullptr: unit diagonal
   const int* pstart = nullptr;   // panel p holds rows [pstart[p], pstart[p+1])
   const int* panel_split = nullptr;
-  const int* panel_slot = nullptr;  // first partial-sum slot (64 doubles each) of a split panel
+  const int* panel_slot = nullptr;  // first partial-sum slot (kPanelRows doubles each) of a split panel
   double* partials = nullptr;       // kPending when idle
   int ntasks = 0;
   const int* task_panel = nullptr;

@@ -56,11 +56,13 @@ struct GraphKey {
 };
 
 // A strictly lower-triangular factor in solve order, cut into panels of at
-// most 64 consecutive rows, each split into the entries left of the panel
-// and the entries inside it, plus the order in which panels are handed out.
+// most kPanelRows consecutive rows, each split into the entries left of the
+// panel and the entries inside it, plus the order in which panels are handed
+// out. A row's in-panel entries list those on earlier 64-row sub-panels of
+// its panel first; in_split marks where the entries of its own sub-panel start.
 struct PanelCsr {
   int32_t n = 0;
-  std::vector<int64_t> off_rp, in_rp;
+  std::vector<int64_t> off_rp, in_rp, in_split;
   std::vector<int32_t> off_col, in_col;
   std::vector<double> off_val, in_val;
   std::vector<int32_t> pstart;  // panel p holds rows [pstart[p], pstart[p+1])
@@ -72,26 +74,49 @@ struct PanelCsr {
 
 // A panel whose rows hold more off-panel entries than this is cut into
 // slices (at most kMaxSlices) that separate blocks sum in parallel.
-constexpr int64_t kSliceEntries = 16384;
-constexpr int32_t kMaxSlices = 64;
+constexpr int64_t kSliceEntries = 4096;
+constexpr int32_t kMaxSlices = kMaxSlicesDev;
 
-// Panel boundaries: a panel closes when it holds 64 rows, or -- once it holds
-// at least kMinPanelRows -- before a row that needs nothing inside it. Such a
-// row usually opens an independent subtree of the elimination order (a new
-// leaf of the nested dissection); cutting there keeps independent subtrees in
-// different panels, so they are solved in parallel instead of as a chain.
-constexpr int32_t kMinPanelRows = 8;
+// Panel boundaries: a panel closes when it holds kPanelRows rows, or -- once
+// it holds at least kMinPanelRows -- before a row that needs nothing inside
+// it. Such a row usually opens an independent subtree of the elimination
+// order (a new leaf of the nested dissection); cutting there keeps independent
+// subtrees in different panels, so they are solved in parallel instead of as
+// a chain. A panel also closes at a 64-row boundary when the next row reads a
+// panel that is deeper in the dependency order than anything the open panel
+// reads: the panel's later sub-panels then never hold back its first one.
+// What remains inside a panel are chains (a dense separator block, mostly),
+// which one block solves sub-panel after sub-panel without waiting on others.
+constexpr int32_t kMinPanelRows = 4;
 
 std::vector<int32_t> cut_panels(const HostCsr& t) {
   std::vector<int32_t> ps{0};
+  std::vector<int32_t> pid(t.n, 0), plevel;  // panel of each closed row, level of each panel
   int32_t s = 0;
+  // 1 + the deepest closed panel that row e reads (columns left of the open panel)
+  auto ext_level = [&](int32_t e) {
+    int32_t lv = 0;
+    for (int64_t p = t.rowptr[e]; p < t.rowptr[e + 1]; ++p)
+      if (t.col[p] < s) lv = std::max(lv, plevel[pid[t.col[p]]] + 1);
+    return lv;
+  };
+  int32_t cur = t.n ? ext_level(0) : 0;
   for (int32_t e = 1; e < t.n; ++e) {
     bool needs_panel = false;
     for (int64_t p = t.rowptr[e]; p < t.rowptr[e + 1] && !needs_panel; ++p)
       needs_panel = t.col[p] >= s;
-    if (e - s >= kPanel || (!needs_panel && e - s >= kMinPanelRows)) {
+    const int32_t rows = e - s;
+    const int32_t lv = ext_level(e);
+    if (rows >= kPanelRows || (!needs_panel && rows >= kMinPanelRows) ||
+        (rows % kPanel == 0 && lv > cur)) {
+      const int32_t q = static_cast<int32_t>(plevel.size());
+      for (int32_t i = s; i < e; ++i) pid[i] = q;
+      plevel.push_back(cur);
       ps.push_back(e);
       s = e;
+      cur = ext_level(e);
+    } else {
+      cur = std::max(cur, lv);
     }
   }
   ps.push_back(t.n);
@@ -120,14 +145,24 @@ PanelCsr split_panels(const HostCsr& t) {
   s.levels = np ? 1 + *std::max_element(level.begin(), level.end()) : 0;
   s.off_rp.assign(t.n + 1, 0);
   s.in_rp.assign(t.n + 1, 0);
+  s.in_split.assign(t.n, 0);
   for (int32_t i = 0; i < t.n; ++i) {
     const int32_t lo = s.pstart[pid[i]];
+    const int32_t sub0 = lo + (i - lo) / kPanel * kPanel;  // first row of i's sub-panel
     for (int64_t p = t.rowptr[i]; p < t.rowptr[i + 1]; ++p) {
       const int32_t j = t.col[p];
       if (j < lo) {
         s.off_col.push_back(j);
         s.off_val.push_back(t.val[p]);
-      } else {
+      } else if (j < sub0) {
+        s.in_col.push_back(j - lo);
+        s.in_val.push_back(t.val[p]);
+      }
+    }
+    s.in_split[i] = static_cast<int64_t>(s.in_col.size());
+    for (int64_t p = t.rowptr[i]; p < t.rowptr[i + 1]; ++p) {
+      const int32_t j = t.col[p];
+      if (j >= sub0) {
         s.in_col.push_back(j - lo);
         s.in_val.push_back(t.val[p]);
       }
@@ -252,7 +287,7 @@ struct cond_plan {
   // offsets into the workspace
   struct {
     size_t a_rp, a_col, a_val, at_rp, at_col, at_val, a_tiles, at_tiles;
-    size_t tri[4][12];
+    size_t tri[4][13];
     size_t u_diag, u_diag_rev, row_perm, rev, scat_s, scat_r;
     size_t vec[10];
     size_t parts[4];
@@ -290,9 +325,10 @@ void plan_layout(cond_plan* p) {
       p->o.tri[f][6] = L.take(t.pstart.size() * 4);
       p->o.tri[f][7] = L.take(t.panel_split.size() * 4);
       p->o.tri[f][8] = L.take(t.panel_slot.size() * 4);
-      p->o.tri[f][9] = L.take(static_cast<size_t>(t.nslots) * kPanel * 8);
+      p->o.tri[f][9] = L.take(static_cast<size_t>(t.nslots) * kPanelRows * 8);
       p->o.tri[f][10] = L.take(t.task_panel.size() * 4);
       p->o.tri[f][11] = L.take(t.task_kind.size() * 4);
+      p->o.tri[f][12] = L.take(static_cast<size_t>(n) * 8);
     }
     p->o.u_diag = L.take(n * 8);
     p->o.u_diag_rev = L.take(n * 8);
@@ -362,12 +398,14 @@ int upload_tri(cond_plan* p, const PanelCsr& t, const size_t* off, const double*
   if ((st = upload(p, off[8], t.panel_slot.data(), t.panel_slot.size() * 4))) return st;
   if ((st = upload(p, off[10], t.task_panel.data(), t.task_panel.size() * 4))) return st;
   if ((st = upload(p, off[11], t.task_kind.data(), t.task_kind.size() * 4))) return st;
-  if (t.nslots > 0) launch_fill(t.nslots * kPanel, at_off<double>(p, off[9]), kPending, p->stream);
+  if ((st = upload(p, off[12], t.in_split.data(), static_cast<size_t>(t.n) * 8))) return st;
+  if (t.nslots > 0) launch_fill(t.nslots * kPanelRows, at_off<double>(p, off[9]), kPending, p->stream);
   out.n = t.n;
   out.off_rp = at_off<long long>(p, off[0]);
   out.off_col = at_off<int>(p, off[1]);
   out.off_val = at_off<double>(p, off[2]);
   out.in_rp = at_off<long long>(p, off[3]);
+  out.in_split = at_off<long long>(p, off[12]);
   out.in_col = at_off<int>(p, off[4]);
   out.in_val = at_off<double>(p, off[5]);
   out.diag = diag_dev;
