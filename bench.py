@@ -247,6 +247,25 @@ def make_matrix(w):
     return stokes2d(w["side"], w["side"], seed=w["seed"])
 
 
+def pmc_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter runs
+    (profiles/pmc_traffic.json), or None when they were taken on another
+    version of the kernel source or not for this workload."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    src = os.path.join(ROOT, "paper_2409_11515_amd", "csrc", "kernels.hip")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec.get("kernels_source_sha256"):
+            return None
+    entry = rec.get("workloads", {}).get(workload, {}).get(kernel)
+    return entry["traffic_bytes"] if entry else None
+
+
 def golden_kappa(w):
     if not w["golden"]:
         return None
@@ -408,8 +427,8 @@ def main():
         "run_ms": {"sigma_max": res["ms_max"], "sigma_min": res["ms_min"]},
         "setup_s": setup_s,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
-                     "avg_us": avg_ms * 1e3, "alg_bytes_per_launch": byts},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": pmc_traffic(args.workload, dom),
+                     "kernel": dom, "avg_us": avg_ms * 1e3, "alg_bytes_per_launch": byts},
         "spmv": spmv,
         "kernels": kernels,
     }
