@@ -47,7 +47,7 @@ WORKLOADS = {
     # 64 matrices, sides U{51..401}, perturbed copies of one base field, 8 starts each
     "c4batch": dict(kind="batch", count=64, side_range=(51, 401), min_route=False),
     # learned warm start: trained on small grids, tested on held-out 201x201 systems
-    "c5warm": dict(kind="warm", train_side=25, test_side=201, min_route=True),
+    "c5warm": dict(kind="warm", train=((51, 300), (101, 150)), test_side=201, min_route=True),
 }
 
 
@@ -55,10 +55,11 @@ def bench_warm(w, args):
     """Warm-started vs plain sigma_min runs on held-out systems.
 
     Training: plain sigma_min runs label the maximisers of ||A^-1 x||/||x|| on
-    seeded training matrices (seeds 10000+), the network is fitted on the
-    device. Test: held-out seeds 20000+; per matrix one sigma_max run, the
-    plain (random-start) sigma_min run, and the warm-started run with its
-    random-start check and fallback; every run stops by the same rule."""
+    seeded training matrices of the sides in w["train"] (seeds 10000+), and
+    the network is fitted on the device. Test: held-out seeds 20000+ at
+    w["test_side"]; per matrix one sigma_max run, the plain (random-start)
+    sigma_min run, and the warm-started run with its random-start check and
+    fallback; every run stops by the same rule."""
     from concurrent.futures import ThreadPoolExecutor
 
     import torch
@@ -69,7 +70,6 @@ def bench_warm(w, args):
 
     opts = dict(max_iter=args.max_iter, stop_rtol=args.stop_rtol, stop_window=args.stop_window)
     lab_opts = dict(max_iter=4000, stop_rtol=1e-7, stop_window=50)
-    ts, ntr = w["train_side"], args.train_count
     t0 = time.perf_counter()
 
     def build(seed, side):
@@ -77,28 +77,40 @@ def bench_warm(w, args):
         a = hydromech2d(side, log_eta=le, log_k=lk)
         return a, np.stack([le, lk]), pa.Plan(a.n, a.rowptr, a.col, a.val)
 
-    fields, labels = [], []
-    with ThreadPoolExecutor(max_workers=8) as ex:
-        for i, (a, f, plan) in enumerate(ex.map(lambda s: build(s, ts), range(10000, 10000 + ntr))):
-            plan.bind()
-            u, _ = label(plan, torch.as_tensor(start_vector(a.n, 10000 + i), device="cuda"),
-                         **lab_opts)
-            plan.close()
-            fields.append(f)
-            labels.append(u)
-            if (i + 1) % 100 == 0:
-                print(f"[bench] labelled {i + 1}/{ntr} ({time.perf_counter() - t0:.0f}s)",
-                      file=sys.stderr, flush=True)
+    sets = []
+    seed0 = 10000
+    train = [] if args.params_in else w["train"]
+    for side, count in train:
+        count = max(16, int(round(count * args.train_scale)))
+        fields, labels = [], []
+        with ThreadPoolExecutor(max_workers=8) as ex:
+            for i, (a, f, plan) in enumerate(ex.map(lambda s: build(s, side),
+                                                    range(seed0, seed0 + count))):
+                plan.bind()
+                u, _ = label(plan, torch.as_tensor(start_vector(a.n, seed0 + i), device="cuda"),
+                             **lab_opts)
+                plan.close()
+                fields.append(f)
+                labels.append(u)
+                if (i + 1) % 50 == 0:
+                    print(f"[bench] labelled {i + 1}/{count} at side {side} "
+                          f"({time.perf_counter() - t0:.0f}s)", file=sys.stderr, flush=True)
+        seed0 += count
+        sets.append((torch.as_tensor(np.asarray(fields), device="cuda").contiguous(),
+                     torch.stack(labels).contiguous()))
     label_s = time.perf_counter() - t0
-    ws = WarmStart(16, w["test_side"], seed=0)
+    ws = WarmStart(16, max(w["test_side"], max(s for s, _ in w["train"])), seed=0,
+                   params=np.load(args.params_in) if args.params_in else None)
     t0 = time.perf_counter()
-    hist = ws.fit(torch.as_tensor(np.asarray(fields), device="cuda").contiguous(),
-                  torch.stack(labels).contiguous(), epochs=args.epochs, batch=16, lr=2e-3,
-                  lr_final=1e-4)
+    hist = [float("nan")]
+    if sets:
+        hist = ws.fit_sets(sets, epochs=args.epochs, batch=16, lr=2e-3, lr_final=1e-4)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
-    print(f"[bench] trained {args.epochs} epochs in {train_s:.1f}s, loss {hist[0]:.3f} -> "
-          f"{hist[-1]:.3f}", file=sys.stderr, flush=True)
+    if args.params_out:
+        np.save(args.params_out, ws.params())
+    print(f"[bench] trained {args.epochs if sets else 0} epochs in {train_s:.1f}s, loss "
+          f"{hist[0]:.3f} -> {hist[-1]:.3f}", file=sys.stderr, flush=True)
 
     side = w["test_side"]
     rows = []
@@ -114,25 +126,45 @@ def bench_warm(w, args):
             ws.predict(ft)  # first call warms the kernels
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
-            ws.predict(ft)
+            xw = ws.predict(ft)[0]
             e1.record()
             torch.cuda.synchronize()
             fwd_ms.append(e0.elapsed_time(e1))
             cold = plan.run(xr, xr, **opts)
-            warm = ws.run(plan, ft, xr, **opts)
+            warm = ws.run(plan, ft, xr, warm_alpha=args.warm_alpha, **opts)
+            # reference: both starts run long without the stop rule; their traces
+            # give the updates each needs to come within 1e-3 of the best value
+            ref_c = plan.run(None, xr, trace=True, x_best=True, max_iter=args.ref_iters)
+            ref_w = plan.run(None, xw, trace=True, max_iter=args.ref_iters, alpha=args.warm_alpha)
+            best = max(ref_c["trace_min"][-1], ref_w["trace_min"][-1],
+                       1.0 / cold["sigma_min"], 1.0 / warm["sigma_min"])
+            ub = ref_c["x_best_min"]
+            overlap = float(abs(torch.dot(xw, ub)) / (xw.norm() * ub.norm()))
+
+            def upd(tr):
+                hit = np.nonzero(tr >= (1 - 1e-3) * best)[0]
+                return int(hit[0]) + 1 if hit.size else None
+
+            k_ref = cold["sigma_max"] * best
             k_cold = cold["kappa"]
             k_warm = cold["sigma_max"] / warm["sigma_min"]
             rows.append(dict(seed=seed, cold_iters=cold["iters_min"], cold_ms=cold["ms_min"],
                              warm_iters=warm["iters_warm"], warm_total_iters=warm["iters_total"],
                              warm_ms=warm["ms_min"], fallback=warm["fallback"],
-                             kappa_plain=k_cold, kappa_warm=k_warm,
-                             kappa_rel_diff=abs(k_warm - k_cold) / k_cold,
+                             kappa_ref=k_ref, kappa_plain=k_cold, kappa_warm=k_warm,
+                             err_plain=(k_ref - k_cold) / k_ref, err_warm=(k_ref - k_warm) / k_ref,
+                             kappa_rel_diff=abs(k_warm - k_cold) / k_cold, overlap=overlap,
+                             updates_to_1e3_plain=upd(ref_c["trace_min"]),
+                             updates_to_1e3_warm=upd(ref_w["trace_min"]),
                              sigma_max_ms=cold["ms_max"]))
             plan.close()
-            print(f"[bench] test {i + 1}/{args.test_count}: cold {cold['iters_min']} updates "
-                  f"{cold['ms_min']:.0f} ms, warm {warm['iters_warm']}+check "
-                  f"{warm['ms_min']:.0f} ms, fallback {warm['fallback']}, "
-                  f"kappa diff {rows[-1]['kappa_rel_diff']:.1e}", file=sys.stderr, flush=True)
+            r_ = rows[-1]
+            print(f"[bench] test {i + 1}/{args.test_count}: stop rule: plain {cold['iters_min']} "
+                  f"updates {cold['ms_min']:.0f} ms err {r_['err_plain']:.1e}; warm "
+                  f"{warm['iters_warm']}+check {warm['ms_min']:.0f} ms err {r_['err_warm']:.1e} "
+                  f"fallback {warm['fallback']}; to 1e-3 of the best: plain "
+                  f"{r_['updates_to_1e3_plain']} warm {r_['updates_to_1e3_warm']}; overlap "
+                  f"{overlap:.3f}", file=sys.stderr, flush=True)
     ws.close()
     cold_ms = np.array([r["cold_ms"] for r in rows])
     warm_ms = np.array([r["warm_ms"] for r in rows])
@@ -140,6 +172,8 @@ def bench_warm(w, args):
     # forward pass: 2 * 9 * sum(cin * cout) FLOP per node with the true channel counts
     flops = 2 * 9 * (2 * 64 + 64 * 64 + 64 * 64 + 64 * 6) * side * side
     fwd = float(np.median(fwd_ms))
+    train_desc = " + ".join(f"{max(16, int(round(c * args.train_scale)))} {s}x{s}"
+                            for s, c in w["train"])
     out = {
         "metric": "time-to-kappa (1e-3 rel) per matrix, warm-started vs plain",
         "value": float(np.mean(smax_ms + warm_ms)) / 1e3 + fwd / 1e3, "unit": "s", "n_gpus": 1,
@@ -148,13 +182,20 @@ def bench_warm(w, args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f64 (network bf16/f32)",
         "data": "synthetic",
         "config": {"workload": f"c5warm: held-out {side}x{side} hydro-mechanical systems "
-                               f"(seeds 20000+), network trained on {ntr} {ts}x{ts} systems",
+                               f"(seeds 20000+), network trained on {train_desc} systems",
                    "epochs": args.epochs, "stop_rtol": args.stop_rtol,
                    "stop_window": args.stop_window, "parallelism": "single GPU"},
         "plain_s": float(np.mean(smax_ms + cold_ms)) / 1e3,
         "speedup_sigma_min": float(np.sum(cold_ms) / np.sum(warm_ms)),
         "fallback_rate": float(np.mean([r["fallback"] for r in rows])),
         "kappa_rel_diff_max": float(max(r["kappa_rel_diff"] for r in rows)),
+        "kappa_err_max": {"plain": float(max(r["err_plain"] for r in rows)),
+                          "warm": float(max(r["err_warm"] for r in rows))},
+        "updates_to_1e3_median": {
+            k: float(np.median([r[f"updates_to_1e3_{k}"] if r[f"updates_to_1e3_{k}"] is not None
+                                else args.ref_iters + 1 for r in rows])) for k in ("plain", "warm")},
+        "warm_alpha": args.warm_alpha,
+        "overlap_median": float(np.median([r["overlap"] for r in rows])),
         "updates_median": {"plain": float(np.median([r["cold_iters"] for r in rows])),
                            "warm": float(np.median([r["warm_iters"] for r in rows])),
                            "warm_with_check": float(np.median([r["warm_total_iters"]
@@ -167,75 +208,6 @@ def bench_warm(w, args):
         "label_s": label_s, "train_s": train_s, "loss": [hist[0], hist[-1]],
         "tests": rows,
     }
-    print(json.dumps(out), flush=True)
-
-
-def bench_batch(w, args):
-    """Batched multi-start sigma_max run vs a loop of plain runs, same starts and options."""
-    import torch
-
-    import paper_2409_11515_amd as pa
-    from synth import hm_batch_specs, hydromech2d, start_block
-
-    t0 = time.perf_counter()
-    specs = hm_batch_specs(count=w["count"], side_range=w["side_range"])
-    mats = [hydromech2d(s, log_eta=le, log_k=lk) for s, le, lk in specs]
-    starts = [start_block(m.n, 8, 7000 + i) for i, m in enumerate(mats)]
-    gen_s = time.perf_counter() - t0
-    nrows = sum(m.n for m in mats)
-    nnz = sum(m.nnz for m in mats)
-    print(f"[bench] batch: {len(mats)} matrices, rows {nrows}, nnz {nnz} ({gen_s:.0f}s)",
-          file=sys.stderr, flush=True)
-    opts = dict(max_iter=args.max_iter, stop_rtol=args.stop_rtol, stop_window=args.stop_window)
-    t0 = time.perf_counter()
-    b = pa.Batch([(m.n, m.rowptr, m.col, m.val) for m in mats], **opts).bind()
-    torch.cuda.synchronize()
-    setup_s = time.perf_counter() - t0
-    x0 = torch.as_tensor(pa.interleave_starts(starts), device="cuda")
-    for _ in range(args.warmup):
-        b.run(x0)
-    times = []
-    for k in range(args.steps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        rb = b.run(x0)
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
-        print(f"[bench] batched step {k}: {times[-1]*1e3:.1f} ms", file=sys.stderr, flush=True)
-    batched_s = float(np.mean(times))
-    # plain path: one plan per matrix, one run per start
-    t_plain = 0.0
-    max_rel = 0.0
-    plain_iters = 0
-    for i, m in enumerate(mats):
-        p = pa.Plan(m.n, m.rowptr, m.col, m.val, sigma_min_method=pa.COND_MIN_NONE, **opts).bind()
-        xs = [torch.as_tensor(starts[i][k], device="cuda") for k in range(8)]
-        p.run(xs[0])  # warm the graph
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        best = [p.run(xs[k]) for k in range(8)]
-        torch.cuda.synchronize()
-        t_plain += time.perf_counter() - t0
-        plain_iters += sum(r["iters_max"] for r in best)
-        smax = max(r["sigma_max"] for r in best)
-        max_rel = max(max_rel, abs(smax - rb["sigma_max"][i]) / smax)
-        p.close()
-        if i % 16 == 15:
-            print(f"[bench] plain loop: {i+1} matrices", file=sys.stderr, flush=True)
-    b_iters = int(rb["pair_iters"].sum())
-    out = {
-        "metric": "time-to-kappa (1e-3 rel) per matrix + SpMV HBM GB/s",
-        "value": batched_s / len(mats), "unit": "s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": batched_s * 1e3, "higher_is_better": False,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "c4batch: 64 hydro-mechanical matrices, sides U{51..401}, "
-                               "8 starts each, sigma_max run", "rows": nrows, "nnz": nnz,
-                   "tile_rows": b.tile_rows, "grid": b.grid, "parallelism": "single GPU"},
-        "batched_s": batched_s, "plain_loop_s": t_plain, "speedup": t_plain / batched_s,
-        "pair_updates": {"batched": b_iters, "plain": plain_iters},
-        "sigma_max_rel_diff_max": max_rel, "setup_s": setup_s,
-    }
-    b.close()
     print(json.dumps(out), flush=True)
 
 
@@ -333,9 +305,15 @@ def main():
     ap.add_argument("--stop-rtol", type=float, default=1e-6)
     ap.add_argument("--stop-window", type=int, default=25)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--train-count", type=int, default=600, help="c5warm: training matrices")
+    ap.add_argument("--train-scale", type=float, default=1.0,
+                    help="c5warm: multiplies the training-set sizes")
     ap.add_argument("--test-count", type=int, default=8, help="c5warm: held-out matrices")
-    ap.add_argument("--epochs", type=int, default=200, help="c5warm: training epochs")
+    ap.add_argument("--epochs", type=int, default=60, help="c5warm: training epochs")
+    ap.add_argument("--params-in", default=None, help="c5warm: trained parameters (.npy), no training")
+    ap.add_argument("--params-out", default=None, help="c5warm: save the trained parameters (.npy)")
+    ap.add_argument("--warm-alpha", type=float, default=1e-2, help="c5warm: alpha of the warm run")
+    ap.add_argument("--ref-iters", type=int, default=1500,
+                    help="c5warm: updates of the long reference runs without the stop rule")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "

@@ -71,12 +71,46 @@ class WarmStart:
                 log(f"epoch {ep + 1}/{epochs} loss {history[-1]:.4f}")
         return history
 
+    def fit_sets(self, sets, epochs: int, batch: int, lr: float = 1e-3, seed: int = 0,
+                 lr_final: float | None = None, log=None) -> list:
+        """Adam over training sets of different sides, [(fields, labels), ...]
+        as in fit; every epoch visits the mini-batches of all sets in one
+        shuffled order (each mini-batch holds one side)."""
+        import torch
+
+        rng = np.random.default_rng(seed)
+        steps_per_epoch = sum(max(1, int(f.shape[0]) // batch) for f, _ in sets)
+        steps = epochs * steps_per_epoch
+        decay = 1.0 if lr_final is None else (lr_final / lr) ** (1.0 / max(1, steps - 1))
+        rate = lr
+        history = []
+        for ep in range(epochs):
+            work = []
+            for k, (f, _) in enumerate(sets):
+                order = rng.permutation(int(f.shape[0]))
+                work += [(k, order[i:i + batch]) for i in range(0, len(order) - batch + 1, batch)]
+            tot = 0.0
+            for w in rng.permutation(len(work)):
+                k, idx = work[w]
+                f, lab = sets[k]
+                ti = torch.as_tensor(idx, device=f.device)
+                tot += self.net.train_step(f.index_select(0, ti).contiguous(),
+                                           lab.index_select(0, ti).contiguous(), rate)
+                rate *= decay
+            history.append(tot / max(len(work), 1))
+            if log:
+                log(f"epoch {ep + 1}/{epochs} loss {history[-1]:.4f}")
+        return history
+
     def predict(self, fields):
         return self.net.predict(fields)
 
-    def run(self, plan: Plan, fields, x0_random, **opts) -> dict:
+    def run(self, plan: Plan, fields, x0_random, warm_alpha=None, **opts) -> dict:
         """The sigma_min run from the predicted start, with a random start as
-        the fallback. fields: CUDA float64 [1, 2, s-1, s-1].
+        the fallback. fields: CUDA float64 [1, 2, s-1, s-1]. warm_alpha, if
+        given, is the step size of the run from the predicted start (a start
+        close to the maximiser survives only steps small against its entries);
+        the random-start runs use the options as given.
 
         1. Run from the predicted start until the stop rule (or max_iter).
         2. Give the random start the same number of updates (the check).
@@ -86,7 +120,7 @@ class WarmStart:
         Returns sigma_min, the updates and device milliseconds spent in all
         runs together, and whether the fallback was taken."""
         x_warm = self.predict(fields)[0]
-        warm = plan.run(None, x_warm, **opts)
+        warm = plan.run(None, x_warm, **({**opts, "alpha": warm_alpha} if warm_alpha else opts))
         t = max(1, int(warm["iters_min"]))
         check = plan.run(None, x0_random, **{**opts, "max_iter": t})
         out = dict(sigma_min=warm["sigma_min"], iters_warm=t, iters_total=t + check["iters_min"],
