@@ -75,7 +75,8 @@ struct cond_batch {
   hipGraphExec_t exec = nullptr;
   BatchKey key;
   struct {
-    size_t a_rp, a_col, a_val, at_rp, at_col, at_val, tiles, tile_mat, mat_tile0;
+    size_t a_rp, a_col, a_val, at_rp, at_col, at_val, tiles, tile_mat, mat_tile0, live_mat,
+        live_pref;
     size_t vec[7], parts[4], pairs, g;
   } o{};
 };
@@ -122,6 +123,7 @@ AdamParams bparams(const cond_opts_t& o) {
 
 void enqueue_batch_iteration(cond_batch* b, const BatchArgs& a, const AdamParams& p) {
   hipStream_t s = b->stream;
+  batch_launch_live(a, s);  // drop the tiles of matrices whose starts have all stopped
   batch_launch_normalise(a, b->grid, s);
   batch_launch_spmm(a, 0, b->grid, s);
   batch_launch_reduce(a, 1, p, s);
@@ -189,6 +191,8 @@ int cond_batch_create(const cond_csr_t* As, int32_t count, const cond_opts_t* o,
   b->o.tiles = take(off, (b->max_tiles + 1) * 8);
   b->o.tile_mat = take(off, b->max_tiles * 4);
   b->o.mat_tile0 = take(off, (count + 1) * 4);
+  b->o.live_mat = take(off, static_cast<size_t>(count) * 4);
+  b->o.live_pref = take(off, (count + 1) * 4);
   for (int k = 0; k < 7; ++k) b->o.vec[k] = take(off, n * K * 8);
   for (int k = 0; k < 4; ++k) b->o.parts[k] = take(off, b->max_tiles * K * 8);
   b->o.pairs = take(off, static_cast<size_t>(count) * K * sizeof(BatchPair));
@@ -257,6 +261,8 @@ int cond_batch_bind(cond_batch_t* b, void* workspace, size_t bytes, void* stream
   a.tiles = reinterpret_cast<const long long*>(b->ws + b->o.tiles);
   a.tile_mat = reinterpret_cast<const int*>(b->ws + b->o.tile_mat);
   a.mat_tile0 = reinterpret_cast<const int*>(b->ws + b->o.mat_tile0);
+  a.live_mat = reinterpret_cast<int*>(b->ws + b->o.live_mat);
+  a.live_pref = reinterpret_cast<int*>(b->ws + b->o.live_pref);
   a.a_rowptr = reinterpret_cast<const int*>(b->ws + b->o.a_rp);
   a.a_col = reinterpret_cast<const int*>(b->ws + b->o.a_col);
   a.a_val = reinterpret_cast<const double*>(b->ws + b->o.a_val);
@@ -272,6 +278,9 @@ int cond_batch_bind(cond_batch_t* b, void* workspace, size_t bytes, void* stream
   a.pairs = reinterpret_cast<BatchPair*>(b->ws + b->o.pairs);
   a.g = reinterpret_cast<BatchGlobal*>(b->ws + b->o.g);
   BCHK(hipMemsetAsync(b->ws + b->o.vec[0], 0, b->nrows * kBatchK * 8, b->stream));
+  // every pair running: the autotuner's products cover every tile
+  BCHK(hipMemsetAsync(b->ws + b->o.pairs, 0, static_cast<size_t>(b->nmat) * kBatchK * sizeof(BatchPair),
+                      b->stream));
   BCHK(hipStreamSynchronize(b->stream));
   // Autotuner: time the A-product for each (tile rows, grid) candidate on
   // this batch and keep the fastest, unless the caller fixed the schedule.
@@ -282,6 +291,7 @@ int cond_batch_bind(cond_batch_t* b, void* workspace, size_t bytes, void* stream
       if (tile_rows && r != tile_rows) continue;
       make_schedule(b, r);
       if ((st = upload_schedule(b))) return st;
+      batch_launch_live(a, b->stream);
       for (int g : kGridCandidates) {
         if (grid && g != grid) continue;
         b->grid = g;

@@ -28,6 +28,7 @@ struct BatchPair {
 struct BatchGlobal {
   long long t_done;
   double b1t, b2t;
+  int nlive;  // tiles of the matrices that still have a running start
 };
 
 struct BatchArgs {
@@ -36,6 +37,8 @@ struct BatchArgs {
   const long long* tiles = nullptr;  // tile t = rows [tiles[t], tiles[t+1]) of one matrix
   const int* tile_mat = nullptr;     // matrix of tile t
   const int* mat_tile0 = nullptr;    // tiles of matrix m: [mat_tile0[m], mat_tile0[m+1])
+  int* live_mat = nullptr;           // matrices with a running start, in order
+  int* live_pref = nullptr;          // their tiles: live index u in [live_pref[j], live_pref[j+1])
   const int* a_rowptr = nullptr;     // block-diagonal A (global row and column indices)
   const int* a_col = nullptr;
   const double* a_val = nullptr;
@@ -51,6 +54,7 @@ struct BatchArgs {
 };
 
 void batch_launch_init(const BatchArgs& a, const double* x0, int grid, hipStream_t s);
+void batch_launch_live(const BatchArgs& a, hipStream_t s);
 void batch_launch_reduce(const BatchArgs& a, int mode, const AdamParams& p, hipStream_t s);
 void batch_launch_normalise(const BatchArgs& a, int grid, hipStream_t s);
 void batch_launch_spmm(const BatchArgs& a, int transpose, int grid, hipStream_t s);

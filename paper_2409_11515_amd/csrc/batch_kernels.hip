@@ -49,6 +49,31 @@ __device__ __forceinline__ void tile_range(int ntiles, long long& t0, long long&
   t1 = static_cast<long long>(ntiles) * (lb + 1) / g;
 }
 
+// The tiles of the matrices that still have a running start ("live" tiles),
+// numbered u = 0..nlive-1 in matrix order, are split over the blocks in
+// contiguous, XCD-aware ranges; live tile u maps to tile
+// mat_tile0[live_mat[j]] + (u - live_pref[j]) for the j with
+// live_pref[j] <= u < live_pref[j+1]. Once every start of a matrix has
+// stopped, no element kernel visits its tiles again.
+struct LiveTiles {
+  long long u, u1;
+  int j;
+  __device__ __forceinline__ void begin(const BatchArgs& a) {
+    const int n = a.g->nlive;
+    const int b = blockIdx.x, g = gridDim.x;
+    const int lb = (g % 8 == 0) ? (b % 8) * (g / 8) + b / 8 : b;
+    u = static_cast<long long>(n) * lb / g;
+    u1 = static_cast<long long>(n) * (lb + 1) / g;
+    j = 0;
+  }
+  // the tile of live index u (advancing j), or -1 past the block's range
+  __device__ __forceinline__ long long tile(const BatchArgs& a) {
+    if (u >= u1) return -1;
+    while (u >= a.live_pref[j + 1]) ++j;
+    return a.mat_tile0[a.live_mat[j]] + (u - a.live_pref[j]);
+  }
+};
+
 // Per-tile partial sums of K values, lane k of each 8-lane group owning start
 // k (K == 8). Reduces the block's per-start accumulators into slot rows.
 template <int K>
@@ -88,6 +113,26 @@ __global__ __launch_bounds__(kB) void b_init_k(BatchArgs a, const double* __rest
     a.g->b1t = 1.0;
     a.g->b2t = 1.0;
   }
+}
+
+// ------------------------------------------------------------ live tiles
+// One block: matrices with a running start, and the prefix of their tile counts.
+template <int K>
+__global__ __launch_bounds__(kB) void b_live_k(BatchArgs a) {
+  if (threadIdx.x != 0) return;
+  int j = 0, u = 0;
+  for (int m = 0; m < a.nmat; ++m) {
+    bool run = false;
+    for (int k = 0; k < K; ++k) run |= !a.pairs[static_cast<long long>(m) * K + k].stopped;
+    if (run) {
+      a.live_mat[j] = m;
+      a.live_pref[j] = u;
+      u += a.mat_tile0[m + 1] - a.mat_tile0[m];
+      ++j;
+    }
+  }
+  a.live_pref[j] = u;
+  a.g->nlive = u;
 }
 
 // --------------------------------------------------------- per-matrix reduce
@@ -170,10 +215,10 @@ __global__ __launch_bounds__(kB) void b_reduce_k(BatchArgs a, int mode, AdamPara
 template <int K>
 __global__ __launch_bounds__(kB) void b_normalise_k(BatchArgs a) {
 #pragma clang fp contract(off)
-  long long t0, t1;
-  tile_range(a.ntiles, t0, t1);
+  LiveTiles lt;
+  lt.begin(a);
   const int k = threadIdx.x % K;
-  for (long long t = t0; t < t1; ++t) {
+  for (long long t = lt.tile(a); t >= 0; ++lt.u, t = lt.tile(a)) {
     const int mat = a.tile_mat[t];
     const BatchPair& q = a.pairs[static_cast<long long>(mat) * K + k];
     const long long r0 = a.tiles[t], r1 = a.tiles[t + 1];
@@ -191,14 +236,14 @@ __global__ __launch_bounds__(kB) void b_normalise_k(BatchArgs a) {
 }
 
 // -------------------------------------------------------------------- spmm
-// Y = M X for K interleaved starts. Each tile is walked in chunks of 32 rows:
-// thread t handles (entry t/K, start t%K), so the K threads of an entry read
-// the same col/val (one transaction) and 64 contiguous bytes of X, and all
-// products of the chunk are in flight at once; they are parked in LDS and
-// thread (row, start) adds up its row. Starts that have stopped are skipped,
-// and a tile whose matrix has no running start is skipped entirely.
+// Y = M X for K interleaved starts. Thread t of a block takes row t / K of a
+// 32-row chunk and start t % K and walks that row: the K threads of a row
+// read the same column index and value (one transaction for all of them)
+// and K contiguous entries of X (64 bytes), so one read of the matrix serves
+// all starts, with no staging and no barrier inside a tile. Starts that have
+// stopped are skipped, and a tile whose matrix has no running start is
+// skipped entirely.
 constexpr int kChunkRowsB = kB / 8;  // 32 rows x 8 starts
-constexpr int kChunkCap = 256;       // entries staged per chunk
 
 template <int K>
 __global__ __launch_bounds__(kB) void b_spmm_k(BatchArgs a, const int* __restrict__ rowptr,
@@ -206,51 +251,36 @@ __global__ __launch_bounds__(kB) void b_spmm_k(BatchArgs a, const int* __restric
                                                const double* __restrict__ val,
                                                const double* __restrict__ x, double* __restrict__ y,
                                                double* __restrict__ parts) {
-  __shared__ double prod[kChunkCap * K];
-  __shared__ int rp_sh[kChunkRowsB + 1];
-  __shared__ int run_sh[K];
-  long long t0, t1;
-  tile_range(a.ntiles, t0, t1);
+#pragma clang fp contract(off)  // products rounded, then added in entry order, as in the plain SpMV
+  LiveTiles lt;
+  lt.begin(a);
   const int k = threadIdx.x % K;
   const int rl = threadIdx.x / K;  // row of this thread inside a chunk
-  for (long long t = t0; t < t1; ++t) {
+  for (long long t = lt.tile(a); t >= 0; ++lt.u, t = lt.tile(a)) {
     const int mat = a.tile_mat[t];
-    if (threadIdx.x < K) run_sh[threadIdx.x] = !a.pairs[static_cast<long long>(mat) * K + threadIdx.x].stopped;
-    __syncthreads();
-    int any = 0;
-#pragma unroll
-    for (int u = 0; u < K; ++u) any |= run_sh[u];
-    const bool mine = run_sh[k] != 0;
+    const bool mine = !a.pairs[static_cast<long long>(mat) * K + k].stopped;
     const long long r0 = a.tiles[t], r1 = a.tiles[t + 1];
     double sq = 0.0;
-    if (any) {
-      for (long long c0 = r0; c0 < r1; c0 += kChunkRowsB) {
-        const int cnt = static_cast<int>(r1 - c0 < kChunkRowsB ? r1 - c0 : kChunkRowsB);
-        if (threadIdx.x <= cnt) rp_sh[threadIdx.x] = rowptr[c0 + threadIdx.x];
-        __syncthreads();
-        const int e0 = rp_sh[0], ne = rp_sh[cnt] - e0;
-        if (ne <= kChunkCap) {
-          for (int idx = threadIdx.x; idx < ne * K; idx += kB) {
-            const int e = e0 + idx / K;
-            if (mine) prod[idx] = val[e] * x[static_cast<long long>(col[e]) * K + k];
-          }
-          __syncthreads();
-          if (rl < cnt && mine) {
-            const int a0 = rp_sh[rl] - e0, a1 = rp_sh[rl + 1] - e0;
-            double acc = 0.0;
-            for (int e = a0; e < a1; ++e) acc += prod[e * K + k];
-            y[(c0 + rl) * K + k] = acc;
-            sq += acc * acc;
-          }
-        } else if (rl < cnt && mine) {
-          // a chunk with long rows: each (row, start) thread walks its row
-          const int p0 = rp_sh[rl], p1 = rp_sh[rl + 1];
-          double acc = 0.0;
-          for (int q = p0; q < p1; ++q) acc += val[q] * x[static_cast<long long>(col[q]) * K + k];
-          y[(c0 + rl) * K + k] = acc;
-          sq += acc * acc;
+    if (mine) {
+      for (long long r = r0 + rl; r < r1; r += kChunkRowsB) {
+        const int p0 = rowptr[r], p1 = rowptr[r + 1];
+        double acc = 0.0;
+        int q = p0;
+        for (; q + 4 <= p1; q += 4) {
+          const int c0 = col[q], c1 = col[q + 1], c2 = col[q + 2], c3 = col[q + 3];
+          const double v0 = val[q], v1 = val[q + 1], v2 = val[q + 2], v3 = val[q + 3];
+          const double x0 = x[static_cast<long long>(c0) * K + k];
+          const double x1 = x[static_cast<long long>(c1) * K + k];
+          const double x2 = x[static_cast<long long>(c2) * K + k];
+          const double x3 = x[static_cast<long long>(c3) * K + k];
+          acc += v0 * x0;
+          acc += v1 * x1;
+          acc += v2 * x2;
+          acc += v3 * x3;
         }
-        __syncthreads();  // rp_sh and prod are reused
+        for (; q < p1; ++q) acc += val[q] * x[static_cast<long long>(col[q]) * K + k];
+        y[r * K + k] = acc;
+        sq += acc * acc;
       }
     }
     if (parts) tile_partials<K>(sq, static_cast<int>(t), parts);
@@ -261,12 +291,12 @@ __global__ __launch_bounds__(kB) void b_spmm_k(BatchArgs a, const int* __restric
 template <int K>
 __global__ __launch_bounds__(kB) void b_pass1_k(BatchArgs a, AdamParams p) {
 #pragma clang fp contract(off)
-  long long t0, t1;
-  tile_range(a.ntiles, t0, t1);
+  LiveTiles lt;
+  lt.begin(a);
   const int k = threadIdx.x % K;
   const double b1 = p.beta1, b2 = p.beta2;
   const double b1t = a.g->b1t * b1, b2t = a.g->b2t * b2;
-  for (long long t = t0; t < t1; ++t) {
+  for (long long t = lt.tile(a); t >= 0; ++lt.u, t = lt.tile(a)) {
     const int mat = a.tile_mat[t];
     const BatchPair& q = a.pairs[static_cast<long long>(mat) * K + k];
     const long long r0 = a.tiles[t], r1 = a.tiles[t + 1];
@@ -297,10 +327,10 @@ __global__ __launch_bounds__(kB) void b_pass1_k(BatchArgs a, AdamParams p) {
 template <int K>
 __global__ __launch_bounds__(kB) void b_pass2_k(BatchArgs a, AdamParams p) {
 #pragma clang fp contract(off)
-  long long t0, t1;
-  tile_range(a.ntiles, t0, t1);
+  LiveTiles lt;
+  lt.begin(a);
   const int k = threadIdx.x % K;
-  for (long long t = t0; t < t1; ++t) {
+  for (long long t = lt.tile(a); t >= 0; ++lt.u, t = lt.tile(a)) {
     const int mat = a.tile_mat[t];
     const BatchPair& q = a.pairs[static_cast<long long>(mat) * K + k];
     const long long r0 = a.tiles[t], r1 = a.tiles[t + 1];
@@ -328,6 +358,9 @@ __global__ __launch_bounds__(kB) void b_pass2_k(BatchArgs a, AdamParams p) {
 
 void batch_launch_init(const BatchArgs& a, const double* x0, int grid, hipStream_t s) {
   b_init_k<kBatchK><<<grid, kB, 0, s>>>(a, x0);
+}
+void batch_launch_live(const BatchArgs& a, hipStream_t s) {
+  b_live_k<kBatchK><<<1, kB, 0, s>>>(a);
 }
 void batch_launch_reduce(const BatchArgs& a, int mode, const AdamParams& p, hipStream_t s) {
   b_reduce_k<kBatchK><<<a.nmat, kB, 0, s>>>(a, mode, p);
