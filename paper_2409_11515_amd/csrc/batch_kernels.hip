@@ -119,20 +119,36 @@ __global__ __launch_bounds__(kB) void b_init_k(BatchArgs a, const double* __rest
 // One block: matrices with a running start, and the prefix of their tile counts.
 template <int K>
 __global__ __launch_bounds__(kB) void b_live_k(BatchArgs a) {
-  if (threadIdx.x != 0) return;
-  int j = 0, u = 0;
-  for (int m = 0; m < a.nmat; ++m) {
-    bool run = false;
-    for (int k = 0; k < K; ++k) run |= !a.pairs[static_cast<long long>(m) * K + k].stopped;
-    if (run) {
-      a.live_mat[j] = m;
-      a.live_pref[j] = u;
-      u += a.mat_tile0[m + 1] - a.mat_tile0[m];
-      ++j;
+  __shared__ int run_sh[kB / K];
+  __shared__ int j_sh, u_sh;
+  if (threadIdx.x == 0) j_sh = u_sh = 0;
+  // matrices in rounds of kB / K: one thread per pair reads its state, then
+  // thread 0 appends the running matrices of the round in order
+  for (int m0 = 0; m0 < a.nmat; m0 += kB / K) {
+    if (threadIdx.x < kB / K) run_sh[threadIdx.x] = 0;
+    __syncthreads();
+    const int m = m0 + static_cast<int>(threadIdx.x) / K;
+    if (m < a.nmat && !a.pairs[static_cast<long long>(m) * K + threadIdx.x % K].stopped)
+      run_sh[threadIdx.x / K] = 1;  // benign: every writer stores 1
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int j = j_sh, u = u_sh;
+      for (int q = 0; q < kB / K && m0 + q < a.nmat; ++q)
+        if (run_sh[q]) {
+          a.live_mat[j] = m0 + q;
+          a.live_pref[j] = u;
+          u += a.mat_tile0[m0 + q + 1] - a.mat_tile0[m0 + q];
+          ++j;
+        }
+      j_sh = j;
+      u_sh = u;
     }
+    __syncthreads();
   }
-  a.live_pref[j] = u;
-  a.g->nlive = u;
+  if (threadIdx.x == 0) {
+    a.live_pref[j_sh] = u_sh;
+    a.g->nlive = u_sh;
+  }
 }
 
 // --------------------------------------------------------- per-matrix reduce
