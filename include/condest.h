@@ -76,7 +76,7 @@ typedef struct {
 /* Options of Algorithm 1. The paper fixes none of alpha, beta1, beta2, eps or
  * max_iter (they are inputs of the algorithm); cond_opts_default() gives
  * alpha = 1e-2, beta1 = 0.9, beta2 = 0.999, eps = 1e-8, max_iter = 20000,
- * no early stop. */
+ * no early stop, no step-size floor (alpha_min = 0, alpha_decay = 0.5). */
 typedef struct {
   double alpha, beta1, beta2, eps;
   int64_t max_iter;    /* Adam updates per run (>= 1) */
@@ -94,6 +94,17 @@ typedef struct {
                           0 = default 1e-3) */
   int32_t profile;     /* 1: launch eagerly (no graph) with a HIP event pair around
                           every kernel; per-kernel times via cond_plan_kernel_stats */
+  double alpha_min;    /* step-size floor. 0 (default) = Algorithm 1 as written:
+                          alpha is constant and the stop rule ends the run. > 0:
+                          when the stop rule fires and alpha > alpha_min, the run
+                          continues with alpha = max(alpha * alpha_decay,
+                          alpha_min) (moments kept) and stops at the first
+                          plateau at the floor. A constant alpha leaves the
+                          estimate short of the optimum by an amount that
+                          shrinks about as alpha^2; the floor sets that bias.
+                          0 <= alpha_min <= alpha */
+  double alpha_decay;  /* factor of each decrease, 0 < alpha_decay < 1 (default
+                          0.5); used only when alpha_min > 0 */
 } cond_opts_t;
 
 typedef struct {

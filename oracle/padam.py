@@ -36,6 +36,12 @@ class PAOptions:
     max_iter: int = 20000
     stop_rtol: float = 0.0
     stop_window: int = 0
+    # Step-size floor (not in the paper; 0 = Algorithm 1 as written). When the
+    # stop rule fires and alpha > alpha_min, the run continues with
+    # alpha = max(alpha * alpha_decay, alpha_min), moments kept, and stops at
+    # the first plateau reached at the floor.
+    alpha_min: float = 0.0
+    alpha_decay: float = 0.5
 
 
 @dataclass
@@ -73,6 +79,7 @@ def projected_adam(apply, evaluate, x0, opts: PAOptions, observer=None) -> PARes
     best = -np.inf
     x_best = x.copy()
     trace = []
+    alpha = opts.alpha
 
     def consider(xc, y):
         nonlocal best, x_best
@@ -87,7 +94,10 @@ def projected_adam(apply, evaluate, x0, opts: PAOptions, observer=None) -> PARes
         if t >= 2:
             consider(x, y)  # evaluation of x_(t-1)
             if _stop_now(trace, t - 1, opts):
-                return PAResult(best, x_best, t - 1, np.asarray(trace), True)
+                if opts.alpha_min > 0.0 and alpha > opts.alpha_min:
+                    alpha = max(alpha * opts.alpha_decay, opts.alpha_min)
+                else:
+                    return PAResult(best, x_best, t - 1, np.asarray(trace), True)
         nx2 = x @ x
         ny2 = y @ y
         g = x / nx2 - w / ny2  # equation nabla_loss
@@ -97,7 +107,7 @@ def projected_adam(apply, evaluate, x0, opts: PAOptions, observer=None) -> PARes
         b2t = b2t * b2
         m_hat = m / (1.0 - b1t)
         v_hat = v / (1.0 - b2t)
-        d = opts.alpha * m_hat / (np.sqrt(v_hat) + opts.eps)
+        d = alpha * m_hat / (np.sqrt(v_hat) + opts.eps)
         d = d - (x @ d) * x  # tangent to the unit sphere
         x_prev = x
         x = x - d

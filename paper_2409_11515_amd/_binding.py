@@ -46,7 +46,8 @@ class OptsT(C.Structure):
     _fields_ = [("alpha", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
                 ("eps", C.c_double), ("max_iter", C.c_int64), ("stop_rtol", C.c_double),
                 ("stop_window", C.c_int64), ("sigma_min_method", C.c_int32), ("chunk", C.c_int32),
-                ("col_perm", C.c_void_p), ("pivot_tol", C.c_double), ("profile", C.c_int32)]
+                ("col_perm", C.c_void_p), ("pivot_tol", C.c_double), ("profile", C.c_int32),
+                ("alpha_min", C.c_double), ("alpha_decay", C.c_double)]
 
 
 class ResultT(C.Structure):

@@ -118,6 +118,8 @@ AdamParams bparams(const cond_opts_t& o) {
   p.stop_rtol = o.stop_rtol;
   p.stop_window = o.stop_window;
   p.max_iter = o.max_iter;
+  p.alpha_min = o.alpha_min;
+  p.alpha_decay = o.alpha_decay;
   return p;
 }
 
@@ -332,6 +334,9 @@ int cond_batch_run(cond_batch_t* b, const cond_opts_t* o, const double* x0, doub
   if (!b->bound) return fail(COND_ESTATE, "batch not bound");
   if (!(o->alpha > 0) || o->max_iter < 1 || o->stop_window < 0 || o->chunk < 0)
     return fail(COND_EINVAL, "invalid Projected Adam options");
+  if (!(o->alpha_min >= 0) || o->alpha_min > o->alpha ||
+      (o->alpha_min > 0 && !(o->alpha_decay > 0 && o->alpha_decay < 1)))
+    return fail(COND_EINVAL, "invalid step-size floor or decay");
   const AdamParams p = bparams(*o);
   const int npairs = b->nmat * kBatchK;
   BatchArgs a = b->args;
@@ -371,6 +376,7 @@ int cond_batch_run(cond_batch_t* b, const cond_opts_t* o, const double* x0, doub
     std::memset(&s, 0, sizeof(s));
     s.best = -1.0;
     s.ckpt = -1.0;
+    s.alpha = o->alpha;
   }
   BCHK(hipEventRecord(b->ev0, b->stream));
   BCHK(hipMemcpyAsync(a.pairs, b->h_pairs, npairs * sizeof(BatchPair), hipMemcpyHostToDevice,

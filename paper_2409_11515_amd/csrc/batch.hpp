@@ -18,6 +18,7 @@ struct BatchPair {
   double nrm;       // ||x|| before normalisation
   double nx2, ny2;  // x.x and ||M x||^2 of the current iterate
   double xd;        // x . dx
+  double alpha;     // step size of the coming update
   long long iters;  // final T once stopped
   int improved;     // the current iterate is the new best
   int stopped;

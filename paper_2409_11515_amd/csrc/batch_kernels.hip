@@ -219,8 +219,12 @@ __global__ __launch_bounds__(kB) void b_reduce_k(BatchArgs a, int mode, AdamPara
       q.flags |= static_cast<int>(COND_F_MAXITER);
     } else if (p.stop_window > 0 && p.stop_rtol > 0.0 && T % p.stop_window == 0) {
       if (T >= 2 * p.stop_window && q.best - q.ckpt <= p.stop_rtol * q.best) {
-        q.stopped = 1;
-        q.iters = T;
+        if (p.alpha_min > 0.0 && q.alpha > p.alpha_min) {
+          q.alpha = fmax(q.alpha * p.alpha_decay, p.alpha_min);  // plateau: smaller step
+        } else {
+          q.stopped = 1;
+          q.iters = T;
+        }
       }
       q.ckpt = q.best;
     }
@@ -328,7 +332,7 @@ __global__ __launch_bounds__(kB) void b_pass1_k(BatchArgs a, AdamParams p) {
         const double vi = b2 * a.v[e] + (1.0 - b2) * (g * g);
         const double mh = mi / (1.0 - b1t);
         const double vh = vi / (1.0 - b2t);
-        const double di = p.alpha * mh / (sqrt(vh) + p.eps);
+        const double di = q.alpha * mh / (sqrt(vh) + p.eps);
         a.m[e] = mi;
         a.v[e] = vi;
         a.d[e] = di;

@@ -125,6 +125,8 @@ void cond_opts_default(cond_opts_t* o) {
   o->chunk = 0;
   o->col_perm = nullptr;
   o->pivot_tol = 1e-3;
+  o->alpha_min = 0.0;
+  o->alpha_decay = 0.5;
 }
 
 int cond_csr_check(const cond_csr_t* A) { return check_csr(A); }

@@ -55,7 +55,7 @@ __device__ __forceinline__ void block_range(long long n, int lb, long long& r0, 
 __global__ __launch_bounds__(kBlock) void init_k(int n, const double* __restrict__ x0,
                                                  double* __restrict__ x, double* __restrict__ m,
                                                  double* __restrict__ v, double* __restrict__ parts_xx,
-                                                 RunState* st) {
+                                                 RunState* st, double alpha0) {
   const int lb = logical_block();
   long long r0, r1;
   block_range(n, lb, r0, r1);
@@ -83,6 +83,8 @@ __global__ __launch_bounds__(kBlock) void init_k(int n, const double* __restrict
     st->abort_wait = 0;
     st->ckpt = -1.0;
     st->ckpt_next = -1.0;
+    st->alpha = alpha0;
+    st->alpha_next = alpha0;
   }
 }
 
@@ -614,6 +616,7 @@ __global__ __launch_bounds__(kBlock) void pass1_k(int n, const double* __restric
   bool improved = false;
   int stop = 0, status = COND_OK, flags = 0;
   long long iters = t - 1;
+  double alpha = st->alpha;
   if (st->abort_wait) {
     stop = 1;
     status = COND_ETIMEOUT;
@@ -632,7 +635,13 @@ __global__ __launch_bounds__(kBlock) void pass1_k(int n, const double* __restric
       stop = 1;
       flags |= static_cast<int>(COND_F_MAXITER);
     } else if (p.stop_window > 0 && p.stop_rtol > 0.0 && T % p.stop_window == 0) {
-      if (T >= 2 * p.stop_window && best_next - st->ckpt <= p.stop_rtol * best_next) stop = 1;
+      if (T >= 2 * p.stop_window && best_next - st->ckpt <= p.stop_rtol * best_next) {
+        // plateau: with a step-size floor, continue with a smaller step until it is reached
+        if (p.alpha_min > 0.0 && alpha > p.alpha_min)
+          alpha = fmax(alpha * p.alpha_decay, p.alpha_min);
+        else
+          stop = 1;
+      }
       ckpt_next = best_next;
     }
   }
@@ -644,6 +653,7 @@ __global__ __launch_bounds__(kBlock) void pass1_k(int n, const double* __restric
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st->best_next = best_next;
     st->ckpt_next = ckpt_next;
+    st->alpha_next = alpha;
     if (t >= 2 && trace && status == COND_OK) trace[t - 2] = best_next;
     if (stop) {
       st->iters = iters;
@@ -663,7 +673,7 @@ __global__ __launch_bounds__(kBlock) void pass1_k(int n, const double* __restric
     const double vi = b2 * v[i] + (1.0 - b2) * (g * g);
     const double mh = mi / (1.0 - b1t);
     const double vh = vi / (1.0 - b2t);
-    const double di = p.alpha * mh / (sqrt(vh) + p.eps);
+    const double di = alpha * mh / (sqrt(vh) + p.eps);
     m[i] = mi;
     v[i] = vi;
     d[i] = di;
@@ -710,6 +720,7 @@ __global__ __launch_bounds__(kBlock) void pass2_k(int n, double* __restrict__ x,
     st->b2t = st->b2t * p.beta2;
     st->best = st->best_next;
     st->ckpt = st->ckpt_next;
+    st->alpha = st->alpha_next;
   }
 }
 
@@ -748,8 +759,8 @@ int grid_for(int n) {
 }
 
 void launch_init(int n, const double* x0, double* x, double* m, double* v, double* parts_xx,
-                 int grid, RunState* st, hipStream_t s) {
-  init_k<<<grid, kBlock, 0, s>>>(n, x0, x, m, v, parts_xx, st);
+                 int grid, RunState* st, double alpha0, hipStream_t s) {
+  init_k<<<grid, kBlock, 0, s>>>(n, x0, x, m, v, parts_xx, st, alpha0);
 }
 
 void launch_normalise(int n, double* x, const double* parts_xx, int grid, double* parts_x,

@@ -44,6 +44,8 @@ struct RunState {
   int flags;         // COND_F_* bits of this run (adam_pass1, block 0)
   int abort_wait;    // 1 when a triangular-solve wait timed out (trsv)
   int pad_;
+  double alpha;       // step size of the coming update (adam_pass2, block 0)
+  double alpha_next;  // after this iteration's stop check (adam_pass1, block 0)
 };
 
 struct AdamParams {
@@ -51,6 +53,8 @@ struct AdamParams {
   double stop_rtol;
   long long stop_window;
   long long max_iter;
+  double alpha_min;    // > 0: on a stop-rule plateau shrink alpha instead of stopping
+  double alpha_decay;  // factor of each shrink
 };
 
 // CSR on the device. rowptr is int32 when idx64 == 0, else int64.
@@ -106,7 +110,7 @@ using TrsvArgs = DevTri;
 int grid_for(int n);  // fixed grid size of the reduction kernels for length n
 
 void launch_init(int n, const double* x0, double* x, double* m, double* v, double* parts_xx,
-                 int grid, RunState* st, hipStream_t s);
+                 int grid, RunState* st, double alpha0, hipStream_t s);
 void launch_normalise(int n, double* x, const double* parts_xx, int grid, double* parts_x,
                       RunState* st, double* const* resets, int nresets, unsigned* tickets,
                       int ntickets, hipStream_t s);

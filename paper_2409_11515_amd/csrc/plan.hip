@@ -428,6 +428,8 @@ AdamParams params_of(const cond_opts_t& o) {
   p.stop_rtol = o.stop_rtol;
   p.stop_window = o.stop_window;
   p.max_iter = o.max_iter;
+  p.alpha_min = o.alpha_min;
+  p.alpha_decay = o.alpha_decay;
   return p;
 }
 
@@ -437,6 +439,9 @@ int check_opts(const cond_opts_t* o) {
       !(o->eps >= 0) || o->max_iter < 1 || o->stop_window < 0 || !(o->stop_rtol >= 0) ||
       o->chunk < 0)
     return fail(COND_EINVAL, "invalid Projected Adam options");
+  if (!(o->alpha_min >= 0) || o->alpha_min > o->alpha ||
+      (o->alpha_min > 0 && !(o->alpha_decay > 0 && o->alpha_decay < 1)))
+    return fail(COND_EINVAL, "invalid step-size floor or decay");
   if (o->sigma_min_method != COND_MIN_LU && o->sigma_min_method != COND_MIN_NONE)
     return fail(COND_EINVAL, "unknown sigma_min method");
   return COND_OK;
@@ -611,7 +616,7 @@ int run_route(cond_plan* p, int route, const cond_opts_t& o, const double* x0, d
   if (o.profile) {
     // eager launches with an event pair around each kernel; poll every iteration
     CHK(hipEventRecord(p->ev_start, p->stream));
-    launch_init(p->n, x0, p->x, p->m, p->v, p->parts_xx, p->grid, p->st, p->stream);
+    launch_init(p->n, x0, p->x, p->m, p->v, p->parts_xx, p->grid, p->st, o.alpha, p->stream);
     CHK(hipGetLastError());
     p->profiling = true;
     int st = COND_OK;
@@ -634,7 +639,7 @@ int run_route(cond_plan* p, int route, const cond_opts_t& o, const double* x0, d
     int st = get_graph(p, route, chunk, trace, xbest, ap, &exec);
     if (st) return st;
     CHK(hipEventRecord(p->ev_start, p->stream));
-    launch_init(p->n, x0, p->x, p->m, p->v, p->parts_xx, p->grid, p->st, p->stream);
+    launch_init(p->n, x0, p->x, p->m, p->v, p->parts_xx, p->grid, p->st, o.alpha, p->stream);
     CHK(hipGetLastError());
     if ((st = replay_until_stop(p, exec, chunk, total))) return st;
   }

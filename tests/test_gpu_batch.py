@@ -73,6 +73,24 @@ def test_batch_stop_rule_matches_oracle(torch_cuda):
             assert r["pair_best"][i, k] == pytest.approx(o.sigma, rel=1e-9)
 
 
+def test_batch_step_size_floor_matches_oracle(torch_cuda):
+    import paper_2409_11515_amd as pa
+
+    torch = torch_cuda
+    mats, starts = _batch_inputs([11, 6])
+    opts = dict(max_iter=6000, stop_rtol=1e-9, stop_window=50, alpha_min=1.25e-3, alpha_decay=0.5)
+    b = pa.Batch([(m.n, m.rowptr, m.col, m.val) for m in mats]).bind(tile_rows=64, grid=1024)
+    x0 = torch.as_tensor(pa.interleave_starts(starts), device="cuda")
+    r = b.run(x0, **opts)
+    b.close()
+    for i, m in enumerate(mats):
+        apply, evaluate = forward_apply(m.n, m.rowptr, m.col, m.val)
+        for k in (1, 6):
+            o = projected_adam(apply, evaluate, starts[i][k], PAOptions(**opts))
+            assert r["pair_iters"][i, k] == o.iters
+            assert r["pair_best"][i, k] == pytest.approx(o.sigma, rel=1e-9)
+
+
 def test_batch_uneven_sizes_and_determinism(torch_cuda):
     import paper_2409_11515_amd as pa
 

@@ -158,7 +158,9 @@ def _both(torch, a, iters, seed=1, **kw):
     p.close()
     o = oracle_estimate(a.n, a.rowptr, a.col, a.val, x0,
                         opts=PAOptions(max_iter=iters, stop_rtol=kw.get("stop_rtol", 0.0),
-                                       stop_window=kw.get("stop_window", 0)))
+                                       stop_window=kw.get("stop_window", 0),
+                                       alpha_min=kw.get("alpha_min", 0.0),
+                                       alpha_decay=kw.get("alpha_decay", 0.5)))
     return g, o
 
 
@@ -210,6 +212,19 @@ def test_early_stop_same_iteration(torch_cuda):
     assert g["iters_max"] == o["iters_max"] and g["iters_min"] == o["iters_min"]
     assert g["iters_max"] < 5000
     assert g["kappa"] == pytest.approx(o["kappa"], rel=1e-3)
+
+
+def test_step_size_floor_same_iteration(torch_cuda):
+    """With a step-size floor both sides shrink alpha at the same plateaus and
+    stop at the same update, later than without it."""
+    a = hydromech2d(21, seed=4)
+    kw = dict(stop_rtol=1e-9, stop_window=50)
+    g0, _ = _both(torch_cuda, a, 8000, **kw)
+    g, o = _both(torch_cuda, a, 8000, alpha_min=1.25e-3, alpha_decay=0.5, **kw)
+    assert g["iters_max"] == o["iters_max"] and g["iters_min"] == o["iters_min"]
+    assert g["iters_max"] > g0["iters_max"] and g["iters_min"] > g0["iters_min"]
+    assert g["sigma_max"] >= g0["sigma_max"] and g["sigma_min"] <= g0["sigma_min"]
+    assert g["kappa"] == pytest.approx(o["kappa"], rel=1e-6)
 
 
 def test_bitwise_determinism(torch_cuda):
