@@ -68,7 +68,8 @@ def bench_warm(w, args):
     from paper_2409_11515_amd.warmstart import WarmStart, label
     from synth import hm_fields, hydromech2d, start_vector
 
-    opts = dict(max_iter=args.max_iter, stop_rtol=args.stop_rtol, stop_window=args.stop_window)
+    opts = dict(max_iter=args.max_iter, stop_rtol=args.stop_rtol, stop_window=args.stop_window,
+                alpha_min=args.alpha_min, alpha_decay=0.5)
     lab_opts = dict(max_iter=4000, stop_rtol=1e-7, stop_window=50)
     t0 = time.perf_counter()
 
@@ -227,7 +228,8 @@ def bench_batch(w, args):
     nnz = sum(m.nnz for m in mats)
     print(f"[bench] batch: {len(mats)} matrices, rows {nrows}, nnz {nnz} ({gen_s:.0f}s)",
           file=sys.stderr, flush=True)
-    opts = dict(max_iter=args.max_iter, stop_rtol=args.stop_rtol, stop_window=args.stop_window)
+    opts = dict(max_iter=args.max_iter, stop_rtol=args.stop_rtol, stop_window=args.stop_window,
+                alpha_min=args.alpha_min, alpha_decay=0.5)
     t0 = time.perf_counter()
     b = pa.Batch([(m.n, m.rowptr, m.col, m.val) for m in mats], **opts).bind()
     torch.cuda.synchronize()
@@ -307,15 +309,19 @@ def pmc_traffic(workload, kernel):
     return entry["traffic_bytes"] if entry else None
 
 
-def golden_kappa(w):
+def golden(w):
+    """(kappa the oracle reaches with the bench's options, a more accurate
+    reference kappa) from tests/golden/, either None when not stored."""
     if not w["golden"]:
-        return None
+        return None, None
     path = os.path.join(ROOT, "tests", "golden", w["golden"])
     if not os.path.exists(path):
-        return None
+        return None, None
     with open(path) as f:
         g = json.load(f)
-    return g.get("kappa", g.get("kappa_svd"))
+    if "kappa_svd" in g:  # exact (extended-precision SVD)
+        return None, g["kappa_svd"]
+    return g.get("kappa"), g.get("reference", {}).get("kappa")
 
 
 def cpu_baseline(a, iters_max, iters_min, budget_s=25.0, min_route=True):
@@ -370,9 +376,11 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="hm201", choices=sorted(WORKLOADS))
-    ap.add_argument("--max-iter", type=int, default=3000)
+    ap.add_argument("--max-iter", type=int, default=6000)
     ap.add_argument("--stop-rtol", type=float, default=1e-6)
     ap.add_argument("--stop-window", type=int, default=25)
+    ap.add_argument("--alpha-min", type=float, default=2.5e-3,
+                    help="step-size floor: on a plateau alpha halves down to this (0: constant alpha)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--train-scale", type=float, default=1.0,
                     help="c5warm: multiplies the training-set sizes")
@@ -385,7 +393,7 @@ def main():
                     help="c5warm: updates of the long reference runs without the stop rule")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
 
@@ -407,6 +415,7 @@ def main():
     print(f"[bench] workload {args.workload}: n={a.n} nnz={a.nnz} (generated in {gen_s:.1f}s)",
           file=sys.stderr, flush=True)
     opts = dict(max_iter=args.max_iter, stop_rtol=args.stop_rtol, stop_window=args.stop_window,
+                alpha_min=args.alpha_min, alpha_decay=0.5,
                 sigma_min_method=pa.COND_MIN_LU if w["min_route"] else pa.COND_MIN_NONE)
     t0 = time.perf_counter()
     plan = pa.Plan(a.n, a.rowptr, a.col, a.val, **opts)
@@ -446,7 +455,7 @@ def main():
                for k, v in stats.items() if v[1]}
     spmv = kernels.get("spmv_A")
 
-    gk = golden_kappa(w)
+    gk, gref = golden(w)
     out = {
         "metric": "time-to-kappa (1e-3 rel) per matrix + SpMV HBM GB/s",
         "value": step_s,
@@ -463,13 +472,16 @@ def main():
         "config": {"workload": f"{args.workload}: six-field staggered-grid hydro-mechanical matrix"
                                if w["kind"] == "hm" else "tiny Stokes",
                    "n": a.n, "nnz": a.nnz, "nnz_l": res["nnz_l"], "nnz_u": res["nnz_u"],
-                   "alpha": 1e-2, "max_iter": args.max_iter, "stop_rtol": args.stop_rtol,
-                   "stop_window": args.stop_window, "parallelism": "single GPU"},
+                   "alpha": 1e-2, "alpha_min": args.alpha_min, "max_iter": args.max_iter,
+                   "stop_rtol": args.stop_rtol, "stop_window": args.stop_window,
+                   "parallelism": "single GPU"},
         "kappa": res["kappa"] if w["min_route"] else None,
         "sigma_max": res["sigma_max"],
         "runs": "sigma_max and sigma_min" if w["min_route"] else "sigma_max only",
         "kappa_golden": gk,
         "kappa_rel_err": (abs(res["kappa"] - gk) / gk) if gk else None,
+        "kappa_reference": gref,
+        "kappa_reference_err": (abs(res["kappa"] - gref) / gref) if gref else None,
         "iters": {"sigma_max": res["iters_max"], "sigma_min": res["iters_min"]},
         "run_ms": {"sigma_max": res["ms_max"], "sigma_min": res["ms_min"]},
         "setup_s": setup_s,

@@ -15,5 +15,5 @@ def pytest_configure(config):
 
 def pytest_collection_modifyitems(config, items):
     # GPU tests fail loudly (not skip) when the device or library is missing,
-    # so that a run on the GPU machine never passes on a silent fallback.
+    # so that a run on a GPU machine never passes on a silent fallback.
     pass

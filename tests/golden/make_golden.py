@@ -13,12 +13,12 @@ Outputs (JSON, one file per workload):
   hm_side6_seed1.json          six-field hydro-mechanical system on 6x6 nodes
                                (n = 216), mpmath inverse at 50 digits;
   hm_side201_seed1.json        the 201x201-node hydro-mechanical system
-                               (n = 242406): the oracle's converged sigma_max,
-                               sigma_min and kappa (Projected Adam, alpha =
-                               1e-2, 2000 / 400 updates, start vectors seeds 11
-                               and 12), with the update counts at which each
-                               running best came within 1e-4 and 1e-3 of its
-                               final value.
+                               (n = 242406), start vectors seeds 11 and 12:
+                               the oracle's sigma_max, sigma_min and kappa
+                               with the benchmark's options (alpha 1e-2, step
+                               floor 2.5e-3, stop rule 1e-6 over 25), and a
+                               reference from 3000 updates at a constant
+                               alpha of 1.25e-3.
 """
 
 from __future__ import annotations
@@ -79,23 +79,32 @@ def main(which=("c1", "hm6")):
         a = hydromech2d(201, seed=1)
         x0a = start_vector(a.n, 11)
         x0b = start_vector(a.n, 12)
-        r = estimate_cond(a.n, a.rowptr, a.col, a.val, x0a, x0b, opts=PAOptions(max_iter=2000),
-                          opts_min=PAOptions(max_iter=400))
-        tmax, tinv = r["trace_max"], r["trace_min"]
+        # (1) the benchmark's own options: step 1e-2 with a floor of 2.5e-3,
+        #     stop rule 1e-6 over 25 updates
+        bench = PAOptions(max_iter=6000, stop_rtol=1e-6, stop_window=25, alpha_min=2.5e-3,
+                          alpha_decay=0.5)
+        r = estimate_cond(a.n, a.rowptr, a.col, a.val, x0a, x0b, opts=bench)
+        # (2) reference: a constant small step (1.25e-3) for 3000 updates, no stop rule
+        ref = PAOptions(alpha=1.25e-3, max_iter=3000)
+        q = estimate_cond(a.n, a.rowptr, a.col, a.val, x0a, x0b, opts=ref)
         _write("hm_side201_seed1.json", {
             "workload": "hydromech2d(side=201, seed=1)", "n": a.n, "nnz": a.nnz,
             "starts": {"sigma_max": "start_vector(n, 11)", "sigma_min": "start_vector(n, 12)"},
-            "opts": {"alpha": 1e-2, "beta1": 0.9, "beta2": 0.999, "eps": 1e-8,
-                     "max_iter_max": 2000, "max_iter_min": 400},
+            "opts": {"alpha": 1e-2, "alpha_min": 2.5e-3, "alpha_decay": 0.5, "beta1": 0.9,
+                     "beta2": 0.999, "eps": 1e-8, "stop_rtol": 1e-6, "stop_window": 25,
+                     "max_iter": 6000},
             "sigma_max": r["sigma_max"], "sigma_min": r["sigma_min"], "kappa": r["kappa"],
-            "iters_to_1e-3": {"max": _first_within(tmax, 1e-3), "min": _first_within(tinv, 1e-3)},
-            "iters_to_1e-4": {"max": _first_within(tmax, 1e-4), "min": _first_within(tinv, 1e-4)},
+            "iters": {"max": r["iters_max"], "min": r["iters_min"]},
+            "reference": {"opts": {"alpha": 1.25e-3, "max_iter": 3000},
+                          "sigma_max": q["sigma_max"], "sigma_min": q["sigma_min"],
+                          "kappa": q["kappa"],
+                          "iters_to_1e-3": {"max": _first_within(q["trace_max"], 1e-3),
+                                            "min": _first_within(q["trace_min"], 1e-3)}},
             "oracle_seconds": {"max_run": r["time_max_s"], "lu": r["time_lu_s"],
                                "min_run": r["time_min_s"]},
             "superlu_nnz": {"L": r["nnz_l"], "U": r["nnz_u"]},
             "method": "oracle Projected Adam (float64, SciPy SuperLU for Algorithm 2)",
         })
-
 
 if __name__ == "__main__":
     main(tuple(sys.argv[1:]) or ("c1", "hm6"))

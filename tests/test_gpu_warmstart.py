@@ -73,7 +73,7 @@ def test_warm_start_needs_fewer_updates(trained):
         ref = max(w["trace_min"][-1], c["trace_min"][-1])
         warm_it.append(_first_within(w["trace_min"], ref))
         cold_it.append(_first_within(c["trace_min"], ref))
-        # the warm-started estimate with its check and fallback, judged by the plain run
+        # the warm-started estimate with its check and fallback, against the plain run
         plain = plan.run(None, xr, max_iter=2000, stop_rtol=1e-7, stop_window=50)
         r = ws.run(plan, f, xr, max_iter=2000, stop_rtol=1e-7, stop_window=50)
         assert r["sigma_min"] == pytest.approx(plain["sigma_min"], rel=1e-3)
