@@ -290,21 +290,29 @@ def make_matrix(w):
     return stokes2d(w["side"], w["side"], seed=w["seed"])
 
 
+def _trsv_source_hash():
+    """SHA-256 of the triangular-solve section of kernels.hip (the code the
+    counters in profiles/pmc_traffic.json were taken on)."""
+    import hashlib
+
+    with open(os.path.join(ROOT, "paper_2409_11515_amd", "csrc", "kernels.hip")) as f:
+        src = f.read()
+    a = src.index("// ----------------------------------------------------------------- trsv")
+    b = src.index("// ---------------------------------------------------------- adam pass 1")
+    return hashlib.sha256(src[a:b].encode()).hexdigest()
+
+
 def pmc_traffic(workload, kernel):
     """HBM bytes per launch of `kernel` from the committed counter runs
     (profiles/pmc_traffic.json), or None when they were taken on another
-    version of the kernel source or not for this workload."""
-    import hashlib
-
+    version of the kernel's source or not for this workload."""
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
-    src = os.path.join(ROOT, "paper_2409_11515_amd", "csrc", "kernels.hip")
-    if not os.path.exists(path):
+    if not os.path.exists(path) or not kernel.startswith("trsv"):
         return None
     with open(path) as f:
         rec = json.load(f)
-    with open(src, "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != rec.get("kernels_source_sha256"):
-            return None
+    if _trsv_source_hash() != rec.get("trsv_source_sha256"):
+        return None
     entry = rec.get("workloads", {}).get(workload, {}).get(kernel)
     return entry["traffic_bytes"] if entry else None
 
