@@ -64,7 +64,7 @@ def order_nd(n, rowptr, col, val) -> np.ndarray:
 class LU:
     """Host LU of the library, P A Q = L U (for checks of the set-up step)."""
 
-    def __init__(self, n, rowptr, col, val, col_perm=None, pivot_tol=1e-3):
+    def __init__(self, n, rowptr, col, val, col_perm=None, pivot_tol=1e-6):
         h = HostCsr(n, rowptr, col, val)
         cp = None if col_perm is None else np.ascontiguousarray(col_perm, np.int32)
         self._h = C.c_void_p()

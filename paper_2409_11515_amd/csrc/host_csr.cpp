@@ -124,7 +124,7 @@ void cond_opts_default(cond_opts_t* o) {
   o->sigma_min_method = COND_MIN_LU;
   o->chunk = 0;
   o->col_perm = nullptr;
-  o->pivot_tol = 1e-3;
+  o->pivot_tol = 1e-6;
   o->alpha_min = 0.0;
   o->alpha_decay = 0.5;
 }

@@ -71,7 +71,7 @@ void csc_as_transpose_csr(int32_t n, const std::vector<int64_t>& cp, std::vector
 int lu_factor(const HostCsr& a, const HostCsr& at, const int32_t* col_perm_in, double tol,
               cond_lu& lu) {
   const int32_t n = a.n;
-  if (!(tol > 0.0 && tol <= 1.0)) tol = 1e-3;
+  if (!(tol > 0.0 && tol <= 1.0)) tol = 1e-6;
   std::vector<int32_t> q(n);
   if (col_perm_in) {
     std::vector<char> seen(n, 0);
