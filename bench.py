@@ -302,10 +302,11 @@ def _trsv_source_hash():
     return hashlib.sha256(src[a:b].encode()).hexdigest()
 
 
-def pmc_traffic(workload, kernel):
+def pmc_traffic(workload, kernel, factor_nnz):
     """HBM bytes per launch of `kernel` from the committed counter runs
     (profiles/pmc_traffic.json), or None when they were taken on another
-    version of the kernel's source or not for this workload."""
+    version of the kernel's source, on other LU factors (factor_nnz = the
+    fill of L and U) or not for this workload."""
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if not os.path.exists(path) or not kernel.startswith("trsv"):
         return None
@@ -313,7 +314,10 @@ def pmc_traffic(workload, kernel):
         rec = json.load(f)
     if _trsv_source_hash() != rec.get("trsv_source_sha256"):
         return None
-    entry = rec.get("workloads", {}).get(workload, {}).get(kernel)
+    wl = rec.get("workloads", {}).get(workload, {})
+    if list(wl.get("factor_nnz", [])) != list(factor_nnz):
+        return None
+    entry = wl.get(kernel)
     return entry["traffic_bytes"] if entry else None
 
 
@@ -494,7 +498,7 @@ def main():
         "run_ms": {"sigma_max": res["ms_max"], "sigma_min": res["ms_min"]},
         "setup_s": setup_s,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": pmc_traffic(args.workload, dom),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": pmc_traffic(args.workload, dom, [res["nnz_l"], res["nnz_u"]]),
                      "kernel": dom, "avg_us": avg_ms * 1e3, "alg_bytes_per_launch": byts},
         "spmv": spmv,
         "kernels": kernels,
