@@ -446,9 +446,13 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_k(TrsvArgs t, const double* _
       q1[j] = r < cnt ? t.off_rp[lo + r + 1] : 0;
     }
     if (kind >= 0 && kind < S) {
-      // ---- slice task: partial off-panel sums over one slice of every row
+      // ---- slice task: partial off-panel sums over one slice of every row's
+      // older entries (the ones on rows before off_split; the finish step
+      // adds the newest ones itself)
 #pragma unroll
       for (int j = 0; j < kSubPanels; ++j) {
+        const int r = g + kPanel * j;
+        if (r < cnt) q1[j] = t.off_split[lo + r];
         const long long len = q1[j] - q0[j];
         q1[j] = q0[j] + len * (kind + 1) / S;
         q0[j] = q0[j] + len * kind / S;
@@ -544,7 +548,12 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_k(TrsvArgs t, const double* _
         }
 #pragma unroll
         for (int off = kLanesPerRow / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kLanesPerRow);
-        sums[j] = acc;
+        // the row's newest entries (on the panels just before this one): the
+        // finish step waits for them itself, one hop fewer on a chain
+        const double recent = r < cnt ? row_sum(t.off_split[lo + r], t.off_rp[lo + r + 1], sub,
+                                                t.off_col, t.off_val, out, st)
+                                      : 0.0;
+        sums[j] = acc + recent;
       }
     }
 #pragma unroll

@@ -86,13 +86,14 @@ constexpr long long kTileEntriesHost = 2048;
 // slices and finishes the panel (S = panel_split[panel]).
 constexpr int kPanel = 64;       // rows of a sub-panel: one wave solves its triangle
 constexpr int kMaxSlicesDev = 64;  // most slices a heavy panel is cut into
-constexpr int kPanelRows = 128;  // rows of a panel: its sub-panels are solved in order by one block
+constexpr int kPanelRows = 64;   // rows of a panel: its sub-panels are solved in order by one block
 struct DevTri {
   int n = 0;
   const long long* off_rp = nullptr;
   const int* off_col = nullptr;
   const double* off_val = nullptr;
   const long long* in_rp = nullptr;
+  const long long* off_split = nullptr;  // per row of a sliced panel: first entry the finish adds
   const long long* in_split = nullptr;  // per row: first in-panel entry inside its own sub-panel
   const int* in_col = nullptr;          // in-panel columns, relative to the panel's first row
   const double* in_val = nullptr;

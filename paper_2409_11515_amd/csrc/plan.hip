@@ -62,7 +62,7 @@ struct GraphKey {
 // its panel first; in_split marks where the entries of its own sub-panel start.
 struct PanelCsr {
   int32_t n = 0;
-  std::vector<int64_t> off_rp, in_rp, in_split;
+  std::vector<int64_t> off_rp, in_rp, in_split, off_split;
   std::vector<int32_t> off_col, in_col;
   std::vector<double> off_val, in_val;
   std::vector<int32_t> pstart;  // panel p holds rows [pstart[p], pstart[p+1])
@@ -73,8 +73,12 @@ struct PanelCsr {
 };
 
 // A panel whose rows hold more off-panel entries than this is cut into
-// slices (at most kMaxSlices) that separate blocks sum in parallel.
+// slices (at most kMaxSlices) that separate blocks sum in parallel. The
+// slices take a row's entries on rows more than kRecentRows before the
+// panel; the finish step takes the newer ones, so a chain of panels (a dense
+// separator block) waits for its predecessor in one step, not two.
 constexpr int64_t kSliceEntries = 4096;
+constexpr int32_t kRecentRows = 64;
 constexpr int32_t kMaxSlices = kMaxSlicesDev;
 
 // Panel boundaries: a panel closes when it holds kPanelRows rows, or -- once
@@ -146,6 +150,7 @@ PanelCsr split_panels(const HostCsr& t) {
   s.off_rp.assign(t.n + 1, 0);
   s.in_rp.assign(t.n + 1, 0);
   s.in_split.assign(t.n, 0);
+  s.off_split.assign(t.n, 0);
   for (int32_t i = 0; i < t.n; ++i) {
     const int32_t lo = s.pstart[pid[i]];
     const int32_t sub0 = lo + (i - lo) / kPanel * kPanel;  // first row of i's sub-panel
@@ -185,6 +190,12 @@ PanelCsr split_panels(const HostCsr& t) {
     s.panel_split[p] = S;
     s.panel_slot[p] = s.nslots;
     s.nslots += S;
+    const int32_t c0 = s.pstart[p] - kRecentRows;  // older entries: columns below c0
+    for (int32_t i = s.pstart[p]; i < s.pstart[p + 1]; ++i) {
+      int64_t e = s.off_rp[i];
+      while (e < s.off_rp[i + 1] && s.off_col[e] < c0) ++e;  // columns are sorted in a row
+      s.off_split[i] = e;
+    }
     for (int32_t k = 0; k <= S; ++k) {
       s.task_panel.push_back(p);
       s.task_kind.push_back(k);
@@ -287,7 +298,7 @@ struct cond_plan {
   // offsets into the workspace
   struct {
     size_t a_rp, a_col, a_val, at_rp, at_col, at_val, a_tiles, at_tiles;
-    size_t tri[4][13];
+    size_t tri[4][14];
     size_t u_diag, u_diag_rev, row_perm, rev, scat_s, scat_r;
     size_t vec[10];
     size_t parts[4];
@@ -329,6 +340,7 @@ void plan_layout(cond_plan* p) {
       p->o.tri[f][10] = L.take(t.task_panel.size() * 4);
       p->o.tri[f][11] = L.take(t.task_kind.size() * 4);
       p->o.tri[f][12] = L.take(static_cast<size_t>(n) * 8);
+      p->o.tri[f][13] = L.take(static_cast<size_t>(n) * 8);
     }
     p->o.u_diag = L.take(n * 8);
     p->o.u_diag_rev = L.take(n * 8);
@@ -399,6 +411,7 @@ int upload_tri(cond_plan* p, const PanelCsr& t, const size_t* off, const double*
   if ((st = upload(p, off[10], t.task_panel.data(), t.task_panel.size() * 4))) return st;
   if ((st = upload(p, off[11], t.task_kind.data(), t.task_kind.size() * 4))) return st;
   if ((st = upload(p, off[12], t.in_split.data(), static_cast<size_t>(t.n) * 8))) return st;
+  if ((st = upload(p, off[13], t.off_split.data(), static_cast<size_t>(t.n) * 8))) return st;
   if (t.nslots > 0) launch_fill(t.nslots * kPanelRows, at_off<double>(p, off[9]), kPending, p->stream);
   out.n = t.n;
   out.off_rp = at_off<long long>(p, off[0]);
@@ -406,6 +419,7 @@ int upload_tri(cond_plan* p, const PanelCsr& t, const size_t* off, const double*
   out.off_val = at_off<double>(p, off[2]);
   out.in_rp = at_off<long long>(p, off[3]);
   out.in_split = at_off<long long>(p, off[12]);
+  out.off_split = at_off<long long>(p, off[13]);
   out.in_col = at_off<int>(p, off[4]);
   out.in_val = at_off<double>(p, off[5]);
   out.diag = diag_dev;
