@@ -93,32 +93,45 @@ __global__ void prep_k(const double* __restrict__ cells, u16* __restrict__ act0,
 
 // ------------------------------------------------------------------ conv
 // out[p, co] = sum_{tap, ci} in[p + tap offset, ci] * wt[co][tap * CIN + ci]
-// One wave per 16 pixels x 16 output channels. A-operand lane l: pixel
-// p0 + l % 16, k = 8 (l / 16) .. + 7; B-operand lane l: channel co0 + l % 16,
-// same k; result lane l: channel co0 + l % 16, pixels p0 + 4 (l / 16) .. + 3.
+// A block of 4 waves takes 64 pixels; the packed weights ([COUT][KP]
+// bfloat16) are first staged in LDS, then each wave computes 16 pixels x all
+// COUT channels: per step of 32 k-values it loads one A fragment (its 16
+// pixels' inputs) and reuses it for COUT/16 MFMAs whose B fragments come from
+// LDS. MFMA v_mfma_f32_16x16x32_bf16 lane layout: A lane l holds row l % 16,
+// k = 8 (l / 16) .. + 7; B lane l holds column l % 16, same k; the result
+// lane l holds column l % 16, rows 4 (l / 16) .. + 3.
 // EPI 0: + bias, ReLU, bfloat16 out; 1: + bias, float32 out (last layer);
 // 2: times (mask > 0), bfloat16 out (input gradient through a ReLU).
+constexpr int kConvWaves = 8;
+
 template <int CIN, int COUT, int EPI>
-__global__ __launch_bounds__(64) void conv_k(const u16* __restrict__ in, const u16* __restrict__ wt,
-                                             const float* __restrict__ bias,
-                                             const u16* __restrict__ mask, void* __restrict__ out,
-                                             int B, int S) {
-  constexpr int K = 9 * CIN, KP = kpad(CIN);
-  const int lane = threadIdx.x;
+__global__ __launch_bounds__(64 * kConvWaves) void conv_k(const u16* __restrict__ in,
+                                                          const u16* __restrict__ wt,
+                                                          const float* __restrict__ bias,
+                                                          const u16* __restrict__ mask,
+                                                          void* __restrict__ out, int B, int S) {
+  constexpr int K = 9 * CIN, KP = kpad(CIN), NB = COUT / 16;
+  __shared__ uint4 w_sh[COUT * KP / 8];
+  for (int i = threadIdx.x; i < COUT * KP / 8; i += 64 * kConvWaves)
+    w_sh[i] = reinterpret_cast<const uint4*>(wt)[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const long long npix = static_cast<long long>(B) * S * S;
-  const long long p0 = static_cast<long long>(blockIdx.x) * 16;
-  const int co0 = blockIdx.y * 16;
+  const long long p0 = (static_cast<long long>(blockIdx.x) * kConvWaves + wave) * 16;
+  if (p0 >= npix) return;  // no barrier follows
   const long long pa = p0 + (lane & 15);
   const bool pin = pa < npix;
   const int b = pin ? static_cast<int>(pa / (S * S)) : 0;
   const int rr = pin ? static_cast<int>(pa % (S * S)) : 0;
   const int y = rr / S, x = rr % S;
   const int kq = 8 * (lane >> 4);
-  const u16* wrow = wt + static_cast<long long>(co0 + (lane & 15)) * KP;
-  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  f32x4 acc[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
   for (int ks = 0; ks < KP; ks += 32) {
     const int k0 = ks + kq;
-    Frag a, w;
+    Frag a;
     a.q = make_uint4(0, 0, 0, 0);
     if (pin && k0 < K) {
       const int tap = k0 / CIN, ci0 = k0 % CIN;
@@ -126,24 +139,32 @@ __global__ __launch_bounds__(64) void conv_k(const u16* __restrict__ in, const u
       if (yy >= 0 && yy < S && xx >= 0 && xx < S)
         a.q = *reinterpret_cast<const uint4*>(in + ((static_cast<long long>(b) * S + yy) * S + xx) * CIN + ci0);
     }
-    w.q = *reinterpret_cast<const uint4*>(wrow + k0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, w.v, acc, 0, 0, 0);
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      Frag w;
+      w.q = w_sh[((j * 16 + (lane & 15)) * KP + k0) / 8];
+      acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, w.v, acc[j], 0, 0, 0);
+    }
   }
-  const int co = co0 + (lane & 15);
-  for (int j = 0; j < 4; ++j) {
-    const long long p = p0 + 4 * (lane >> 4) + j;
-    if (p >= npix) continue;
-    float v = acc[j];
-    if (EPI == 0) {
-      v += bias[co];
-      v = v > 0.f ? v : 0.f;
-      static_cast<u16*>(out)[p * COUT + co] = to_bf16(v);
-    } else if (EPI == 1) {
-      v += bias[co];
-      static_cast<float*>(out)[p * COUT + co] = v;
-    } else {
-      v = from_bf16(mask[p * COUT + co]) > 0.f ? v : 0.f;
-      static_cast<u16*>(out)[p * COUT + co] = to_bf16(v);
+#pragma unroll
+  for (int jb = 0; jb < NB; ++jb) {
+    const int co = jb * 16 + (lane & 15);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const long long p = p0 + 4 * (lane >> 4) + j;
+      if (p >= npix) continue;
+      float v = acc[jb][j];
+      if (EPI == 0) {
+        v += bias[co];
+        v = v > 0.f ? v : 0.f;
+        static_cast<u16*>(out)[p * COUT + co] = to_bf16(v);
+      } else if (EPI == 1) {
+        v += bias[co];
+        static_cast<float*>(out)[p * COUT + co] = v;
+      } else {
+        v = from_bf16(mask[p * COUT + co]) > 0.f ? v : 0.f;
+        static_cast<u16*>(out)[p * COUT + co] = to_bf16(v);
+      }
     }
   }
 }
@@ -341,8 +362,8 @@ template <int CIN, int COUT, int EPI>
 void conv(cond_cnn* n, const u16* in, const u16* wt, const float* bias, const u16* mask, void* out,
           int B, int S) {
   const long long npix = static_cast<long long>(B) * S * S;
-  dim3 grid(static_cast<unsigned>((npix + 15) / 16), COUT / 16);
-  conv_k<CIN, COUT, EPI><<<grid, 64, 0, n->stream>>>(in, wt, bias, mask, out, B, S);
+  const unsigned blocks = static_cast<unsigned>((npix + 16 * kConvWaves - 1) / (16 * kConvWaves));
+  conv_k<CIN, COUT, EPI><<<blocks, 64 * kConvWaves, 0, n->stream>>>(in, wt, bias, mask, out, B, S);
 }
 
 void forward(cond_cnn* n, int B, int S) {
