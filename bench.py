@@ -38,16 +38,21 @@ import numpy as np  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
-    "hm201": dict(kind="hm", side=201, seed=1, golden="hm_side201_seed1.json", min_route=True),
+    # alpha: initial Adam step, halved on each stop-rule plateau down to the
+    # floor (--alpha-min); single systems start large, the batch at 1e-2 since
+    # its slowest start sets its time and each halving costs a plateau
+    "hm201": dict(kind="hm", side=201, seed=1, golden="hm_side201_seed1.json", min_route=True,
+                  alpha=4e-2),
     # 6M rows: the sigma_max run (SpMV / A^T-SpMV / Adam) is the HBM roofline
     # measurement; the host LU of this system is not attempted
-    "hm1001": dict(kind="hm", side=1001, seed=2, golden=None, min_route=False),
+    "hm1001": dict(kind="hm", side=1001, seed=2, golden=None, min_route=False, alpha=4e-2),
     "stokes10": dict(kind="stokes", side=10, seed=0, golden="c1_stokes_10x10_seed0.json",
-                     min_route=True),
+                     min_route=True, alpha=1e-2),
     # 64 matrices, sides U{51..401}, perturbed copies of one base field, 8 starts each
-    "c4batch": dict(kind="batch", count=64, side_range=(51, 401), min_route=False),
+    "c4batch": dict(kind="batch", count=64, side_range=(51, 401), min_route=False, alpha=1e-2),
     # learned warm start: trained on small grids, tested on held-out 201x201 systems
-    "c5warm": dict(kind="warm", train=((51, 300), (101, 150)), test_side=201, min_route=True),
+    "c5warm": dict(kind="warm", train=((51, 300), (101, 150)), test_side=201, min_route=True,
+                   alpha=4e-2),
 }
 
 
@@ -69,7 +74,7 @@ def bench_warm(w, args):
     from synth import hm_fields, hydromech2d, start_vector
 
     opts = dict(max_iter=args.max_iter, stop_rtol=args.stop_rtol, stop_window=args.stop_window,
-                alpha_min=args.alpha_min, alpha_decay=0.5)
+                alpha=args.alpha, alpha_min=args.alpha_min, alpha_decay=0.5)
     lab_opts = dict(max_iter=4000, stop_rtol=1e-7, stop_window=50)
     t0 = time.perf_counter()
 
@@ -133,10 +138,13 @@ def bench_warm(w, args):
             fwd_ms.append(e0.elapsed_time(e1))
             cold = plan.run(xr, xr, **opts)
             warm = ws.run(plan, ft, xr, warm_alpha=args.warm_alpha, **opts)
-            # reference: both starts run long without the stop rule; their traces
-            # give the updates each needs to come within 1e-3 of the best value
-            ref_c = plan.run(None, xr, trace=True, x_best=True, max_iter=args.ref_iters)
-            ref_w = plan.run(None, xw, trace=True, max_iter=args.ref_iters, alpha=args.warm_alpha)
+            # reference: both starts run long at the floor step without the stop
+            # rule; their traces give the updates each needs to come within 1e-3
+            # of the best value
+            ref_a = args.alpha_min if args.alpha_min > 0 else args.alpha
+            ref_c = plan.run(None, xr, trace=True, x_best=True, max_iter=args.ref_iters,
+                             alpha=ref_a)
+            ref_w = plan.run(None, xw, trace=True, max_iter=args.ref_iters, alpha=ref_a)
             best = max(ref_c["trace_min"][-1], ref_w["trace_min"][-1],
                        1.0 / cold["sigma_min"], 1.0 / warm["sigma_min"])
             ub = ref_c["x_best_min"]
@@ -229,7 +237,7 @@ def bench_batch(w, args):
     print(f"[bench] batch: {len(mats)} matrices, rows {nrows}, nnz {nnz} ({gen_s:.0f}s)",
           file=sys.stderr, flush=True)
     opts = dict(max_iter=args.max_iter, stop_rtol=args.stop_rtol, stop_window=args.stop_window,
-                alpha_min=args.alpha_min, alpha_decay=0.5)
+                alpha=args.alpha, alpha_min=args.alpha_min, alpha_decay=0.5)
     t0 = time.perf_counter()
     b = pa.Batch([(m.n, m.rowptr, m.col, m.val) for m in mats], **opts).bind()
     torch.cuda.synchronize()
@@ -391,6 +399,8 @@ def main():
     ap.add_argument("--max-iter", type=int, default=6000)
     ap.add_argument("--stop-rtol", type=float, default=1e-6)
     ap.add_argument("--stop-window", type=int, default=25)
+    ap.add_argument("--alpha", type=float, default=None,
+                    help="initial Adam step size (default: the workload's)")
     ap.add_argument("--alpha-min", type=float, default=2.5e-3,
                     help="step-size floor: on a plateau alpha halves down to this (0: constant alpha)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -401,7 +411,7 @@ def main():
     ap.add_argument("--params-in", default=None, help="c5warm: trained parameters (.npy), no training")
     ap.add_argument("--params-out", default=None, help="c5warm: save the trained parameters (.npy)")
     ap.add_argument("--warm-alpha", type=float, default=1e-2, help="c5warm: alpha of the warm run")
-    ap.add_argument("--ref-iters", type=int, default=1500,
+    ap.add_argument("--ref-iters", type=int, default=2500,
                     help="c5warm: updates of the long reference runs without the stop rule")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -415,6 +425,8 @@ def main():
     from synth import start_vector
 
     w = WORKLOADS[args.workload]
+    if args.alpha is None:
+        args.alpha = w["alpha"]
     if w["kind"] == "batch":
         bench_batch(w, args)
         return
@@ -427,7 +439,7 @@ def main():
     print(f"[bench] workload {args.workload}: n={a.n} nnz={a.nnz} (generated in {gen_s:.1f}s)",
           file=sys.stderr, flush=True)
     opts = dict(max_iter=args.max_iter, stop_rtol=args.stop_rtol, stop_window=args.stop_window,
-                alpha_min=args.alpha_min, alpha_decay=0.5,
+                alpha=args.alpha, alpha_min=args.alpha_min, alpha_decay=0.5,
                 sigma_min_method=pa.COND_MIN_LU if w["min_route"] else pa.COND_MIN_NONE)
     t0 = time.perf_counter()
     plan = pa.Plan(a.n, a.rowptr, a.col, a.val, **opts)
@@ -484,7 +496,7 @@ def main():
         "config": {"workload": f"{args.workload}: six-field staggered-grid hydro-mechanical matrix"
                                if w["kind"] == "hm" else "tiny Stokes",
                    "n": a.n, "nnz": a.nnz, "nnz_l": res["nnz_l"], "nnz_u": res["nnz_u"],
-                   "alpha": 1e-2, "alpha_min": args.alpha_min, "max_iter": args.max_iter,
+                   "alpha": args.alpha, "alpha_min": args.alpha_min, "max_iter": args.max_iter,
                    "stop_rtol": args.stop_rtol, "stop_window": args.stop_window,
                    "parallelism": "single GPU"},
         "kappa": res["kappa"] if w["min_route"] else None,

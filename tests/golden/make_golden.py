@@ -15,7 +15,7 @@ Outputs (JSON, one file per workload):
   hm_side201_seed1.json        the 201x201-node hydro-mechanical system
                                (n = 242406), start vectors seeds 11 and 12:
                                the oracle's sigma_max, sigma_min and kappa
-                               with the benchmark's options (alpha 1e-2, step
+                               with the benchmark's options (alpha 4e-2, step
                                floor 2.5e-3, stop rule 1e-6 over 25), and a
                                reference from 3000 updates at a constant
                                alpha of 1.25e-3.
@@ -79,10 +79,10 @@ def main(which=("c1", "hm6")):
         a = hydromech2d(201, seed=1)
         x0a = start_vector(a.n, 11)
         x0b = start_vector(a.n, 12)
-        # (1) the benchmark's own options: step 1e-2 with a floor of 2.5e-3,
-        #     stop rule 1e-6 over 25 updates
-        bench = PAOptions(max_iter=6000, stop_rtol=1e-6, stop_window=25, alpha_min=2.5e-3,
-                          alpha_decay=0.5)
+        # (1) the benchmark's own options: step 4e-2 halving to a floor of
+        #     2.5e-3, stop rule 1e-6 over 25 updates
+        bench = PAOptions(alpha=4e-2, max_iter=6000, stop_rtol=1e-6, stop_window=25,
+                          alpha_min=2.5e-3, alpha_decay=0.5)
         r = estimate_cond(a.n, a.rowptr, a.col, a.val, x0a, x0b, opts=bench)
         # (2) reference: a constant small step (1.25e-3) for 3000 updates, no stop rule
         ref = PAOptions(alpha=1.25e-3, max_iter=3000)
@@ -90,7 +90,7 @@ def main(which=("c1", "hm6")):
         _write("hm_side201_seed1.json", {
             "workload": "hydromech2d(side=201, seed=1)", "n": a.n, "nnz": a.nnz,
             "starts": {"sigma_max": "start_vector(n, 11)", "sigma_min": "start_vector(n, 12)"},
-            "opts": {"alpha": 1e-2, "alpha_min": 2.5e-3, "alpha_decay": 0.5, "beta1": 0.9,
+            "opts": {"alpha": 4e-2, "alpha_min": 2.5e-3, "alpha_decay": 0.5, "beta1": 0.9,
                      "beta2": 0.999, "eps": 1e-8, "stop_rtol": 1e-6, "stop_window": 25,
                      "max_iter": 6000},
             "sigma_max": r["sigma_max"], "sigma_min": r["sigma_min"], "kappa": r["kappa"],

@@ -60,7 +60,8 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-@pytest.mark.parametrize("side,seeds", [(13, (1, 2, 3)), (4, (7,)), (37, (5, 6))])
+# 201: the full size of the warm-start workload (40401 pixels, a ragged last tile)
+@pytest.mark.parametrize("side,seeds", [(13, (1, 2, 3)), (4, (7,)), (37, (5, 6)), (201, (9,))])
 def test_forward_matches_oracle(torch_cuda, side, seeds):
     import paper_2409_11515_amd as pa
 
@@ -68,7 +69,7 @@ def test_forward_matches_oracle(torch_cuda, side, seeds):
     params = _params(11)
     cells = _fields(side, seeds)
     B = len(seeds)
-    net = pa.CNN(max_batch=4, max_side=40, train=False).set_params(cnn.flatten(params))
+    net = pa.CNN(max_batch=4, max_side=max(side, 40), train=False).set_params(cnn.flatten(params))
     x0 = net.predict(torch.as_tensor(cells, device="cuda")).cpu().numpy()
     ref = _oracle_forward(params, cells)
     unr = _oracle_forward(params, cells, rounded=False)
@@ -123,7 +124,7 @@ def _labels(side, seeds, seed):
     return np.ascontiguousarray(rng.standard_normal((len(seeds), 6 * side * side)).astype(np.float32))
 
 
-@pytest.mark.parametrize("side,seeds", [(13, (1, 2, 3)), (21, (4,))])
+@pytest.mark.parametrize("side,seeds", [(13, (1, 2, 3)), (21, (4,)), (201, (9,))])
 def test_gradients_match_oracle(torch_cuda, side, seeds):
     import paper_2409_11515_amd as pa
 
@@ -131,7 +132,7 @@ def test_gradients_match_oracle(torch_cuda, side, seeds):
     params = _params(12)
     cells = _fields(side, seeds)
     labels = _labels(side, seeds, 3)
-    net = pa.CNN(max_batch=4, max_side=32, train=True).set_params(cnn.flatten(params))
+    net = pa.CNN(max_batch=4, max_side=max(side, 32), train=True).set_params(cnn.flatten(params))
     g, losses = net.gradients(torch.as_tensor(cells, device="cuda"),
                               torch.as_tensor(labels, device="cuda"))
     g_ref, l_ref = _oracle_gradients(params, cells, labels)
