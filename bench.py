@@ -299,15 +299,21 @@ def make_matrix(w):
 
 
 def _trsv_source_hash():
-    """SHA-256 of the triangular-solve section of kernels.hip (the code the
-    counters in profiles/pmc_traffic.json were taken on)."""
+    """SHA-256 of the triangular-solve section of kernels.hip and of the panel
+    schedule in plan.hip (the code the counters in profiles/pmc_traffic.json
+    were taken on)."""
     import hashlib
 
-    with open(os.path.join(ROOT, "paper_2409_11515_amd", "csrc", "kernels.hip")) as f:
+    csrc = os.path.join(ROOT, "paper_2409_11515_amd", "csrc")
+    with open(os.path.join(csrc, "kernels.hip")) as f:
         src = f.read()
     a = src.index("// ----------------------------------------------------------------- trsv")
     b = src.index("// ---------------------------------------------------------- adam pass 1")
-    return hashlib.sha256(src[a:b].encode()).hexdigest()
+    with open(os.path.join(csrc, "plan.hip")) as f:
+        plan = f.read()
+    c = plan.index("constexpr int64_t kSliceEntries")
+    d = plan.index("// Row i -> n-1-i")
+    return hashlib.sha256((src[a:b] + plan[c:d]).encode()).hexdigest()
 
 
 def pmc_traffic(workload, kernel, factor_nnz):
@@ -515,6 +521,10 @@ def main():
         "spmv": spmv,
         "kernels": kernels,
     }
+    if w["min_route"]:
+        # panel schedule of each triangular solve: (dependency levels, tasks, panels)
+        out["trsv_schedule"] = {k: dict(zip(("levels", "tasks", "panels"), v))
+                                for k, v in plan.solve_info().items()}
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(a, res["iters_max"], res["iters_min"],

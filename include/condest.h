@@ -218,6 +218,13 @@ int cond_plan_run(cond_plan_t* plan, const cond_opts_t* o, const double* x0_max,
  * read or written once. */
 int cond_plan_kernel_stats(const cond_plan_t* plan, double* ms, int64_t* launches, double* bytes);
 
+/* Schedule of the four triangular solves of Algorithm 2 (order L, U, U^T,
+ * L^T; caller-allocated arrays of 4): dependency levels of the panel graph
+ * (its longest chain), tasks handed out per solve (whole panels, slices and
+ * finish steps) and panels. Host data, available after cond_plan_create;
+ * COND_EINVAL for a plan without the sigma_min route. */
+int cond_plan_solve_info(const cond_plan_t* plan, int32_t* levels, int64_t* tasks, int64_t* panels);
+
 /* One step of the path at a time, on device vectors of length n (for checks
  * against the oracle): y = A x; y = A^T x; r = A^-1 x and s = A^-T r
  * (Algorithm 2). Asynchronous on the plan's stream. */

@@ -189,6 +189,17 @@ class Plan:
               "plan_kernel_stats")
         return {name: (float(ms[i]), int(cnt[i]), float(by[i])) for i, name in enumerate(KERNEL_NAMES)}
 
+    def solve_info(self) -> dict:
+        """{solve: (levels, tasks, panels)} of the four triangular solves
+        (L, U, Ut, Lt): the panel schedule the planner chose."""
+        lv = np.zeros(4, np.int32)
+        tk = np.zeros(4, np.int64)
+        pn = np.zeros(4, np.int64)
+        check(lib().cond_plan_solve_info(self._h, lv.ctypes.data, tk.ctypes.data, pn.ctypes.data),
+              "plan_solve_info")
+        return {name: (int(lv[i]), int(tk[i]), int(pn[i]))
+                for i, name in enumerate(("L", "U", "Ut", "Lt"))}
+
     def spmv(self, x, transpose=False):
         import torch
 

@@ -86,14 +86,18 @@ constexpr int32_t kMaxSlices = kMaxSlicesDev;
 // it. Such a row usually opens an independent subtree of the elimination
 // order (a new leaf of the nested dissection); cutting there keeps independent
 // subtrees in different panels, so they are solved in parallel instead of as
-// a chain. A panel also closes at a 64-row boundary when the next row reads a
-// panel that is deeper in the dependency order than anything the open panel
-// reads: the panel's later sub-panels then never hold back its first one.
-// What remains inside a panel are chains (a dense separator block, mostly),
-// which one block solves sub-panel after sub-panel without waiting on others.
+// a chain. With `merge`, such a row instead joins the open panel when it reads
+// panels exactly as deep as the open panel does: it would run in the same
+// dependency level anyway, and one task fewer is cheaper than the parallelism
+// (the leaves of a nested dissection are thousands of panels of a few rows).
+// A panel also closes at a 64-row boundary when the next row reads a panel
+// that is deeper in the dependency order than anything the open panel reads:
+// the panel's later sub-panels then never hold back its first one. What
+// remains inside a panel are chains (a dense separator block, mostly), which
+// one block solves sub-panel after sub-panel without waiting on others.
 constexpr int32_t kMinPanelRows = 4;
 
-std::vector<int32_t> cut_panels(const HostCsr& t) {
+std::vector<int32_t> cut_panels(const HostCsr& t, bool merge) {
   std::vector<int32_t> ps{0};
   std::vector<int32_t> pid(t.n, 0), plevel;  // panel of each closed row, level of each panel
   int32_t s = 0;
@@ -111,7 +115,7 @@ std::vector<int32_t> cut_panels(const HostCsr& t) {
       needs_panel = t.col[p] >= s;
     const int32_t rows = e - s;
     const int32_t lv = ext_level(e);
-    if (rows >= kPanelRows || (!needs_panel && rows >= kMinPanelRows) ||
+    if (rows >= kPanelRows || (!needs_panel && rows >= kMinPanelRows && (!merge || lv != cur)) ||
         (rows % kPanel == 0 && lv > cur)) {
       const int32_t q = static_cast<int32_t>(plevel.size());
       for (int32_t i = s; i < e; ++i) pid[i] = q;
@@ -127,21 +131,60 @@ std::vector<int32_t> cut_panels(const HostCsr& t) {
   return ps;
 }
 
-PanelCsr split_panels(const HostCsr& t) {
-  PanelCsr s;
-  s.n = t.n;
-  s.pstart = cut_panels(t);
-  const int32_t np = static_cast<int32_t>(s.pstart.size()) - 1;
-  std::vector<int32_t> pid(t.n);
+// Level of each panel: one more than the deepest panel it reads from.
+std::vector<int32_t> panel_levels(const HostCsr& t, const std::vector<int32_t>& pstart,
+                                  std::vector<int32_t>& pid) {
+  const int32_t np = static_cast<int32_t>(pstart.size()) - 1;
+  pid.assign(t.n, 0);
   for (int32_t p = 0; p < np; ++p)
-    for (int32_t i = s.pstart[p]; i < s.pstart[p + 1]; ++i) pid[i] = p;
-  // level of a panel: one more than the deepest panel it reads from
+    for (int32_t i = pstart[p]; i < pstart[p + 1]; ++i) pid[i] = p;
   std::vector<int32_t> level(np, 0);
   for (int32_t i = 0; i < t.n; ++i)
     for (int64_t p = t.rowptr[i]; p < t.rowptr[i + 1]; ++p) {
       const int32_t q = pid[t.col[p]];
       if (q != pid[i]) level[pid[i]] = std::max(level[pid[i]], level[q] + 1);
     }
+  return level;
+}
+
+int32_t slices_of(int64_t work) {
+  return static_cast<int32_t>(std::min<int64_t>(kMaxSlices, (work + kSliceEntries - 1) / kSliceEntries));
+}
+
+// Estimated solve time of a cut, in microseconds: every dependency level
+// costs a wait-and-publish round trip, every task a fixed hand-out and
+// set-up cost spread over the resident blocks. Both constants are fits to
+// the measured solves of the four factor orientations of a 242k-row
+// hydro-mechanical system on MI355X (256 resident blocks).
+constexpr double kLevelUs = 4.9;
+constexpr double kTaskUs = 0.0148;
+
+double cut_cost(const HostCsr& t, const std::vector<int32_t>& pstart) {
+  std::vector<int32_t> pid;
+  const std::vector<int32_t> level = panel_levels(t, pstart, pid);
+  const int32_t np = static_cast<int32_t>(pstart.size()) - 1;
+  int64_t tasks = 0;
+  for (int32_t p = 0; p < np; ++p) {
+    int64_t work = 0;  // entries left of the panel
+    for (int32_t i = pstart[p]; i < pstart[p + 1]; ++i)
+      for (int64_t e = t.rowptr[i]; e < t.rowptr[i + 1]; ++e) work += t.col[e] < pstart[p];
+    const int32_t S = slices_of(work);
+    tasks += S > 1 ? S + 1 : 1;
+  }
+  const int32_t levels = np ? 1 + *std::max_element(level.begin(), level.end()) : 0;
+  return kLevelUs * levels + kTaskUs * static_cast<double>(tasks);
+}
+
+PanelCsr split_panels(const HostCsr& t) {
+  PanelCsr s;
+  s.n = t.n;
+  // the cheaper of the two cuts by the cost model (merging the leaves pays
+  // where they are many small panels, splitting where they are few)
+  std::vector<int32_t> split = cut_panels(t, false), merged = cut_panels(t, true);
+  s.pstart = cut_cost(t, merged) < cut_cost(t, split) ? std::move(merged) : std::move(split);
+  const int32_t np = static_cast<int32_t>(s.pstart.size()) - 1;
+  std::vector<int32_t> pid;
+  const std::vector<int32_t> level = panel_levels(t, s.pstart, pid);
   std::vector<int32_t> order(np);
   for (int32_t p = 0; p < np; ++p) order[p] = p;
   std::stable_sort(order.begin(), order.end(),
@@ -180,8 +223,7 @@ PanelCsr split_panels(const HostCsr& t) {
   s.panel_slot.assign(np, 0);
   for (int32_t p : order) {
     const int64_t work = s.off_rp[s.pstart[p + 1]] - s.off_rp[s.pstart[p]];
-    const int32_t S = static_cast<int32_t>(
-        std::min<int64_t>(kMaxSlices, (work + kSliceEntries - 1) / kSliceEntries));
+    const int32_t S = slices_of(work);
     if (S <= 1) {
       s.task_panel.push_back(p);
       s.task_kind.push_back(-1);
@@ -871,6 +913,18 @@ int cond_plan_kernel_stats(const cond_plan_t* p, double* ms, int64_t* launches, 
     ms[k] = p->kms[k];
     launches[k] = p->kcnt[k];
     if (bytes) bytes[k] = p->kcnt[k] ? p->kbytes[k] / static_cast<double>(p->kcnt[k]) : 0.0;
+  }
+  return COND_OK;
+}
+
+int cond_plan_solve_info(const cond_plan_t* p, int32_t* levels, int64_t* tasks, int64_t* panels) {
+  if (!p || !levels || !tasks || !panels) return fail(COND_EINVAL, "null argument");
+  if (!p->want_min) return fail(COND_EINVAL, "the plan has no sigma_min route");
+  const PanelCsr* tris[4] = {&p->pL, &p->pU, &p->pUt, &p->pLt};
+  for (int k = 0; k < 4; ++k) {
+    levels[k] = tris[k]->levels;
+    tasks[k] = static_cast<int64_t>(tris[k]->task_panel.size());
+    panels[k] = static_cast<int64_t>(tris[k]->pstart.size()) - 1;
   }
   return COND_OK;
 }

@@ -142,6 +142,23 @@ def test_plan_create_on_host_reports_workspace():
     p.close()
 
 
+def test_solve_schedule_on_host():
+    # the panel schedule is host data: a panel holds 1..64 rows, a level at
+    # least one panel, a panel at least one task (slices plus a finish step)
+    a = hydromech2d(40, seed=2)
+    p = pa.Plan(a.n, a.rowptr, a.col, a.val)
+    info = p.solve_info()
+    assert set(info) == {"L", "U", "Ut", "Lt"}
+    for levels, tasks, panels in info.values():
+        assert 1 <= levels <= panels <= tasks
+        assert -(-a.n // 64) <= panels <= a.n
+    p.close()
+    q = pa.Plan(a.n, a.rowptr, a.col, a.val, sigma_min_method=pa.COND_MIN_NONE)
+    with pytest.raises(_binding.CondError):
+        q.solve_info()
+    q.close()
+
+
 def test_batch_create_on_host():
     # batch set-up is host work: concatenation and workspace sizing
     mats = [hydromech2d(s, seed=s) for s in (5, 7, 6)]

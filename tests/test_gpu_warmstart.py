@@ -5,7 +5,8 @@ The network is trained from scratch on the device: plain sigma_min runs
 small seeded training systems, and Adam fits the network to them. On
 held-out systems the run from the predicted start must reach the plain
 run's ||A^-1||_2 estimate to 1e-3 in clearly fewer updates than the run
-from a random start, and the warm-started estimate (with its random-start
+from a random start on the same system (geometric mean of the ratios at
+most 0.6, ahead on at least 6 of 8 systems), and the warm-started estimate (with its random-start
 check and fallback) must agree with the plain one to 1e-3.
 """
 
@@ -78,4 +79,9 @@ def test_warm_start_needs_fewer_updates(trained):
         r = ws.run(plan, f, xr, max_iter=2000, stop_rtol=1e-7, stop_window=50)
         assert r["sigma_min"] == pytest.approx(plain["sigma_min"], rel=1e-3)
         plan.close()
-    assert np.median(warm_it) <= 0.6 * np.median(cold_it), (warm_it, cold_it)
+    # paired per system: the geometric mean of the ratios (the usual summary of
+    # speed-ups), and the warm start ahead on most systems
+    ratio = np.asarray(warm_it, float) / np.asarray(cold_it, float)
+    gmean = float(np.exp(np.mean(np.log(ratio))))
+    print("updates to 1e-3: warm", warm_it, "random", cold_it, "geometric mean ratio", gmean)
+    assert gmean <= 0.6 and np.sum(ratio < 1.0) >= 6, (warm_it, cold_it, gmean)
