@@ -298,41 +298,46 @@ def make_matrix(w):
     return stokes2d(w["side"], w["side"], seed=w["seed"])
 
 
-def _trsv_source_hash():
-    """SHA-256 of the triangular-solve section of kernels.hip and of the panel
-    schedule in plan.hip (the code the counters in profiles/pmc_traffic.json
-    were taken on)."""
+def _source_hash(kind):
+    """SHA-256 of the code a kernel family's counters in profiles/pmc_traffic.json
+    were taken on: for "trsv" the triangular-solve section of kernels.hip and
+    the panel schedule in plan.hip, for "spmv" the streaming SpMV section of
+    kernels.hip and the row tiles in plan.hip."""
     import hashlib
 
     csrc = os.path.join(ROOT, "paper_2409_11515_amd", "csrc")
     with open(os.path.join(csrc, "kernels.hip")) as f:
         src = f.read()
-    a = src.index("// ----------------------------------------------------------------- trsv")
-    b = src.index("// ---------------------------------------------------------- adam pass 1")
     with open(os.path.join(csrc, "plan.hip")) as f:
         plan = f.read()
-    c = plan.index("constexpr int64_t kSliceEntries")
-    d = plan.index("// Row i -> n-1-i")
-    return hashlib.sha256((src[a:b] + plan[c:d]).encode()).hexdigest()
+    if kind == "trsv":
+        parts = [src[src.index("// ----------------------------------------------------------------- trsv"):
+                     src.index("// ---------------------------------------------------------- adam pass 1")],
+                 plan[plan.index("constexpr int64_t kSliceEntries"):plan.index("// Row i -> n-1-i")]]
+    else:
+        parts = [src[src.index("// ---------------------------------------------------------- spmv (stream)"):
+                     src.index("// ---------------------------------------------------------------- sumsq")],
+                 plan[plan.index("// Row tiles for the streaming SpMV"):plan.index("int choose_lpr")]]
+    return hashlib.sha256("".join(parts).encode()).hexdigest()
 
 
-def pmc_traffic(workload, kernel, factor_nnz):
+def pmc_traffic(workload, kernel, key):
     """HBM bytes per launch of `kernel` from the committed counter runs
     (profiles/pmc_traffic.json), or None when they were taken on another
-    version of the kernel's source, on other LU factors (factor_nnz = the
-    fill of L and U) or not for this workload."""
+    version of the kernel's source, on other data (key: the fill of L and U
+    for the solves, n and nnz for the SpMV) or not for this workload."""
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
-    if not os.path.exists(path) or not kernel.startswith("trsv"):
+    if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if _trsv_source_hash() != rec.get("trsv_source_sha256"):
-        return None
     wl = rec.get("workloads", {}).get(workload, {})
-    if list(wl.get("factor_nnz", [])) != list(factor_nnz):
+    if kernel not in wl:
         return None
-    entry = wl.get(kernel)
-    return entry["traffic_bytes"] if entry else None
+    kind = "trsv" if kernel.startswith("trsv") else "spmv"
+    if wl.get("source_sha256") != _source_hash(kind) or list(wl.get("key", [])) != list(key):
+        return None
+    return wl[kernel]["traffic_bytes"]
 
 
 def golden(w):
@@ -486,6 +491,7 @@ def main():
     spmv = kernels.get("spmv_A")
 
     gk, gref = golden(w)
+    traffic_key = [res["nnz_l"], res["nnz_u"]] if dom.startswith("trsv") else [a.n, a.nnz]
     out = {
         "metric": "time-to-kappa (1e-3 rel) per matrix + SpMV HBM GB/s",
         "value": step_s,
@@ -516,7 +522,7 @@ def main():
         "run_ms": {"sigma_max": res["ms_max"], "sigma_min": res["ms_min"]},
         "setup_s": setup_s,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": pmc_traffic(args.workload, dom, [res["nnz_l"], res["nnz_u"]]),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": pmc_traffic(args.workload, dom, traffic_key),
                      "kernel": dom, "avg_us": avg_ms * 1e3, "alg_bytes_per_launch": byts},
         "spmv": spmv,
         "kernels": kernels,
