@@ -244,9 +244,11 @@ __global__ __launch_bounds__(kBlock) void sumsq_k(int n, const double* __restric
 // Off-panel sums: each wave takes 4 rows at once, 16 lanes per row, loads
 // unrolled for memory-level parallelism. A slice task stores its partial
 // sums into fixed slots; the finish task adds the slices in slice order, so
-// the result does not depend on timing. In-panel part: the triangle is
-// staged in LDS column-major and wave 0 runs the forward substitution column
-// by column, lane r owning row r.
+// the result does not depend on timing. In-panel part: the inverse of the
+// sub-panel's triangle, formed on the host, is staged in LDS before the
+// first wait, and once the sums are in the sub-panel's values are one
+// product with it, each row by its 16 lanes, instead of a substitution whose
+// 64 dependent steps sat on the critical path of every level.
 //
 // Solved values and slice partials are published by one 64-bit atomic store
 // each; until then a slot holds the kPending pattern, so the value is its
@@ -293,13 +295,6 @@ __device__ __forceinline__ void publish(double* p, double v) {
   __hip_atomic_store(reinterpret_cast<unsigned long long*>(p),
                      static_cast<unsigned long long>(__double_as_longlong(v)), __ATOMIC_RELAXED,
                      __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ double readlane_d(double v, int l) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane(static_cast<int>(b), l);
-  const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), l);
-  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
 }
 
 // Sum of off-panel entries [p0, p1) of one row against the solved values,
@@ -404,14 +399,15 @@ constexpr int kSubPanels = kPanelRows / kPanel;
 static_assert(kSubPanels == 1 || kSubPanels == 2, "one or two sub-panels per panel");
 constexpr int kLocalPerLane = kPanel / kLanesPerRow;  // entries of a row on the first sub-panel
 
-template <bool UNIT>
+constexpr int kLdW = kPanel + 1;  // LDS row stride of a staged inverse (padded against bank conflicts)
+
 __global__ __launch_bounds__(kTrsvBlock) void trsv_k(TrsvArgs t, const double* __restrict__ rhs,
                                                      const int* __restrict__ rhs_perm, double* out,
                                                      double* __restrict__ scatter,
                                                      const int* __restrict__ scatter_perm,
                                                      unsigned* ticket, RunState* st) {
-  // sub-panel triangles, column-major: (r, c) of sub-panel k at [k][c*64 + r]
-  __shared__ double m_sh[kSubPanels][kPanel * kPanel];
+  // inverse of sub-panel k's triangle, row-major: (r, c) at [k][r * kLdW + c]
+  __shared__ double w_sh[kSubPanels][kPanel * kLdW];
   __shared__ double t_sh[kPanelRows];  // off-panel sums (then minus the first sub-panel)
   __shared__ double b_sh[kPanelRows];  // right-hand side of the panel's rows
   __shared__ double x_sh[kPanel];      // solved values of the first sub-panel
@@ -471,8 +467,6 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_k(TrsvArgs t, const double* _
       continue;
     }
     // ---- everything that needs no solved value
-    for (int e = threadIdx.x; e < kSubPanels * kPanel * kPanel; e += kTrsvBlock) (&m_sh[0][0])[e] = 0.0;
-    __syncthreads();
     int lc[kLocalPerLane];
     double lv[kLocalPerLane];
 #pragma unroll
@@ -485,8 +479,8 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_k(TrsvArgs t, const double* _
       const int r = g + kPanel * j;
       if (r < cnt) {
         if (sub == 0) b_sh[r] = rhs_perm ? rhs[rhs_perm[lo + r]] : rhs[lo + r];
-        const long long e0 = t.in_rp[lo + r], em = t.in_split[lo + r], e1 = t.in_rp[lo + r + 1];
         if (j > 0) {  // entries on the first sub-panel: at most 64, four per lane
+          const long long e0 = t.in_rp[lo + r], em = t.in_split[lo + r];
 #pragma unroll
           for (int u = 0; u < kLocalPerLane; ++u) {
             const long long e = e0 + u * kLanesPerRow + sub;
@@ -494,18 +488,15 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_k(TrsvArgs t, const double* _
             lv[u] = e < em ? t.in_val[e] : 0.0;
           }
         }
-        // the sub-panel's own triangle: at most 63 entries, four per lane
-        int c[4];
-        double v[4];
+      }
+      // row g of the sub-panel's inverse, columns sub + 16 u (zero above the
+      // diagonal and past the sub-panel's last row)
+      const int ck = cnt - kPanel * j < kPanel ? cnt - kPanel * j : kPanel;
+      const double* w = t.winv + t.woff[P] + static_cast<long long>(j) * kTriPacked;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const long long e = em + u * kLanesPerRow + sub;
-          c[u] = e < e1 ? t.in_col[e] - kPanel * j : -1;
-          v[u] = e < e1 ? t.in_val[e] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (c[u] >= 0) m_sh[j][c[u] * kPanel + g] = v[u];
+      for (int u = 0; u < kLocalPerLane; ++u) {
+        const int c = sub + u * kLanesPerRow;
+        w_sh[j][g * kLdW + c] = (g < ck && c <= g) ? w[g * (g + 1) / 2 + c] : 0.0;
       }
     }
     // ---- off-panel sums of every row (these wait for the panel's inputs)
@@ -560,7 +551,7 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_k(TrsvArgs t, const double* _
     for (int j = 0; j < kSubPanels; ++j)
       if (g + kPanel * j < cnt && sub == 0) t_sh[g + kPanel * j] = sums[j];
     __syncthreads();
-    // ---- the sub-panels in order: forward substitution, lane l owns row k0 + l
+    // ---- the sub-panels in order: x = W (b - sums), row g by its 16 lanes
 #pragma unroll
     for (int j = 0; j < kSubPanels; ++j) {
       const int k0 = kPanel * j;
@@ -576,27 +567,19 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_k(TrsvArgs t, const double* _
         if (g < ck && sub == 0) t_sh[k0 + g] += acc;
         __syncthreads();
       }
-      if (wave == 0) {
-        double acc = 0.0, dinv = 1.0;
-        if (lane < ck) {
-          acc = b_sh[k0 + lane] - t_sh[k0 + lane];
-          if (!UNIT) dinv = 1.0 / t.diag[lo + k0 + lane];
-        }
-        double mine = 0.0;
-        double mnext = m_sh[j][lane];
-        for (int s = 0; s < ck; ++s) {
-          const double mcol = mnext;
-          if (s + 1 < ck) mnext = m_sh[j][(s + 1) * kPanel + lane];
-          const double xs = readlane_d(UNIT ? acc : acc * dinv, s);
-          if (lane == s) mine = xs;
-          if (lane > s) acc -= mcol * xs;
-        }
-        if (lane < ck) {
-          const long long i = lo + k0 + lane;
-          if (j == 0) x_sh[lane] = mine;
-          publish(out + i, mine);
-          if (scatter) scatter[scatter_perm[i]] = mine;
-        }
+      double acc = 0.0;
+#pragma unroll
+      for (int u = 0; u < kLocalPerLane; ++u) {
+        const int c = sub + u * kLanesPerRow;
+        if (c <= g && c < ck) acc += w_sh[j][g * kLdW + c] * (b_sh[k0 + c] - t_sh[k0 + c]);
+      }
+#pragma unroll
+      for (int off = kLanesPerRow / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kLanesPerRow);
+      if (g < ck && sub == 0) {
+        const long long i = lo + k0 + g;
+        if (j == 0) x_sh[g] = acc;
+        publish(out + i, acc);
+        if (scatter) scatter[scatter_perm[i]] = acc;
       }
       __syncthreads();  // x_sh feeds the next sub-panel; LDS and task_sh are reused
     }
@@ -809,10 +792,7 @@ void launch_trsv(const DevTri& t, const double* rhs, const int* rhs_perm, double
   long long blocks = t.ntasks < 512 ? t.ntasks : 512;
   if (blocks < 1) blocks = 1;
   const int g = static_cast<int>(blocks);
-  if (t.diag)
-    trsv_k<false><<<g, kTrsvBlock, 0, s>>>(t, rhs, rhs_perm, out, scatter, scatter_perm, ticket, st);
-  else
-    trsv_k<true><<<g, kTrsvBlock, 0, s>>>(t, rhs, rhs_perm, out, scatter, scatter_perm, ticket, st);
+  trsv_k<<<g, kTrsvBlock, 0, s>>>(t, rhs, rhs_perm, out, scatter, scatter_perm, ticket, st);
 }
 
 void launch_pass1(int n, const double* x, const double* w, double* m, double* v, double* d,

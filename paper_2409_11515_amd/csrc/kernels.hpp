@@ -87,6 +87,7 @@ constexpr long long kTileEntriesHost = 2048;
 constexpr int kPanel = 64;       // rows of a sub-panel: one wave solves its triangle
 constexpr int kMaxSlicesDev = 64;  // most slices a heavy panel is cut into
 constexpr int kPanelRows = 64;   // rows of a panel: its sub-panels are solved in order by one block
+constexpr int kTriPacked = kPanel * (kPanel + 1) / 2;  // entries of a packed 64-row triangle
 struct DevTri {
   int n = 0;
   const long long* off_rp = nullptr;
@@ -97,7 +98,11 @@ struct DevTri {
   const long long* in_split = nullptr;  // per row: first in-panel entry inside its own sub-panel
   const int* in_col = nullptr;          // in-panel columns, relative to the panel's first row
   const double* in_val = nullptr;
-  const double* diag = nullptr;  // nullptr: unit diagonal
+  // inverse of each sub-panel's triangle (its own in-panel entries and the
+  // diagonal, unit for L), lower rows packed: (r, c) at r (r + 1) / 2 + c;
+  // sub-panel j of panel p at winv + woff[p] + j * kTriPacked
+  const double* winv = nullptr;
+  const long long* woff = nullptr;
   const int* pstart = nullptr;   // panel p holds rows [pstart[p], pstart[p+1])
   const int* panel_split = nullptr;
   const int* panel_slot = nullptr;  // first partial-sum slot (kPanelRows doubles each) of a split panel

@@ -68,6 +68,10 @@ struct PanelCsr {
   std::vector<int32_t> pstart;  // panel p holds rows [pstart[p], pstart[p+1])
   std::vector<int32_t> panel_split, panel_slot;  // slices per panel, first slot of a split panel
   std::vector<int32_t> task_panel, task_kind;    // tasks in dependency-level order
+  // inverse of each sub-panel's triangle, lower rows packed; panel p's
+  // sub-panel j at winv[woff[p] + j * kTriPacked]
+  std::vector<double> winv;
+  std::vector<int64_t> woff;
   int32_t levels = 0;
   int32_t nslots = 0;
 };
@@ -153,11 +157,12 @@ int32_t slices_of(int64_t work) {
 
 // Estimated solve time of a cut, in microseconds: every dependency level
 // costs a wait-and-publish round trip, every task a fixed hand-out and
-// set-up cost spread over the resident blocks. Both constants are fits to
-// the measured solves of the four factor orientations of a 242k-row
-// hydro-mechanical system on MI355X (256 resident blocks).
-constexpr double kLevelUs = 4.9;
-constexpr double kTaskUs = 0.0148;
+// set-up cost spread over the resident blocks. Both constants are a
+// least-squares fit to eight measured solves on MI355X (256 resident
+// blocks): the four factor orientations of a 242k-row hydro-mechanical
+// system, each cut both ways.
+constexpr double kLevelUs = 2.5;
+constexpr double kTaskUs = 0.0152;
 
 double cut_cost(const HostCsr& t, const std::vector<int32_t>& pstart) {
   std::vector<int32_t> pid;
@@ -244,6 +249,49 @@ PanelCsr split_panels(const HostCsr& t) {
     }
   }
   return s;
+}
+
+// The inverse of every sub-panel's triangle: its own in-panel entries below
+// the diagonal and diag (nullptr: a unit diagonal) on it, inverted column by
+// column by substitution in float64. The kernel then forms a sub-panel's
+// values as one product with it instead of 64 dependent steps.
+void invert_panels(PanelCsr& s, const double* diag) {
+  const int32_t np = static_cast<int32_t>(s.pstart.size()) - 1;
+  s.woff.assign(np, 0);
+  int64_t total = 0;
+  for (int32_t p = 0; p < np; ++p) {
+    s.woff[p] = total;
+    const int32_t cnt = s.pstart[p + 1] - s.pstart[p];
+    for (int32_t k0 = 0; k0 < cnt; k0 += kPanel) {
+      const int64_t ck = std::min(kPanel, cnt - k0);
+      total += ck * (ck + 1) / 2;
+    }
+  }
+  s.winv.assign(total, 0.0);
+  std::vector<double> t(kPanel * kPanel), w(kPanel * kPanel);
+  for (int32_t p = 0; p < np; ++p) {
+    const int32_t lo = s.pstart[p], cnt = s.pstart[p + 1] - lo;
+    for (int32_t k0 = 0, j = 0; k0 < cnt; k0 += kPanel, ++j) {
+      const int32_t ck = std::min(kPanel, cnt - k0);
+      // the sub-panel's triangle, dense: strictly lower entries, then the diagonal
+      std::fill(t.begin(), t.end(), 0.0);
+      for (int32_t r = 0; r < ck; ++r) {
+        const int32_t i = lo + k0 + r;
+        for (int64_t e = s.in_split[i]; e < s.in_rp[i + 1]; ++e) t[r * kPanel + (s.in_col[e] - k0)] = s.in_val[e];
+        t[r * kPanel + r] = diag ? diag[i] : 1.0;
+      }
+      std::fill(w.begin(), w.end(), 0.0);
+      for (int32_t c = 0; c < ck; ++c)
+        for (int32_t r = c; r < ck; ++r) {
+          double a = r == c ? 1.0 : 0.0;
+          for (int32_t k = c; k < r; ++k) a -= t[r * kPanel + k] * w[k * kPanel + c];
+          w[r * kPanel + c] = a / t[r * kPanel + r];
+        }
+      double* out = s.winv.data() + s.woff[p] + static_cast<int64_t>(j) * kTriPacked;
+      for (int32_t r = 0; r < ck; ++r)
+        for (int32_t c = 0; c <= r; ++c) out[r * (r + 1) / 2 + c] = w[r * kPanel + c];
+    }
+  }
 }
 
 // Row i -> n-1-i and column j -> n-1-j: an upper factor becomes lower.
@@ -340,8 +388,8 @@ struct cond_plan {
   // offsets into the workspace
   struct {
     size_t a_rp, a_col, a_val, at_rp, at_col, at_val, a_tiles, at_tiles;
-    size_t tri[4][14];
-    size_t u_diag, u_diag_rev, row_perm, rev, scat_s, scat_r;
+    size_t tri[4][16];
+    size_t row_perm, rev, scat_s, scat_r;
     size_t vec[10];
     size_t parts[4];
     size_t st, st_free, tickets;
@@ -383,9 +431,9 @@ void plan_layout(cond_plan* p) {
       p->o.tri[f][11] = L.take(t.task_kind.size() * 4);
       p->o.tri[f][12] = L.take(static_cast<size_t>(n) * 8);
       p->o.tri[f][13] = L.take(static_cast<size_t>(n) * 8);
+      p->o.tri[f][14] = L.take(t.winv.size() * 8);
+      p->o.tri[f][15] = L.take(t.woff.size() * 8);
     }
-    p->o.u_diag = L.take(n * 8);
-    p->o.u_diag_rev = L.take(n * 8);
     p->o.row_perm = L.take(n * 4);
     p->o.rev = L.take(n * 4);
     p->o.scat_s = L.take(n * 4);
@@ -438,8 +486,7 @@ int upload_csr(cond_plan* p, const HostCsr& a, size_t rp, size_t col, size_t val
   return COND_OK;
 }
 
-int upload_tri(cond_plan* p, const PanelCsr& t, const size_t* off, const double* diag_dev,
-               DevTri& out) {
+int upload_tri(cond_plan* p, const PanelCsr& t, const size_t* off, DevTri& out) {
   int st;
   if ((st = upload(p, off[0], t.off_rp.data(), (t.n + 1) * 8))) return st;
   if ((st = upload(p, off[1], t.off_col.data(), t.off_col.size() * 4))) return st;
@@ -454,6 +501,8 @@ int upload_tri(cond_plan* p, const PanelCsr& t, const size_t* off, const double*
   if ((st = upload(p, off[11], t.task_kind.data(), t.task_kind.size() * 4))) return st;
   if ((st = upload(p, off[12], t.in_split.data(), static_cast<size_t>(t.n) * 8))) return st;
   if ((st = upload(p, off[13], t.off_split.data(), static_cast<size_t>(t.n) * 8))) return st;
+  if ((st = upload(p, off[14], t.winv.data(), t.winv.size() * 8))) return st;
+  if ((st = upload(p, off[15], t.woff.data(), t.woff.size() * 8))) return st;
   if (t.nslots > 0) launch_fill(t.nslots * kPanelRows, at_off<double>(p, off[9]), kPending, p->stream);
   out.n = t.n;
   out.off_rp = at_off<long long>(p, off[0]);
@@ -464,7 +513,8 @@ int upload_tri(cond_plan* p, const PanelCsr& t, const size_t* off, const double*
   out.off_split = at_off<long long>(p, off[13]);
   out.in_col = at_off<int>(p, off[4]);
   out.in_val = at_off<double>(p, off[5]);
-  out.diag = diag_dev;
+  out.winv = at_off<double>(p, off[14]);
+  out.woff = at_off<long long>(p, off[15]);
   out.pstart = at_off<int>(p, off[6]);
   out.panel_split = at_off<int>(p, off[7]);
   out.panel_slot = at_off<int>(p, off[8]);
@@ -755,6 +805,10 @@ int cond_plan_create(const cond_csr_t* A, const cond_opts_t* o, cond_plan_t** ou
         p->scat_s[k] = f.row_perm[n - 1 - k];
         p->scat_r[k] = f.col_perm[n - 1 - k];
       }
+      invert_panels(p->pL, nullptr);
+      invert_panels(p->pU, p->udiag_rev.data());
+      invert_panels(p->pUt, f.u_diag.data());
+      invert_panels(p->pLt, nullptr);
     }
   } catch (const std::bad_alloc&) {
     return fail(COND_ENOMEM, "host memory exhausted in set-up");
@@ -806,18 +860,14 @@ int cond_plan_bind(cond_plan_t* p, void* workspace, size_t bytes, void* stream) 
     return st;
   if (p->want_min) {
     const cond_lu& f = *p->lu;
-    if ((st = upload(p, p->o.u_diag, f.u_diag.data(), p->n * 8))) return st;
-    if ((st = upload(p, p->o.u_diag_rev, p->udiag_rev.data(), p->n * 8))) return st;
     if ((st = upload(p, p->o.row_perm, f.row_perm.data(), p->n * 4))) return st;
     if ((st = upload(p, p->o.rev, p->rev.data(), p->n * 4))) return st;
     if ((st = upload(p, p->o.scat_s, p->scat_s.data(), p->n * 4))) return st;
     if ((st = upload(p, p->o.scat_r, p->scat_r.data(), p->n * 4))) return st;
-    const double* dg = at_off<double>(p, p->o.u_diag);
-    const double* dgr = at_off<double>(p, p->o.u_diag_rev);
-    if ((st = upload_tri(p, p->pL, p->o.tri[0], nullptr, p->dL))) return st;
-    if ((st = upload_tri(p, p->pU, p->o.tri[1], dgr, p->dU))) return st;
-    if ((st = upload_tri(p, p->pUt, p->o.tri[2], dg, p->dUt))) return st;
-    if ((st = upload_tri(p, p->pLt, p->o.tri[3], nullptr, p->dLt))) return st;
+    if ((st = upload_tri(p, p->pL, p->o.tri[0], p->dL))) return st;
+    if ((st = upload_tri(p, p->pU, p->o.tri[1], p->dU))) return st;
+    if ((st = upload_tri(p, p->pUt, p->o.tri[2], p->dUt))) return st;
+    if ((st = upload_tri(p, p->pLt, p->o.tri[3], p->dLt))) return st;
     p->d_row_perm = at_off<int>(p, p->o.row_perm);
     p->d_rev = at_off<int>(p, p->o.rev);
     p->d_scat_s = at_off<int>(p, p->o.scat_s);
