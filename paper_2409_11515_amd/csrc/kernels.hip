@@ -428,12 +428,16 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_k(TrsvArgs t, const double* _
     __syncthreads();
     const unsigned T = task_sh;
     if (T >= static_cast<unsigned>(t.ntasks)) break;
-    const int P = t.task_panel[T];
-    const int kind = t.task_kind[T];  // -1 whole panel, 0..S-1 slice, S finish
-    const long long lo = t.pstart[P];
-    const int cnt = t.pstart[P + 1] - t.pstart[P];
-    const int S = t.panel_split[P];
-    double* slots = t.partials + static_cast<long long>(t.panel_slot[P]) * kPanelRows;
+    // the task's record: one round trip instead of the task list and then
+    // the panel's own arrays
+    const int4 ra = reinterpret_cast<const int4*>(t.task_rec)[2 * static_cast<long long>(T)];
+    const int4 rb = reinterpret_cast<const int4*>(t.task_rec)[2 * static_cast<long long>(T) + 1];
+    const int P = ra.x;
+    const int kind = ra.y;  // -1 whole panel, 0..S-1 slice, S finish
+    const long long lo = ra.z;
+    const int cnt = ra.w;
+    const int S = rb.x;
+    double* slots = t.partials + static_cast<long long>(rb.y) * kPanelRows;
     long long q0[kSubPanels], q1[kSubPanels];  // the group's rows g + 64 j: off-panel ranges
 #pragma unroll
     for (int j = 0; j < kSubPanels; ++j) {

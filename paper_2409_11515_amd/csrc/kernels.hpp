@@ -110,6 +110,9 @@ struct DevTri {
   int ntasks = 0;
   const int* task_panel = nullptr;
   const int* task_kind = nullptr;
+  // per task, 8 ints (two 16-byte loads): panel, kind, first row, rows,
+  // slices, first partial-sum slot, 0, 0
+  const int* task_rec = nullptr;
 };
 using TrsvArgs = DevTri;
 

@@ -68,6 +68,7 @@ struct PanelCsr {
   std::vector<int32_t> pstart;  // panel p holds rows [pstart[p], pstart[p+1])
   std::vector<int32_t> panel_split, panel_slot;  // slices per panel, first slot of a split panel
   std::vector<int32_t> task_panel, task_kind;    // tasks in dependency-level order
+  std::vector<int32_t> task_rec;  // per task: panel, kind, first row, rows, slices, slot, 0, 0
   // inverse of each sub-panel's triangle, lower rows packed; panel p's
   // sub-panel j at winv[woff[p] + j * kTriPacked]
   std::vector<double> winv;
@@ -248,6 +249,13 @@ PanelCsr split_panels(const HostCsr& t) {
       s.task_kind.push_back(k);
     }
   }
+  s.task_rec.reserve(8 * s.task_panel.size());
+  for (size_t k = 0; k < s.task_panel.size(); ++k) {
+    const int32_t p = s.task_panel[k];
+    const int32_t rec[8] = {p, s.task_kind[k], s.pstart[p], s.pstart[p + 1] - s.pstart[p],
+                            s.panel_split[p], s.panel_slot[p], 0, 0};
+    s.task_rec.insert(s.task_rec.end(), rec, rec + 8);
+  }
   return s;
 }
 
@@ -388,7 +396,7 @@ struct cond_plan {
   // offsets into the workspace
   struct {
     size_t a_rp, a_col, a_val, at_rp, at_col, at_val, a_tiles, at_tiles;
-    size_t tri[4][16];
+    size_t tri[4][17];
     size_t row_perm, rev, scat_s, scat_r;
     size_t vec[10];
     size_t parts[4];
@@ -433,6 +441,7 @@ void plan_layout(cond_plan* p) {
       p->o.tri[f][13] = L.take(static_cast<size_t>(n) * 8);
       p->o.tri[f][14] = L.take(t.winv.size() * 8);
       p->o.tri[f][15] = L.take(t.woff.size() * 8);
+      p->o.tri[f][16] = L.take(t.task_rec.size() * 4);
     }
     p->o.row_perm = L.take(n * 4);
     p->o.rev = L.take(n * 4);
@@ -503,6 +512,7 @@ int upload_tri(cond_plan* p, const PanelCsr& t, const size_t* off, DevTri& out) 
   if ((st = upload(p, off[13], t.off_split.data(), static_cast<size_t>(t.n) * 8))) return st;
   if ((st = upload(p, off[14], t.winv.data(), t.winv.size() * 8))) return st;
   if ((st = upload(p, off[15], t.woff.data(), t.woff.size() * 8))) return st;
+  if ((st = upload(p, off[16], t.task_rec.data(), t.task_rec.size() * 4))) return st;
   if (t.nslots > 0) launch_fill(t.nslots * kPanelRows, at_off<double>(p, off[9]), kPending, p->stream);
   out.n = t.n;
   out.off_rp = at_off<long long>(p, off[0]);
@@ -522,6 +532,7 @@ int upload_tri(cond_plan* p, const PanelCsr& t, const size_t* off, DevTri& out) 
   out.ntasks = static_cast<int>(t.task_panel.size());
   out.task_panel = at_off<int>(p, off[10]);
   out.task_kind = at_off<int>(p, off[11]);
+  out.task_rec = at_off<int>(p, off[16]);
   return COND_OK;
 }
 
