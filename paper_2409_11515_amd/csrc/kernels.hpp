@@ -93,8 +93,9 @@ struct DevTri {
   const long long* off_rp = nullptr;
   const int* off_col = nullptr;
   const double* off_val = nullptr;
-  const long long* in_rp = nullptr;
   const long long* off_split = nullptr;  // per row of a sliced panel: first entry the finish adds
+  // in-panel entries (read only for a second sub-panel's entries on the first)
+  const long long* in_rp = nullptr;
   const long long* in_split = nullptr;  // per row: first in-panel entry inside its own sub-panel
   const int* in_col = nullptr;          // in-panel columns, relative to the panel's first row
   const double* in_val = nullptr;
@@ -103,15 +104,11 @@ struct DevTri {
   // sub-panel j of panel p at winv + woff[p] + j * kTriPacked
   const double* winv = nullptr;
   const long long* woff = nullptr;
-  const int* pstart = nullptr;   // panel p holds rows [pstart[p], pstart[p+1])
-  const int* panel_split = nullptr;
-  const int* panel_slot = nullptr;  // first partial-sum slot (kPanelRows doubles each) of a split panel
-  double* partials = nullptr;       // kPending when idle
+  double* partials = nullptr;  // slice partial sums, kPanelRows doubles per slot; kPending when idle
   int ntasks = 0;
-  const int* task_panel = nullptr;
-  const int* task_kind = nullptr;
-  // per task, 8 ints (two 16-byte loads): panel, kind, first row, rows,
-  // slices, first partial-sum slot, 0, 0
+  // per task, in dependency-level order, 8 ints (two 16-byte loads): panel,
+  // kind (-1 whole panel, 0..S-1 slice, S finish), first row, rows, slices
+  // S, first partial-sum slot, 0, 0
   const int* task_rec = nullptr;
 };
 using TrsvArgs = DevTri;

@@ -43,6 +43,12 @@ struct Layout {
   }
 };
 
+// Device arrays of one solve's panel structure (offsets into the workspace).
+enum TriSlot {
+  kOffRp, kOffCol, kOffVal, kOffSplit, kInRp, kInSplit, kInCol, kInVal,
+  kPartials, kWinv, kWoff, kTaskRec, kTriSlots
+};
+
 struct GraphKey {
   int route = -1;
   int chunk = 0;
@@ -396,7 +402,7 @@ struct cond_plan {
   // offsets into the workspace
   struct {
     size_t a_rp, a_col, a_val, at_rp, at_col, at_val, a_tiles, at_tiles;
-    size_t tri[4][17];
+    size_t tri[4][kTriSlots];
     size_t row_perm, rev, scat_s, scat_r;
     size_t vec[10];
     size_t parts[4];
@@ -425,23 +431,21 @@ void plan_layout(cond_plan* p) {
     const PanelCsr* tris[4] = {&p->pL, &p->pU, &p->pUt, &p->pLt};
     for (int f = 0; f < 4; ++f) {
       const PanelCsr& t = *tris[f];
-      p->o.tri[f][0] = L.take((n + 1) * 8);
-      p->o.tri[f][1] = L.take(t.off_col.size() * 4);
-      p->o.tri[f][2] = L.take(t.off_val.size() * 8);
-      p->o.tri[f][3] = L.take((n + 1) * 8);
-      p->o.tri[f][4] = L.take(t.in_col.size() * 4);
-      p->o.tri[f][5] = L.take(t.in_val.size() * 8);
-      p->o.tri[f][6] = L.take(t.pstart.size() * 4);
-      p->o.tri[f][7] = L.take(t.panel_split.size() * 4);
-      p->o.tri[f][8] = L.take(t.panel_slot.size() * 4);
-      p->o.tri[f][9] = L.take(static_cast<size_t>(t.nslots) * kPanelRows * 8);
-      p->o.tri[f][10] = L.take(t.task_panel.size() * 4);
-      p->o.tri[f][11] = L.take(t.task_kind.size() * 4);
-      p->o.tri[f][12] = L.take(static_cast<size_t>(n) * 8);
-      p->o.tri[f][13] = L.take(static_cast<size_t>(n) * 8);
-      p->o.tri[f][14] = L.take(t.winv.size() * 8);
-      p->o.tri[f][15] = L.take(t.woff.size() * 8);
-      p->o.tri[f][16] = L.take(t.task_rec.size() * 4);
+      size_t* o = p->o.tri[f];
+      o[kOffRp] = L.take((n + 1) * 8);
+      o[kOffCol] = L.take(t.off_col.size() * 4);
+      o[kOffVal] = L.take(t.off_val.size() * 8);
+      o[kOffSplit] = L.take(static_cast<size_t>(n) * 8);
+      // in-panel entries: read only for a second sub-panel's entries on the first
+      const bool in_entries = kPanelRows > kPanel;
+      o[kInRp] = L.take(in_entries ? (n + 1) * 8 : 0);
+      o[kInSplit] = L.take(in_entries ? static_cast<size_t>(n) * 8 : 0);
+      o[kInCol] = L.take(in_entries ? t.in_col.size() * 4 : 0);
+      o[kInVal] = L.take(in_entries ? t.in_val.size() * 8 : 0);
+      o[kPartials] = L.take(static_cast<size_t>(t.nslots) * kPanelRows * 8);
+      o[kWinv] = L.take(t.winv.size() * 8);
+      o[kWoff] = L.take(t.woff.size() * 8);
+      o[kTaskRec] = L.take(t.task_rec.size() * 4);
     }
     p->o.row_perm = L.take(n * 4);
     p->o.rev = L.take(n * 4);
@@ -497,42 +501,34 @@ int upload_csr(cond_plan* p, const HostCsr& a, size_t rp, size_t col, size_t val
 
 int upload_tri(cond_plan* p, const PanelCsr& t, const size_t* off, DevTri& out) {
   int st;
-  if ((st = upload(p, off[0], t.off_rp.data(), (t.n + 1) * 8))) return st;
-  if ((st = upload(p, off[1], t.off_col.data(), t.off_col.size() * 4))) return st;
-  if ((st = upload(p, off[2], t.off_val.data(), t.off_val.size() * 8))) return st;
-  if ((st = upload(p, off[3], t.in_rp.data(), (t.n + 1) * 8))) return st;
-  if ((st = upload(p, off[4], t.in_col.data(), t.in_col.size() * 4))) return st;
-  if ((st = upload(p, off[5], t.in_val.data(), t.in_val.size() * 8))) return st;
-  if ((st = upload(p, off[6], t.pstart.data(), t.pstart.size() * 4))) return st;
-  if ((st = upload(p, off[7], t.panel_split.data(), t.panel_split.size() * 4))) return st;
-  if ((st = upload(p, off[8], t.panel_slot.data(), t.panel_slot.size() * 4))) return st;
-  if ((st = upload(p, off[10], t.task_panel.data(), t.task_panel.size() * 4))) return st;
-  if ((st = upload(p, off[11], t.task_kind.data(), t.task_kind.size() * 4))) return st;
-  if ((st = upload(p, off[12], t.in_split.data(), static_cast<size_t>(t.n) * 8))) return st;
-  if ((st = upload(p, off[13], t.off_split.data(), static_cast<size_t>(t.n) * 8))) return st;
-  if ((st = upload(p, off[14], t.winv.data(), t.winv.size() * 8))) return st;
-  if ((st = upload(p, off[15], t.woff.data(), t.woff.size() * 8))) return st;
-  if ((st = upload(p, off[16], t.task_rec.data(), t.task_rec.size() * 4))) return st;
-  if (t.nslots > 0) launch_fill(t.nslots * kPanelRows, at_off<double>(p, off[9]), kPending, p->stream);
+  if ((st = upload(p, off[kOffRp], t.off_rp.data(), (t.n + 1) * 8))) return st;
+  if ((st = upload(p, off[kOffCol], t.off_col.data(), t.off_col.size() * 4))) return st;
+  if ((st = upload(p, off[kOffVal], t.off_val.data(), t.off_val.size() * 8))) return st;
+  if ((st = upload(p, off[kOffSplit], t.off_split.data(), static_cast<size_t>(t.n) * 8))) return st;
+  if (kPanelRows > kPanel) {
+    if ((st = upload(p, off[kInRp], t.in_rp.data(), (t.n + 1) * 8))) return st;
+    if ((st = upload(p, off[kInSplit], t.in_split.data(), static_cast<size_t>(t.n) * 8))) return st;
+    if ((st = upload(p, off[kInCol], t.in_col.data(), t.in_col.size() * 4))) return st;
+    if ((st = upload(p, off[kInVal], t.in_val.data(), t.in_val.size() * 8))) return st;
+  }
+  if ((st = upload(p, off[kWinv], t.winv.data(), t.winv.size() * 8))) return st;
+  if ((st = upload(p, off[kWoff], t.woff.data(), t.woff.size() * 8))) return st;
+  if ((st = upload(p, off[kTaskRec], t.task_rec.data(), t.task_rec.size() * 4))) return st;
+  if (t.nslots > 0) launch_fill(t.nslots * kPanelRows, at_off<double>(p, off[kPartials]), kPending, p->stream);
   out.n = t.n;
-  out.off_rp = at_off<long long>(p, off[0]);
-  out.off_col = at_off<int>(p, off[1]);
-  out.off_val = at_off<double>(p, off[2]);
-  out.in_rp = at_off<long long>(p, off[3]);
-  out.in_split = at_off<long long>(p, off[12]);
-  out.off_split = at_off<long long>(p, off[13]);
-  out.in_col = at_off<int>(p, off[4]);
-  out.in_val = at_off<double>(p, off[5]);
-  out.winv = at_off<double>(p, off[14]);
-  out.woff = at_off<long long>(p, off[15]);
-  out.pstart = at_off<int>(p, off[6]);
-  out.panel_split = at_off<int>(p, off[7]);
-  out.panel_slot = at_off<int>(p, off[8]);
-  out.partials = at_off<double>(p, off[9]);
+  out.off_rp = at_off<long long>(p, off[kOffRp]);
+  out.off_col = at_off<int>(p, off[kOffCol]);
+  out.off_val = at_off<double>(p, off[kOffVal]);
+  out.off_split = at_off<long long>(p, off[kOffSplit]);
+  out.in_rp = at_off<long long>(p, off[kInRp]);
+  out.in_split = at_off<long long>(p, off[kInSplit]);
+  out.in_col = at_off<int>(p, off[kInCol]);
+  out.in_val = at_off<double>(p, off[kInVal]);
+  out.winv = at_off<double>(p, off[kWinv]);
+  out.woff = at_off<long long>(p, off[kWoff]);
+  out.partials = at_off<double>(p, off[kPartials]);
+  out.task_rec = at_off<int>(p, off[kTaskRec]);
   out.ntasks = static_cast<int>(t.task_panel.size());
-  out.task_panel = at_off<int>(p, off[10]);
-  out.task_kind = at_off<int>(p, off[11]);
-  out.task_rec = at_off<int>(p, off[16]);
   return COND_OK;
 }
 
