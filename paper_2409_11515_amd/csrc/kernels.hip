@@ -391,10 +391,11 @@ __device__ __forceinline__ void row_sums(const long long* p0, const long long* p
 
 // A panel of up to kPanelRows rows is solved by one block as kSubPanels
 // sub-panels of 64 rows. Everything that does not depend on solved values --
-// the right-hand side, each sub-panel's triangle (into LDS) and the entries of
-// the second sub-panel on the first (into registers) -- is loaded before the
-// first wait, so that once the panel's inputs are published only the
-// off-panel sums, the short LDS steps and the substitutions remain.
+// the right-hand side, the inverse of each sub-panel's triangle (into LDS)
+// and the entries of the second sub-panel on the first (into registers) --
+// is loaded before the first wait, so that once the panel's inputs are
+// published only the off-panel sums and the short products with the
+// inverses remain.
 constexpr int kSubPanels = kPanelRows / kPanel;
 static_assert(kSubPanels == 1 || kSubPanels == 2, "one or two sub-panels per panel");
 constexpr int kLocalPerLane = kPanel / kLanesPerRow;  // entries of a row on the first sub-panel
