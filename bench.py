@@ -317,7 +317,7 @@ def _source_hash(kind):
     else:
         parts = [src[src.index("// ---------------------------------------------------------- spmv (stream)"):
                      src.index("// ---------------------------------------------------------------- sumsq")],
-                 plan[plan.index("// Row tiles for the streaming SpMV"):plan.index("int choose_lpr")]]
+                 plan[plan.index("// Row tiles for the streaming SpMV"):plan.index("}  // namespace\n\nstruct cond_plan")]]
     return hashlib.sha256("".join(parts).encode()).hexdigest()
 
 

@@ -121,39 +121,6 @@ __global__ __launch_bounds__(kBlock) void normalise_k(int n, double* __restrict_
   if (blockIdx.x == 0 && threadIdx.x < ntickets) tickets[threadIdx.x] = 0u;
 }
 
-// ----------------------------------------------------------------- spmv
-// y = A x, vector CSR: LPR lanes per row, partial sums of y.y per block.
-template <int LPR, typename IT>
-__global__ __launch_bounds__(kBlock) void spmv_k(int n, const IT* __restrict__ rowptr,
-                                                 const int* __restrict__ col,
-                                                 const double* __restrict__ val,
-                                                 const double* __restrict__ x, double* __restrict__ y,
-                                                 double* __restrict__ parts, const RunState* st) {
-  if (st && st->stop_req) return;
-  constexpr int kGroups = kBlock / LPR;
-  const int lb = logical_block();
-  long long r0, r1;
-  block_range(n, lb, r0, r1);
-  const int lane = threadIdx.x % LPR;
-  const int grp = threadIdx.x / LPR;
-  double sq = 0.0;
-  for (long long r = r0 + grp; r < r1; r += kGroups) {
-    const IT p0 = rowptr[r], p1 = rowptr[r + 1];
-    double acc = 0.0;
-    for (IT p = p0 + lane; p < p1; p += LPR) acc += val[p] * x[col[p]];
-#pragma unroll
-    for (int off = LPR / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, LPR);
-    if (lane == 0) {
-      y[r] = acc;
-      sq += acc * acc;
-    }
-  }
-  if (parts) {
-    const double s = block_sum(sq);
-    if (threadIdx.x == 0) parts[lb] = s;
-  }
-}
-
 // ---------------------------------------------------------- spmv (stream)
 // y = A x by row tiles: the host cuts the rows into tiles of at most 256 rows
 // and kStreamCap entries (a longer row is a tile of its own). A block streams
@@ -732,19 +699,6 @@ __global__ void zero_u32_k(unsigned* p, int count) {
   if (i < count) p[i] = 0u;
 }
 
-template <typename IT>
-void spmv_dispatch(const DevCsr& a, const double* x, double* y, double* parts, int grid,
-                   const RunState* st, hipStream_t s) {
-  const IT* rp = static_cast<const IT*>(a.rowptr);
-  switch (a.lpr) {
-    case 4: spmv_k<4, IT><<<grid, kBlock, 0, s>>>(a.n, rp, a.col, a.val, x, y, parts, st); break;
-    case 8: spmv_k<8, IT><<<grid, kBlock, 0, s>>>(a.n, rp, a.col, a.val, x, y, parts, st); break;
-    case 16: spmv_k<16, IT><<<grid, kBlock, 0, s>>>(a.n, rp, a.col, a.val, x, y, parts, st); break;
-    case 32: spmv_k<32, IT><<<grid, kBlock, 0, s>>>(a.n, rp, a.col, a.val, x, y, parts, st); break;
-    default: spmv_k<64, IT><<<grid, kBlock, 0, s>>>(a.n, rp, a.col, a.val, x, y, parts, st); break;
-  }
-}
-
 }  // namespace
 
 int grid_for(int n) {
@@ -771,19 +725,12 @@ void launch_normalise(int n, double* x, const double* parts_xx, int grid, double
 
 void launch_spmv(const DevCsr& a, const double* x, double* y, double* parts_y, int grid,
                  const RunState* st, hipStream_t s) {
-  if (a.tiles) {
-    if (a.idx64)
-      spmv_stream_k<long long><<<grid, kBlock, 0, s>>>(
-          a.ntiles, a.tiles, static_cast<const long long*>(a.rowptr), a.col, a.val, x, y, parts_y, st);
-    else
-      spmv_stream_k<int><<<grid, kBlock, 0, s>>>(a.ntiles, a.tiles, static_cast<const int*>(a.rowptr),
-                                                 a.col, a.val, x, y, parts_y, st);
-    return;
-  }
   if (a.idx64)
-    spmv_dispatch<long long>(a, x, y, parts_y, grid, st, s);
+    spmv_stream_k<long long><<<grid, kBlock, 0, s>>>(
+        a.ntiles, a.tiles, static_cast<const long long*>(a.rowptr), a.col, a.val, x, y, parts_y, st);
   else
-    spmv_dispatch<int>(a, x, y, parts_y, grid, st, s);
+    spmv_stream_k<int><<<grid, kBlock, 0, s>>>(a.ntiles, a.tiles, static_cast<const int*>(a.rowptr),
+                                               a.col, a.val, x, y, parts_y, st);
 }
 
 void launch_sumsq(int n, const double* z, double* parts, int grid, const RunState* st,

@@ -65,9 +65,8 @@ struct DevCsr {
   int idx64 = 0;
   const int* col = nullptr;
   const double* val = nullptr;
-  int lpr = 8;  // lanes per row for the vector-CSR SpMV (power of two, 4..64)
-  // row tiles for the streaming SpMV (nullptr: vector CSR): tile t holds rows
-  // [tiles[t], tiles[t+1]), at most 256 rows and 2048 entries unless one row
+  // row tiles of the streaming SpMV: tile t holds rows [tiles[t],
+  // tiles[t+1]), at most 256 rows and 2048 entries unless one row
   const int* tiles = nullptr;
   int ntiles = 0;
 };

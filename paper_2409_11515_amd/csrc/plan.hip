@@ -342,12 +342,6 @@ std::vector<int32_t> make_tiles(const HostCsr& a) {
   return t;
 }
 
-int choose_lpr(double mean_nnz_per_row) {
-  int l = 4;
-  while (l < 64 && l < mean_nnz_per_row) l <<= 1;
-  return l;
-}
-
 }  // namespace
 
 struct cond_plan {
@@ -492,7 +486,6 @@ int upload_csr(cond_plan* p, const HostCsr& a, size_t rp, size_t col, size_t val
   out.idx64 = idx64 ? 1 : 0;
   out.col = at_off<int>(p, col);
   out.val = at_off<double>(p, val);
-  out.lpr = choose_lpr(static_cast<double>(a.nnz()) / std::max(1, a.n));
   if ((st = upload(p, tiles_off, tiles.data(), tiles.size() * 4))) return st;
   out.tiles = at_off<int>(p, tiles_off);
   out.ntiles = static_cast<int>(tiles.size()) - 1;
