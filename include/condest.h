@@ -225,6 +225,15 @@ int cond_plan_kernel_stats(const cond_plan_t* plan, double* ms, int64_t* launche
  * COND_EINVAL for a plan without the sigma_min route. */
 int cond_plan_solve_info(const cond_plan_t* plan, int32_t* levels, int64_t* tasks, int64_t* panels);
 
+/* Algorithm 2's r = A^-1 x and s = A^-T r (x, r, s: host arrays of length
+ * n, caller-owned) computed on the host from the same device-ready data the
+ * four solves run on -- panels, packed inverses of the sub-panel triangles,
+ * right-hand-side gathers and output scatters -- in the order the device
+ * applies them. For checking the solve schedule without a device; available
+ * after cond_plan_create. COND_EINVAL for a plan without the sigma_min route,
+ * COND_ENOMEM if host scratch cannot be allocated. */
+int cond_plan_solve_replay(const cond_plan_t* plan, const double* x, double* r, double* s);
+
 /* One step of the path at a time, on device vectors of length n (for checks
  * against the oracle): y = A x; y = A^T x; r = A^-1 x and s = A^-T r
  * (Algorithm 2). Asynchronous on the plan's stream. */

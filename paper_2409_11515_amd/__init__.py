@@ -200,6 +200,16 @@ class Plan:
         return {name: (int(lv[i]), int(tk[i]), int(pn[i]))
                 for i, name in enumerate(("L", "U", "Ut", "Lt"))}
 
+    def solve_replay(self, x):
+        """(r, s) = (A^-1 x, A^-T r) on the host from the device-ready solve
+        schedule (numpy float64 in and out); needs no device."""
+        x = np.ascontiguousarray(x, np.float64)
+        r = np.empty_like(x)
+        s = np.empty_like(x)
+        check(lib().cond_plan_solve_replay(self._h, x.ctypes.data, r.ctypes.data, s.ctypes.data),
+              "plan_solve_replay")
+        return r, s
+
     def spmv(self, x, transpose=False):
         import torch
 

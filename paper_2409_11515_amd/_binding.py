@@ -67,6 +67,7 @@ EXPORTS = (
     "cond_lu_export", "cond_lu_solve_host", "cond_plan_create", "cond_plan_workspace_bytes",
     "cond_plan_bind", "cond_plan_destroy", "cond_plan_run", "cond_plan_spmv",
     "cond_plan_inverse_apply", "cond_estimate", "cond_plan_kernel_stats", "cond_plan_solve_info",
+    "cond_plan_solve_replay",
     "cond_batch_create",
     "cond_batch_info", "cond_batch_bind", "cond_batch_run", "cond_batch_destroy",
     "cond_cnn_param_count", "cond_cnn_create", "cond_cnn_set_params", "cond_cnn_get_params",
@@ -116,6 +117,7 @@ def lib():
     L.cond_estimate.argtypes = [C.POINTER(CsrT), C.POINTER(OptsT), vp, vp, vp, C.POINTER(ResultT)]
     L.cond_plan_kernel_stats.argtypes = [vp, vp, vp, vp]
     L.cond_plan_solve_info.argtypes = [vp, vp, vp, vp]
+    L.cond_plan_solve_replay.argtypes = [vp, vp, vp, vp]
     L.cond_batch_create.argtypes = [vp, i32, C.POINTER(OptsT), C.POINTER(vp)]
     L.cond_batch_info.argtypes = [vp, vp, C.POINTER(C.c_size_t), C.POINTER(i32), C.POINTER(i32)]
     L.cond_batch_bind.argtypes = [vp, vp, C.c_size_t, vp, i32, i32]

@@ -979,6 +979,59 @@ int cond_plan_solve_info(const cond_plan_t* p, int32_t* levels, int64_t* tasks, 
   return COND_OK;
 }
 
+namespace {
+
+// One solve as the device runs it, on the host: panels in order, each row's
+// right-hand side gathered, its off-panel entries subtracted, a second
+// sub-panel's entries on the first subtracted, then each sub-panel's values
+// as the product with its packed triangle inverse.
+void replay_solve(const PanelCsr& t, const int32_t* gather, const double* in, double* out) {
+  const int32_t np = static_cast<int32_t>(t.pstart.size()) - 1;
+  std::vector<double> acc(kPanelRows);
+  for (int32_t q = 0; q < np; ++q) {
+    const int32_t lo = t.pstart[q], cnt = t.pstart[q + 1] - lo;
+    for (int32_t r = 0; r < cnt; ++r) {
+      const int32_t i = lo + r;
+      double a = in[gather ? gather[i] : i];
+      for (int64_t e = t.off_rp[i]; e < t.off_rp[i + 1]; ++e) a -= t.off_val[e] * out[t.off_col[e]];
+      acc[r] = a;
+    }
+    for (int32_t k0 = 0, j = 0; k0 < cnt; k0 += kPanel, ++j) {
+      const int32_t ck = std::min(kPanel, cnt - k0);
+      for (int32_t r = 0; r < ck && j > 0; ++r) {
+        const int32_t i = lo + k0 + r;
+        for (int64_t e = t.in_rp[i]; e < t.in_split[i]; ++e) acc[k0 + r] -= t.in_val[e] * out[lo + t.in_col[e]];
+      }
+      const double* w = t.winv.data() + t.woff[q] + static_cast<int64_t>(j) * kTriPacked;
+      for (int32_t r = 0; r < ck; ++r) {
+        double x = 0.0;
+        for (int32_t c = 0; c <= r; ++c) x += w[r * (r + 1) / 2 + c] * acc[k0 + c];
+        out[lo + k0 + r] = x;
+      }
+    }
+  }
+}
+
+}  // namespace
+
+int cond_plan_solve_replay(const cond_plan_t* p, const double* x, double* r, double* s) {
+  if (!p || !x || !r || !s) return fail(COND_EINVAL, "null argument");
+  if (!p->want_min) return fail(COND_EINVAL, "the plan has no sigma_min route");
+  try {
+    const int32_t n = p->n;
+    std::vector<double> c(n), z(n), h(n), wv(n);
+    replay_solve(p->pL, p->lu->row_perm.data(), x, c.data());
+    replay_solve(p->pU, p->rev.data(), c.data(), z.data());
+    for (int32_t k = 0; k < n; ++k) r[p->scat_r[k]] = z[k];
+    replay_solve(p->pUt, p->rev.data(), z.data(), h.data());
+    replay_solve(p->pLt, p->rev.data(), h.data(), wv.data());
+    for (int32_t k = 0; k < n; ++k) s[p->scat_s[k]] = wv[k];
+  } catch (const std::bad_alloc&) {
+    return fail(COND_ENOMEM, "host memory exhausted");
+  }
+  return COND_OK;
+}
+
 int cond_plan_spmv(cond_plan_t* p, int transpose, const double* x, double* y) {
   if (!p || !x || !y) return fail(COND_EINVAL, "null argument");
   if (!p->bound) return fail(COND_ESTATE, "plan not bound");

@@ -159,6 +159,32 @@ def test_solve_schedule_on_host():
     q.close()
 
 
+@pytest.mark.parametrize("mk,bound", [(lambda: stokes2d(10, 10, seed=0), 1e-9),
+                                      (lambda: hydromech2d(30, seed=3), 1e-9),
+                                      (lambda: hydromech2d(61, seed=5), 1e-9),
+                                      (lambda: hydromech2d(201, seed=1), 1e-6)])
+def test_solve_schedule_replayed_on_host(mk, bound):
+    # the data the device solves run on (panels, packed inverses of the
+    # sub-panel triangles, gathers, scatters), applied on the host in the
+    # device's order, solve the system: componentwise backward errors, and
+    # agreement with the oracle's SuperLU solves (two pivoted factorisations)
+    from oracle.inverse import LUInverse
+
+    a = mk()
+    p = pa.Plan(a.n, a.rowptr, a.col, a.val)
+    x = start_vector(a.n, 2)
+    r, s = p.solve_replay(x)
+    p.close()
+    A = a.to_scipy()
+    be_r = np.max(np.abs(A @ r - x) / (abs(A) @ np.abs(r) + np.abs(x)))
+    be_s = np.max(np.abs(A.T @ s - r) / (abs(A.T) @ np.abs(s) + np.abs(r)))
+    assert be_r < bound and be_s < bound, (be_r, be_s)
+    if a.n <= 30000:
+        r_ref, s_ref = LUInverse(a.n, a.rowptr, a.col, a.val).apply(x)
+        assert np.linalg.norm(r - r_ref) <= 1e-6 * np.linalg.norm(r_ref)
+        assert np.linalg.norm(s - s_ref) <= 1e-6 * np.linalg.norm(s_ref)
+
+
 def test_batch_create_on_host():
     # batch set-up is host work: concatenation and workspace sizing
     mats = [hydromech2d(s, seed=s) for s in (5, 7, 6)]
