@@ -17,7 +17,7 @@ import scipy.sparse as sp
 import paper_2409_11515_amd as pa
 from paper_2409_11515_amd import _binding
 from oracle.csr import transpose_csr
-from synth import Csr, hydromech2d, scaled_banded, stokes2d, start_vector
+from synth import Csr, csr_from_dense, diag_csr, hydromech2d, scaled_banded, stokes2d, start_vector
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -159,7 +159,22 @@ def test_solve_schedule_on_host():
     q.close()
 
 
-@pytest.mark.parametrize("mk,bound", [(lambda: stokes2d(10, 10, seed=0), 1e-9),
+def _dense(n, seed):
+    rng = np.random.default_rng(seed)
+    return csr_from_dense(rng.standard_normal((n, n)) + 2.0 * np.sqrt(n) * np.eye(n))
+
+
+def _perm_diag(n, seed):
+    rng = np.random.default_rng(seed)
+    return diag_csr(10.0 ** rng.uniform(-6, 6, n), row_perm=rng.permutation(n),
+                    col_perm=rng.permutation(n))
+
+
+@pytest.mark.parametrize("mk,bound", [(lambda: csr_from_dense(np.array([[3.0]])), 1e-15),
+                                      (lambda: _perm_diag(50, 1), 1e-15),
+                                      (lambda: scaled_banded(300, seed=1), 1e-12),
+                                      (lambda: _dense(300, 2), 1e-12),
+                                      (lambda: stokes2d(10, 10, seed=0), 1e-9),
                                       (lambda: hydromech2d(30, seed=3), 1e-9),
                                       (lambda: hydromech2d(61, seed=5), 1e-9),
                                       (lambda: hydromech2d(201, seed=1), 1e-6)])
@@ -167,7 +182,9 @@ def test_solve_schedule_replayed_on_host(mk, bound):
     # the data the device solves run on (panels, packed inverses of the
     # sub-panel triangles, gathers, scatters), applied on the host in the
     # device's order, solve the system: componentwise backward errors, and
-    # agreement with the oracle's SuperLU solves (two pivoted factorisations)
+    # agreement with the oracle's SuperLU solves (two pivoted factorisations).
+    # Edge cases: a 1x1 matrix, a permuted diagonal (one level, one panel),
+    # banded and dense matrices (full panels, sliced panels at 300x300)
     from oracle.inverse import LUInverse
 
     a = mk()
