@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <future>
 #include <memory>
 #include <new>
 #include <string>
@@ -791,10 +792,6 @@ int cond_plan_create(const cond_csr_t* A, const cond_opts_t* o, cond_plan_t** ou
       if (st) return st;
       const cond_lu& f = *p->lu;
       const int32_t n = f.n;
-      p->pL = split_panels(f.l_rows);
-      p->pU = split_panels(reverse_order(f.u_rows));
-      p->pUt = split_panels(f.u_cols);
-      p->pLt = split_panels(reverse_order(f.l_cols));
       p->udiag_rev.resize(n);
       p->rev.resize(n);
       p->scat_s.resize(n);
@@ -805,10 +802,23 @@ int cond_plan_create(const cond_csr_t* A, const cond_opts_t* o, cond_plan_t** ou
         p->scat_s[k] = f.row_perm[n - 1 - k];
         p->scat_r[k] = f.col_perm[n - 1 - k];
       }
-      invert_panels(p->pL, nullptr);
-      invert_panels(p->pU, p->udiag_rev.data());
-      invert_panels(p->pUt, f.u_diag.data());
-      invert_panels(p->pLt, nullptr);
+      // the four schedules are independent host work, one thread each; each
+      // is the same computation as on one thread
+      auto sched = [](const HostCsr& t, const double* diag) {
+        PanelCsr s = split_panels(t);
+        invert_panels(s, diag);
+        return s;
+      };
+      std::future<PanelCsr> fut[4] = {
+          std::async(std::launch::async, [&] { return sched(f.l_rows, nullptr); }),
+          std::async(std::launch::async,
+                     [&] { return sched(reverse_order(f.u_rows), p->udiag_rev.data()); }),
+          std::async(std::launch::async, [&] { return sched(f.u_cols, f.u_diag.data()); }),
+          std::async(std::launch::async, [&] { return sched(reverse_order(f.l_cols), nullptr); })};
+      p->pL = fut[0].get();  // get() rethrows a thread's exception
+      p->pU = fut[1].get();
+      p->pUt = fut[2].get();
+      p->pLt = fut[3].get();
     }
   } catch (const std::bad_alloc&) {
     return fail(COND_ENOMEM, "host memory exhausted in set-up");
