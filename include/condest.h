@@ -47,7 +47,9 @@ extern "C" {
                                sigma_min = 0 and kappa = +inf are reported */
 #define COND_ENOMEM (-3)    /* host allocation failed or the workspace is too small */
 #define COND_EHIP (-4)      /* a HIP runtime call failed */
-#define COND_ENUMERIC (-5)  /* a norm became zero or non-finite during the iteration */
+#define COND_ENUMERIC (-5)  /* a norm became zero or non-finite during the iteration, or
+                               (cond_plan_create) a diagonal block of the LU factors
+                               has no finite float64 inverse */
 #define COND_ESTATE (-6)    /* entry points called out of order (e.g. run before bind) */
 #define COND_ETIMEOUT (-7)  /* a triangular-solve wait exceeded its spin limit */
 

@@ -100,7 +100,7 @@ const char* cond_strerror(int status) {
     case COND_ESINGULAR: return "matrix is singular (zero pivot)";
     case COND_ENOMEM: return "out of memory or workspace too small";
     case COND_EHIP: return "HIP runtime error";
-    case COND_ENUMERIC: return "norm became zero or non-finite";
+    case COND_ENUMERIC: return "norm became zero or non-finite, or a factor block has no finite inverse";
     case COND_ESTATE: return "call out of order";
     case COND_ETIMEOUT: return "triangular-solve wait exceeded its spin limit";
     default: return "unknown status";

@@ -819,6 +819,12 @@ int cond_plan_create(const cond_csr_t* A, const cond_opts_t* o, cond_plan_t** ou
       p->pU = fut[1].get();
       p->pUt = fut[2].get();
       p->pLt = fut[3].get();
+      // a diagonal block whose inverse overflows float64 would turn every
+      // solve into NaN: refuse the plan instead
+      for (const PanelCsr* t : {&p->pL, &p->pU, &p->pUt, &p->pLt})
+        for (double w : t->winv)
+          if (!std::isfinite(w))
+            return fail(COND_ENUMERIC, "a diagonal block of the LU factors has no finite float64 inverse");
     }
   } catch (const std::bad_alloc&) {
     return fail(COND_ENOMEM, "host memory exhausted in set-up");
