@@ -229,11 +229,14 @@ int cond_plan_solve_info(const cond_plan_t* plan, int32_t* levels, int64_t* task
 
 /* Algorithm 2's r = A^-1 x and s = A^-T r (x, r, s: host arrays of length
  * n, caller-owned) computed on the host from the same device-ready data the
- * four solves run on -- panels, packed inverses of the sub-panel triangles,
- * right-hand-side gathers and output scatters -- in the order the device
- * applies them. For checking the solve schedule without a device; available
- * after cond_plan_create. COND_EINVAL for a plan without the sigma_min route,
- * COND_ENOMEM if host scratch cannot be allocated. */
+ * four solves run on -- task records, slices and their partial-sum slots,
+ * packed inverses of the sub-panel triangles, right-hand-side gathers and
+ * output scatters -- taking the tasks in ticket order. For checking the
+ * solve schedule without a device; available after cond_plan_create.
+ * COND_ESTATE if a task would read a value that only a later ticket solves,
+ * or a slot no slice wrote (the device would then wait on work handed out
+ * after it); COND_EINVAL for a plan without the sigma_min route; COND_ENOMEM
+ * if host scratch cannot be allocated. */
 int cond_plan_solve_replay(const cond_plan_t* plan, const double* x, double* r, double* s);
 
 /* One step of the path at a time, on device vectors of length n (for checks

@@ -997,20 +997,59 @@ int cond_plan_solve_info(const cond_plan_t* p, int32_t* levels, int64_t* tasks, 
 
 namespace {
 
-// One solve as the device runs it, on the host: panels in order, each row's
-// right-hand side gathered, its off-panel entries subtracted, a second
-// sub-panel's entries on the first subtracted, then each sub-panel's values
-// as the product with its packed triangle inverse.
-void replay_solve(const PanelCsr& t, const int32_t* gather, const double* in, double* out) {
-  const int32_t np = static_cast<int32_t>(t.pstart.size()) - 1;
+// One solve as the device runs it, on the host: the tasks in ticket order,
+// read from the same task records; a slice task sums its share of each row's
+// older off-panel entries into its slot, a finish task adds the slots in
+// order and the newest entries, a whole-panel task all off-panel entries;
+// then a second sub-panel's entries on the first come off, and each
+// sub-panel's values are the product with its packed triangle inverse.
+// Every value a task reads must have been solved by an earlier ticket (the
+// condition under which every wait on the device ends) and every slot a
+// finish step reads must have been written; otherwise the schedule is
+// reported broken (returns false).
+bool replay_solve(const PanelCsr& t, const int32_t* gather, const double* in, double* out) {
+  const int32_t n = t.n;
+  std::vector<char> ready(n, 0);
+  std::vector<double> slots(static_cast<size_t>(t.nslots) * kPanelRows, 0.0);
+  std::vector<char> slot_set(static_cast<size_t>(t.nslots) * kPanelRows, 0);
   std::vector<double> acc(kPanelRows);
-  for (int32_t q = 0; q < np; ++q) {
-    const int32_t lo = t.pstart[q], cnt = t.pstart[q + 1] - lo;
+  bool ok = true;
+  auto sum = [&](int64_t e0, int64_t e1) {
+    double a = 0.0;
+    for (int64_t e = e0; e < e1; ++e) {
+      ok = ok && ready[t.off_col[e]];
+      a += t.off_val[e] * out[t.off_col[e]];
+    }
+    return a;
+  };
+  const size_t ntasks = t.task_rec.size() / 8;
+  for (size_t k = 0; k < ntasks && ok; ++k) {
+    const int32_t* rec = &t.task_rec[8 * k];
+    const int32_t q = rec[0], kind = rec[1], lo = rec[2], cnt = rec[3], S = rec[4], slot = rec[5];
+    if (kind >= 0 && kind < S) {  // slice
+      for (int32_t r = 0; r < cnt; ++r) {
+        const int64_t q0 = t.off_rp[lo + r], len = t.off_split[lo + r] - q0;
+        const size_t at = static_cast<size_t>(slot + kind) * kPanelRows + r;
+        slots[at] = sum(q0 + len * kind / S, q0 + len * (kind + 1) / S);
+        slot_set[at] = 1;
+      }
+      continue;
+    }
     for (int32_t r = 0; r < cnt; ++r) {
       const int32_t i = lo + r;
-      double a = in[gather ? gather[i] : i];
-      for (int64_t e = t.off_rp[i]; e < t.off_rp[i + 1]; ++e) a -= t.off_val[e] * out[t.off_col[e]];
-      acc[r] = a;
+      double sums;
+      if (kind < 0) {
+        sums = sum(t.off_rp[i], t.off_rp[i + 1]);
+      } else {  // finish
+        sums = 0.0;
+        for (int32_t m = 0; m < S; ++m) {
+          const size_t at = static_cast<size_t>(slot + m) * kPanelRows + r;
+          ok = ok && slot_set[at];
+          sums += slots[at];
+        }
+        sums += sum(t.off_split[i], t.off_rp[i + 1]);
+      }
+      acc[r] = in[gather ? gather[i] : i] - sums;
     }
     for (int32_t k0 = 0, j = 0; k0 < cnt; k0 += kPanel, ++j) {
       const int32_t ck = std::min(kPanel, cnt - k0);
@@ -1023,9 +1062,12 @@ void replay_solve(const PanelCsr& t, const int32_t* gather, const double* in, do
         double x = 0.0;
         for (int32_t c = 0; c <= r; ++c) x += w[r * (r + 1) / 2 + c] * acc[k0 + c];
         out[lo + k0 + r] = x;
+        ready[lo + k0 + r] = 1;
       }
     }
   }
+  for (int32_t i = 0; i < n && ok; ++i) ok = ready[i];
+  return ok;
 }
 
 }  // namespace
@@ -1036,11 +1078,12 @@ int cond_plan_solve_replay(const cond_plan_t* p, const double* x, double* r, dou
   try {
     const int32_t n = p->n;
     std::vector<double> c(n), z(n), h(n), wv(n);
-    replay_solve(p->pL, p->lu->row_perm.data(), x, c.data());
-    replay_solve(p->pU, p->rev.data(), c.data(), z.data());
+    const bool ok = replay_solve(p->pL, p->lu->row_perm.data(), x, c.data()) &&
+                    replay_solve(p->pU, p->rev.data(), c.data(), z.data()) &&
+                    replay_solve(p->pUt, p->rev.data(), z.data(), h.data()) &&
+                    replay_solve(p->pLt, p->rev.data(), h.data(), wv.data());
+    if (!ok) return fail(COND_ESTATE, "solve schedule reads a value before its ticket is solved");
     for (int32_t k = 0; k < n; ++k) r[p->scat_r[k]] = z[k];
-    replay_solve(p->pUt, p->rev.data(), z.data(), h.data());
-    replay_solve(p->pLt, p->rev.data(), h.data(), wv.data());
     for (int32_t k = 0; k < n; ++k) s[p->scat_s[k]] = wv[k];
   } catch (const std::bad_alloc&) {
     return fail(COND_ENOMEM, "host memory exhausted");

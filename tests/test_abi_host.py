@@ -179,10 +179,12 @@ def _perm_diag(n, seed):
                                       (lambda: hydromech2d(61, seed=5), 1e-9),
                                       (lambda: hydromech2d(201, seed=1), 1e-6)])
 def test_solve_schedule_replayed_on_host(mk, bound):
-    # the data the device solves run on (panels, packed inverses of the
-    # sub-panel triangles, gathers, scatters), applied on the host in the
-    # device's order, solve the system: componentwise backward errors, and
-    # agreement with the oracle's SuperLU solves (two pivoted factorisations).
+    # the data the device solves run on (task records, slices and slots,
+    # packed inverses of the sub-panel triangles, gathers, scatters), with
+    # the tasks taken in ticket order, solve the system: componentwise
+    # backward errors, and agreement with the oracle's SuperLU solves (two
+    # pivoted factorisations). The replay itself refuses a schedule in
+    # which a task reads a value that a later ticket solves.
     # Edge cases: a 1x1 matrix, a permuted diagonal (one level, one panel),
     # banded and dense matrices (full panels, sliced panels at 300x300)
     from oracle.inverse import LUInverse
