@@ -15,6 +15,9 @@ the method:
                   factorisation (SciPy's SuperLU, or a dense LU for tiny
                   matrices);
 * ``estimate`` -- kappa_2 = sigma_max / sigma_min from the two runs;
+* ``ablation`` -- not the paper's method: sigma_min by descending on
+                  ||A x|| / ||x|| with products alone (the comparison that
+                  shows why the paper needs Algorithm 2);
 * ``exact``    -- closed forms and extended-precision singular values used to
                   pin the oracle itself.
 """

@@ -6,8 +6,8 @@ sigma_min: Algorithm 1 with M = A^-1 through Algorithm 2 (one LU), giving
 matrix", equation for kappa_2 via singular values).
 
 Optional ablation, not the paper's method: ``min_method="spmv"`` minimises
-||A x||/||x|| directly with the same optimiser (gradient sign flipped),
-which the paper does not do.
+||A x||/||x|| directly with the same optimiser (gradient sign flipped; see
+``ablation``), which the paper does not do.
 """
 
 from __future__ import annotations
@@ -18,7 +18,8 @@ import numpy as np
 
 from .csr import spmv, transpose_csr, validate_csr
 from .inverse import LUInverse
-from .padam import PAOptions, PAResult, projected_adam
+from .ablation import minimise_by_spmv
+from .padam import PAOptions, projected_adam
 
 EPS_MACH = float(np.finfo(np.float64).eps)
 
@@ -35,44 +36,6 @@ def forward_apply(n, rowptr, col, val):
         return y, spmv(t_rowptr, t_col, t_val, y)
 
     return apply, evaluate
-
-
-def _min_by_spmv(apply_fwd, x0, opts: PAOptions) -> PAResult:
-    """Ablation: minimise ||A x||/||x|| with the gradient of -L; returns the minimum.
-
-    Same update and projections as Algorithm 1; the last pass of the loop only
-    evaluates x_T.
-    """
-    x = np.array(x0, dtype=np.float64)
-    x = x / np.sqrt(x @ x)
-    m = np.zeros_like(x)
-    v = np.zeros_like(x)
-    b1t = b2t = 1.0
-    best = np.inf
-    x_best = x.copy()
-    trace = []
-    for t in range(1, opts.max_iter + 2):
-        y, w = apply_fwd(x)
-        nx2 = x @ x
-        ny2 = y @ y
-        if t >= 2:
-            s = np.sqrt(ny2 / nx2)
-            if s < best:
-                best = s
-                x_best = x.copy()
-            trace.append(best)
-        if t == opts.max_iter + 1:
-            break
-        g = w / ny2 - x / nx2
-        m = opts.beta1 * m + (1 - opts.beta1) * g
-        v = opts.beta2 * v + (1 - opts.beta2) * (g * g)
-        b1t *= opts.beta1
-        b2t *= opts.beta2
-        d = opts.alpha * (m / (1 - b1t)) / (np.sqrt(v / (1 - b2t)) + opts.eps)
-        d = d - (x @ d) * x
-        x = x - d
-        x = x / np.sqrt(x @ x)
-    return PAResult(best, x_best, opts.max_iter, np.asarray(trace), False)
 
 
 def estimate_cond(n, rowptr, col, val, x0_max, x0_min=None, opts: PAOptions | None = None,
@@ -105,7 +68,7 @@ def estimate_cond(n, rowptr, col, val, x0_max, x0_min=None, opts: PAOptions | No
                    x_min=rinv.x_best, inv_norm=rinv.sigma)
     elif min_method == "spmv":
         t0 = time.perf_counter()
-        rmin = _min_by_spmv(apply_fwd, x0_min, opts_min)
+        rmin = minimise_by_spmv(apply_fwd, eval_fwd, x0_min, opts_min)
         out["time_min_s"] = time.perf_counter() - t0
         out.update(sigma_min=rmin.sigma, iters_min=rmin.iters, trace_min=rmin.trace, x_min=rmin.x_best)
     else:
@@ -113,9 +76,3 @@ def estimate_cond(n, rowptr, col, val, x0_max, x0_min=None, opts: PAOptions | No
     out["kappa"] = out["sigma_max"] / out["sigma_min"]
     out["numerically_singular"] = out["kappa"] >= 1.0 / EPS_MACH
     return out
-
-
-def kappa_trace(trace_max, trace_inv):
-    """Running kappa estimate if both runs advance one step at a time."""
-    k = min(len(trace_max), len(trace_inv))
-    return np.asarray(trace_max[:k]) * np.asarray(trace_inv[:k])

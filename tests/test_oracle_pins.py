@@ -14,7 +14,8 @@ import pytest
 import scipy.sparse as sp
 
 from oracle import PAOptions, estimate_cond, forward_apply, projected_adam
-from oracle.csr import spmv, spmv_exact, transpose_csr, validate_csr, CsrError
+from oracle.ablation import minimise_by_spmv
+from oracle.csr import spmv, spmv_abs, spmv_exact, transpose_csr, validate_csr, CsrError
 from oracle.exact import kappa_blockdiag2, sv_2x2, sv_extremes_mp_inverse
 from oracle.inverse import LUInverse
 from synth import Csr, csr_from_dense, diag_csr, scaled_banded, start_vector
@@ -284,3 +285,101 @@ def test_lu_solves_backward_error(n, bound):
 def test_validation_rejects(bad):
     with pytest.raises(CsrError):
         validate_csr(bad[0], np.array(bad[1]), np.array(bad[2], dtype=np.int64), np.array(bad[3]))
+
+
+def test_spmv_abs_on_integers():
+    # (|A| |x|)_i is the scale of every componentwise SpMV bar: exact on
+    # integer data against integer arithmetic, never below |A x|, and equal
+    # to A x when A and x are non-negative
+    rng = np.random.default_rng(21)
+    n = 250
+    a = sp.random(n, n, density=0.04, random_state=22, format="csr")
+    a.data = rng.integers(-(2**20), 2**20, a.nnz).astype(float)
+    x = rng.integers(-(2**20), 2**20, n).astype(float)
+    c = Csr.from_scipy(a)
+    exact = (abs(a).astype(np.int64) @ np.abs(x).astype(np.int64)).astype(float)
+    got = spmv_abs(c.rowptr, c.col, c.val, x)
+    np.testing.assert_array_equal(got, exact)
+    assert np.all(got >= np.abs(spmv(c.rowptr, c.col, c.val, x)))
+    pos = Csr(c.n, c.rowptr, c.col, np.abs(c.val))
+    np.testing.assert_array_equal(spmv_abs(pos.rowptr, pos.col, pos.val, np.abs(x)),
+                                  spmv(pos.rowptr, pos.col, pos.val, np.abs(x)))
+
+
+# ------------------------------------- ablation: sigma_min by SpMV alone
+def _min_spmv(a: Csr, seed, **kw):
+    apply, evaluate = forward_apply(a.n, a.rowptr, a.col, a.val)
+    return minimise_by_spmv(apply, evaluate, start_vector(a.n, seed), PAOptions(**kw))
+
+
+def test_spmv_min_diagonal_kappa_1e2():
+    # well-conditioned (kappa ~ 1e2, n = 60): the descent reaches min |d|
+    # from above; a flipped gradient sign would climb to max |d| instead and
+    # a ">" in the best rule would report the largest value seen
+    rng = np.random.default_rng(200)
+    n = 60
+    d = rng.choice([-1.0, 1.0], n) * 10.0 ** rng.uniform(0, 2, n)
+    a = diag_csr(d, rng.permutation(n), rng.permutation(n))
+    r = _min_spmv(a, 1, max_iter=20000)
+    assert np.abs(d).min() <= r.sigma <= np.abs(d).min() * (1 + 1e-5)
+    assert np.all(np.diff(r.trace) <= 0)
+    # with the step-size floor it lands on the closed form
+    r2 = _min_spmv(a, 1, max_iter=20000, alpha_min=1e-4, stop_rtol=1e-9, stop_window=50)
+    assert r2.sigma == pytest.approx(np.abs(d).min(), rel=1e-12)
+    assert r2.iters < 20000 and r2.iters % 50 == 0
+
+
+def test_spmv_min_block_diagonal_closed_form():
+    # non-symmetric 2x2 blocks, moderate kappa: A^T in place of A changes the
+    # smallest singular value of each block
+    rng = np.random.default_rng(31)
+    nb = 15
+    blocks = rng.standard_normal((nb, 2, 2)) + 3.0 * np.eye(2)
+    blocks[:, 0, 1] *= 4.0
+    a = block_diag_2x2(blocks)
+    smax, smin, _ = kappa_blockdiag2(blocks)
+    r = _min_spmv(a, 2, max_iter=20000, alpha_min=1e-4, stop_rtol=1e-10, stop_window=50)
+    assert r.sigma == pytest.approx(smin, rel=1e-9)
+
+
+@pytest.mark.parametrize("c", [4.0, -(2.0**-12)])
+def test_spmv_min_scaled_identity_fixed_point(c):
+    a = diag_csr(np.full(23, c))
+    r = _min_spmv(a, 4, max_iter=30)
+    assert r.sigma == abs(c)
+    x0 = start_vector(23, 4)
+    np.testing.assert_allclose(r.x_best, x0 / np.sqrt(x0 @ x0), rtol=0, atol=8e-16)
+
+
+def test_spmv_min_power_of_two_scaling_bitwise():
+    a = scaled_banded(50, seed=3, col_decades=2, row_decades=1)
+    b = Csr(a.n, a.rowptr, a.col, a.val * 2.0**-33)
+    ra = _min_spmv(a, 5, max_iter=200)
+    rb = _min_spmv(b, 5, max_iter=200)
+    np.testing.assert_array_equal(ra.x_best, rb.x_best)
+    np.testing.assert_array_equal(rb.trace, ra.trace * 2.0**-33)
+
+
+def test_spmv_min_is_an_upper_bound_and_fails_at_large_kappa():
+    # every iterate's ||A x|| / ||x|| is >= sigma_min; at kappa ~ 1e4 the
+    # descent is still far from it after 20000 updates (the reason the paper
+    # computes ||A^-1|| through an LU instead)
+    rng = np.random.default_rng(201)
+    n = 60
+    d = rng.choice([-1.0, 1.0], n) * 10.0 ** rng.uniform(0, 4, n)
+    a = diag_csr(d)
+    r = _min_spmv(a, 1, max_iter=20000)
+    assert r.sigma >= np.abs(d).min()
+    assert r.sigma > 2.0 * np.abs(d).min()
+    e = _est(a, 1, iters=4000)  # the LU route on the same matrix
+    assert e["sigma_min"] == pytest.approx(np.abs(d).min(), rel=1e-9)
+
+
+def test_estimate_cond_spmv_route_matches_ablation():
+    a = scaled_banded(40, seed=9, col_decades=1, row_decades=1)
+    x0 = start_vector(a.n, 7)
+    o = PAOptions(max_iter=500)
+    r = estimate_cond(a.n, a.rowptr, a.col, a.val, x0, opts=o, min_method="spmv")
+    rr = _min_spmv(a, 7, max_iter=500)
+    assert r["sigma_min"] == rr.sigma
+    assert r["kappa"] == r["sigma_max"] / rr.sigma
