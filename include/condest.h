@@ -55,6 +55,13 @@ extern "C" {
 
 /* sigma_min route */
 #define COND_MIN_LU 0   /* the paper's route: Algorithm 2, one LU + triangular solves */
+#define COND_MIN_SPMV 1 /* ablation, not the paper's method: sigma_min as the smallest
+                           ||A x|| / ||x|| reached by the same Projected Adam iteration
+                           descending on log||A v|| - log||v|| (the gradient of equation
+                           nabla_loss negated), with products by A and A^T only. Every
+                           value is an upper bound of sigma_min; at large kappa it does
+                           not converge in practice, which is why the paper factors A.
+                           Needs no LU: any plan can run it */
 #define COND_MIN_NONE 2 /* skip the sigma_min run */
 
 /* result flags */
@@ -86,7 +93,9 @@ typedef struct {
                           T >= 2*stop_window, stop when
                           best_T - best_{T-W} <= stop_rtol * best_T; 0 = off */
   int64_t stop_window; /* W; 0 = off */
-  int32_t sigma_min_method; /* COND_MIN_LU or COND_MIN_NONE */
+  int32_t sigma_min_method; /* COND_MIN_LU, COND_MIN_SPMV or COND_MIN_NONE; chosen at
+                               create (COND_MIN_LU factors A there) and may change at run
+                               to COND_MIN_SPMV or COND_MIN_NONE */
   int32_t chunk;       /* iterations per captured HIP graph launch (0 = automatic) */
   const int32_t* col_perm; /* optional fill-reducing column order for the LU (host,
                               n entries, a permutation); NULL = built-in nested

@@ -21,6 +21,7 @@ from ._binding import (  # noqa: F401
     COND_F_NUMSING,
     COND_MIN_LU,
     COND_MIN_NONE,
+    COND_MIN_SPMV,
     CondError,
     HostCsr,
     ResultT,
@@ -102,6 +103,27 @@ class LU:
             self._h = C.c_void_p()
 
 
+def _vec(x, n, name="x", dtype=None):
+    """Device pointer of ``x`` after checking it is what the C ABI reads: a
+    contiguous CUDA tensor of ``n`` elements of ``dtype`` (float64 unless
+    given). Raises ValueError before any launch otherwise, so a host, short,
+    strided or float32 tensor never reaches a kernel."""
+    import torch
+
+    dtype = torch.float64 if dtype is None else dtype
+    if not isinstance(x, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor on the GPU")
+    if x.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, not {x.dtype}")
+    if not x.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if x.numel() != n:
+        raise ValueError(f"{name} must have {n} elements, not {x.numel()}")
+    if x.device.type != "cuda":
+        raise ValueError(f"{name} must be on a CUDA (HIP) device, not {x.device}")
+    return x.data_ptr()
+
+
 def _stream_ptr(torch, stream):
     if stream is None:
         stream = torch.cuda.current_stream()
@@ -150,6 +172,10 @@ class Plan:
         import torch
 
         o = make_opts(**{**self._opts_dict(), **opts})
+        if x0_max is None and x0_min is None:
+            raise ValueError("run needs x0_max, x0_min or both")
+        p_max = None if x0_max is None else _vec(x0_max, self.n, "x0_max")
+        p_min = None if x0_min is None else _vec(x0_min, self.n, "x0_min")
         dev = (x0_max if x0_max is not None else x0_min).device
         T = int(o.max_iter)
         tmax = torch.zeros(T, dtype=torch.float64, device=dev) if trace else None
@@ -157,8 +183,7 @@ class Plan:
         bmax = torch.zeros(self.n, dtype=torch.float64, device=dev) if x_best else None
         bmin = torch.zeros(self.n, dtype=torch.float64, device=dev) if x_best else None
         res = ResultT()
-        st = lib().cond_plan_run(self._h, C.byref(o), None if x0_max is None else x0_max.data_ptr(),
-                                 None if x0_min is None else x0_min.data_ptr(), C.byref(res),
+        st = lib().cond_plan_run(self._h, C.byref(o), p_max, p_min, C.byref(res),
                                  None if tmax is None else tmax.data_ptr(),
                                  None if tmin is None else tmin.data_ptr(),
                                  None if bmax is None else bmax.data_ptr(),
@@ -213,17 +238,19 @@ class Plan:
     def spmv(self, x, transpose=False):
         import torch
 
+        px = _vec(x, self.n)
         y = torch.empty_like(x)
-        check(lib().cond_plan_spmv(self._h, 1 if transpose else 0, x.data_ptr(), y.data_ptr()),
+        check(lib().cond_plan_spmv(self._h, 1 if transpose else 0, px, y.data_ptr()),
               "plan_spmv")
         return y
 
     def inverse_apply(self, x):
         import torch
 
+        px = _vec(x, self.n)
         r = torch.empty_like(x)
         s = torch.empty_like(x)
-        check(lib().cond_plan_inverse_apply(self._h, x.data_ptr(), r.data_ptr(), s.data_ptr()),
+        check(lib().cond_plan_inverse_apply(self._h, px, r.data_ptr(), s.data_ptr()),
               "plan_inverse_apply")
         return r, s
 
@@ -286,6 +313,7 @@ class Batch:
         o = make_opts(**{**{f: getattr(self.opts, f) for f, _ in self.opts._fields_
                             if f != "col_perm"}, **opts})
         npairs = self.count * self.K
+        px = _vec(x0, int(self.row0[-1]) * self.K, "x0")
         smax = np.zeros(self.count)
         best = np.zeros(npairs)
         iters = np.zeros(npairs, np.int64)
@@ -293,7 +321,7 @@ class Batch:
         tr = torch.zeros(npairs * int(o.max_iter), dtype=torch.float64,
                          device=x0.device) if trace else None
         ms = C.c_double()
-        st = lib().cond_batch_run(self._h, C.byref(o), x0.data_ptr(), smax.ctypes.data,
+        st = lib().cond_batch_run(self._h, C.byref(o), px, smax.ctypes.data,
                                   best.ctypes.data, iters.ctypes.data, status.ctypes.data,
                                   None if tr is None else tr.data_ptr(), None, C.byref(ms))
         out = dict(sigma_max=smax, pair_best=best.reshape(self.count, self.K),
@@ -331,8 +359,9 @@ def estimate_cond(n, rowptr, col, val, x0_max, x0_min=None, stream=None, **opts)
     h = HostCsr(n, rowptr, col, val)
     o = make_opts(**opts)
     res = ResultT()
-    st = lib().cond_estimate(C.byref(h.struct), C.byref(o), x0_max.data_ptr(),
-                             None if x0_min is None else x0_min.data_ptr(),
+    p_max = _vec(x0_max, int(n), "x0_max")
+    p_min = None if x0_min is None else _vec(x0_min, int(n), "x0_min")
+    st = lib().cond_estimate(C.byref(h.struct), C.byref(o), p_max, p_min,
                              _stream_ptr(torch, stream), C.byref(res))
     check(st, "estimate")
     return {f: getattr(res, f) for f, _ in ResultT._fields_}
@@ -373,9 +402,10 @@ class CNN:
     def _shape(fields):
         import torch
 
-        if fields.dtype != torch.float64 or fields.dim() != 4 or fields.shape[1] != 2 \
+        if not isinstance(fields, torch.Tensor) or fields.device.type != "cuda" \
+                or fields.dtype != torch.float64 or fields.dim() != 4 or fields.shape[1] != 2 \
                 or fields.shape[2] != fields.shape[3] or not fields.is_contiguous():
-            raise ValueError("fields must be a contiguous float64 tensor [batch, 2, s-1, s-1]")
+            raise ValueError("fields must be a contiguous float64 CUDA tensor [batch, 2, s-1, s-1]")
         return int(fields.shape[0]), int(fields.shape[2]) + 1
 
     def predict(self, fields):
@@ -387,7 +417,10 @@ class CNN:
         return x0
 
     def gradients(self, fields, labels):
+        import torch
+
         b, s = self._shape(fields)
+        _vec(labels, b * 6 * s * s, "labels", torch.float32)
         g = np.zeros(self.param_count, np.float32)
         losses = np.zeros(b, np.float32)
         check(lib().cond_cnn_gradients(self._h, fields.data_ptr(), labels.data_ptr(), b, s,
@@ -395,7 +428,10 @@ class CNN:
         return g, losses
 
     def train_step(self, fields, labels, lr) -> float:
+        import torch
+
         b, s = self._shape(fields)
+        _vec(labels, b * 6 * s * s, "labels", torch.float32)
         ml = C.c_float()
         check(lib().cond_cnn_train_step(self._h, fields.data_ptr(), labels.data_ptr(), b, s,
                                         float(lr), C.byref(ml)), "cnn_train_step")

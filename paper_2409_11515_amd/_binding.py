@@ -25,6 +25,7 @@ COND_ENUMERIC = -5
 COND_ESTATE = -6
 COND_ETIMEOUT = -7
 COND_MIN_LU = 0
+COND_MIN_SPMV = 1
 COND_MIN_NONE = 2
 COND_F_NUMSING = 1
 COND_F_MAXITER = 2

@@ -55,7 +55,7 @@ __device__ __forceinline__ void block_range(long long n, int lb, long long& r0, 
 __global__ __launch_bounds__(kBlock) void init_k(int n, const double* __restrict__ x0,
                                                  double* __restrict__ x, double* __restrict__ m,
                                                  double* __restrict__ v, double* __restrict__ parts_xx,
-                                                 RunState* st, double alpha0) {
+                                                 RunState* st, double alpha0, int minimise) {
   const int lb = logical_block();
   long long r0, r1;
   block_range(n, lb, r0, r1);
@@ -70,8 +70,11 @@ __global__ __launch_bounds__(kBlock) void init_k(int n, const double* __restrict
   const double s = block_sum(acc);
   if (threadIdx.x == 0) parts_xx[lb] = s;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    st->best = -1.0;  // below any norm ratio: the first evaluation always improves
-    st->best_next = -1.0;
+    // below (above, when minimising) any norm ratio: the first evaluation
+    // always improves
+    const double start = minimise ? __longlong_as_double(0x7FF0000000000000ll) : -1.0;
+    st->best = start;
+    st->best_next = start;
     st->b1t = 1.0;
     st->b2t = 1.0;
     st->t_done = 0;
@@ -81,8 +84,8 @@ __global__ __launch_bounds__(kBlock) void init_k(int n, const double* __restrict
     st->status = 0;
     st->flags = 0;
     st->abort_wait = 0;
-    st->ckpt = -1.0;
-    st->ckpt_next = -1.0;
+    st->ckpt = start;
+    st->ckpt_next = start;
     st->alpha = alpha0;
     st->alpha_next = alpha0;
   }
@@ -588,9 +591,9 @@ __global__ __launch_bounds__(kBlock) void pass1_k(int n, const double* __restric
     stop = 1;
     status = COND_ENUMERIC;
   } else if (t >= 2) {
-    // sigma(x_{t-1}) = ||M x|| / ||x||; strict ">" keeps the earliest best
+    // sigma(x_{t-1}) = ||M x|| / ||x||; a strict comparison keeps the earliest best
     const double sigma = sqrt(ny2 / nx2);
-    if (sigma > best) {
+    if (p.minimise ? sigma < best : sigma > best) {
       improved = true;
       best_next = sigma;
     }
@@ -599,7 +602,8 @@ __global__ __launch_bounds__(kBlock) void pass1_k(int n, const double* __restric
       stop = 1;
       flags |= static_cast<int>(COND_F_MAXITER);
     } else if (p.stop_window > 0 && p.stop_rtol > 0.0 && T % p.stop_window == 0) {
-      if (T >= 2 * p.stop_window && best_next - st->ckpt <= p.stop_rtol * best_next) {
+      const double gain = p.minimise ? st->ckpt - best_next : best_next - st->ckpt;
+      if (T >= 2 * p.stop_window && gain <= p.stop_rtol * best_next) {
         // plateau: with a step-size floor, continue with a smaller step until it is reached
         if (p.alpha_min > 0.0 && alpha > p.alpha_min)
           alpha = fmax(alpha * p.alpha_decay, p.alpha_min);
@@ -632,7 +636,8 @@ __global__ __launch_bounds__(kBlock) void pass1_k(int n, const double* __restric
   double acc = 0.0;
   for (long long i = r0 + threadIdx.x; i < r1; i += kBlock) {
     const double xi = x[i];
-    const double g = xi / nx2 - w[i] / ny2;  // equation nabla_loss
+    // equation nabla_loss (negated when minimising)
+    const double g = p.minimise ? w[i] / ny2 - xi / nx2 : xi / nx2 - w[i] / ny2;
     const double mi = b1 * m[i] + (1.0 - b1) * g;
     const double vi = b2 * v[i] + (1.0 - b2) * (g * g);
     const double mh = mi / (1.0 - b1t);
@@ -710,8 +715,8 @@ int grid_for(int n) {
 }
 
 void launch_init(int n, const double* x0, double* x, double* m, double* v, double* parts_xx,
-                 int grid, RunState* st, double alpha0, hipStream_t s) {
-  init_k<<<grid, kBlock, 0, s>>>(n, x0, x, m, v, parts_xx, st, alpha0);
+                 int grid, RunState* st, double alpha0, int minimise, hipStream_t s) {
+  init_k<<<grid, kBlock, 0, s>>>(n, x0, x, m, v, parts_xx, st, alpha0, minimise);
 }
 
 void launch_normalise(int n, double* x, const double* parts_xx, int grid, double* parts_x,

@@ -55,6 +55,10 @@ struct AdamParams {
   long long max_iter;
   double alpha_min;    // > 0: on a stop-rule plateau shrink alpha instead of stopping
   double alpha_decay;  // factor of each shrink
+  // 1: descend on log||M v|| - log||v|| (the gradient of equation nabla_loss
+  // negated) and keep the smallest sigma -- the SpMV-only sigma_min ablation
+  int minimise;
+  int pad_;
 };
 
 // CSR on the device. rowptr is int32 when idx64 == 0, else int64.
@@ -115,7 +119,7 @@ using TrsvArgs = DevTri;
 int grid_for(int n);  // fixed grid size of the reduction kernels for length n
 
 void launch_init(int n, const double* x0, double* x, double* m, double* v, double* parts_xx,
-                 int grid, RunState* st, double alpha0, hipStream_t s);
+                 int grid, RunState* st, double alpha0, int minimise, hipStream_t s);
 void launch_normalise(int n, double* x, const double* parts_xx, int grid, double* parts_x,
                       RunState* st, double* const* resets, int nresets, unsigned* tickets,
                       int ntickets, hipStream_t s);

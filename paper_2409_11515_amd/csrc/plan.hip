@@ -380,8 +380,8 @@ struct cond_plan {
   unsigned* tickets = nullptr;
   RunState* h_state = nullptr;  // pinned, two slots
   int grid = 8;
-  GraphKey key[2];
-  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  GraphKey key[3];
+  hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
   // eager profiling (opts.profile): event pairs around every launch
   std::vector<hipEvent_t> evpool;
   struct Rec {
@@ -537,6 +537,7 @@ AdamParams params_of(const cond_opts_t& o) {
   p.max_iter = o.max_iter;
   p.alpha_min = o.alpha_min;
   p.alpha_decay = o.alpha_decay;
+  p.minimise = 0;
   return p;
 }
 
@@ -549,7 +550,8 @@ int check_opts(const cond_opts_t* o) {
   if (!(o->alpha_min >= 0) || o->alpha_min > o->alpha ||
       (o->alpha_min > 0 && !(o->alpha_decay > 0 && o->alpha_decay < 1)))
     return fail(COND_EINVAL, "invalid step-size floor or decay");
-  if (o->sigma_min_method != COND_MIN_LU && o->sigma_min_method != COND_MIN_NONE)
+  if (o->sigma_min_method != COND_MIN_LU && o->sigma_min_method != COND_MIN_SPMV &&
+      o->sigma_min_method != COND_MIN_NONE)
     return fail(COND_EINVAL, "unknown sigma_min method");
   return COND_OK;
 }
@@ -584,12 +586,14 @@ struct Prof {
   }
 };
 
-// One iteration of the chosen route, enqueued on the plan stream.
+// One iteration of the chosen route, enqueued on the plan stream: 0 the
+// sigma_max run (M = A), 1 the sigma_min run of Algorithm 2 (M = A^-1), 2 the
+// SpMV-only sigma_min ablation (M = A, minimising; ap.minimise is set).
 void enqueue_iteration(cond_plan* p, int route, double* trace, double* xbest, const AdamParams& ap) {
   hipStream_t s = p->stream;
   const int n = p->n, g = p->grid;
   const double dn = n;
-  if (route == 0) {
+  if (route != 1) {
     { Prof pr(p, COND_K_NORMALISE, 16.0 * dn);
       launch_normalise(n, p->x, p->parts_xx, g, p->parts_x, p->st, nullptr, 0, nullptr, 0, s); }
     { Prof pr(p, COND_K_SPMV_A, spmv_bytes(p->dA));
@@ -718,12 +722,14 @@ struct RouteResult {
 
 int run_route(cond_plan* p, int route, const cond_opts_t& o, const double* x0, double* trace,
               double* xbest, RouteResult& rr) {
-  const AdamParams ap = params_of(o);
+  AdamParams ap = params_of(o);
+  ap.minimise = route == 2 ? 1 : 0;
   const long long total = o.max_iter + 1;  // the last pass only evaluates x_T
   if (o.profile) {
     // eager launches with an event pair around each kernel; poll every iteration
     CHK(hipEventRecord(p->ev_start, p->stream));
-    launch_init(p->n, x0, p->x, p->m, p->v, p->parts_xx, p->grid, p->st, o.alpha, p->stream);
+    launch_init(p->n, x0, p->x, p->m, p->v, p->parts_xx, p->grid, p->st, o.alpha, ap.minimise,
+                p->stream);
     CHK(hipGetLastError());
     p->profiling = true;
     int st = COND_OK;
@@ -741,12 +747,13 @@ int run_route(cond_plan* p, int route, const cond_opts_t& o, const double* x0, d
     p->profiling = false;
     if (st) return st;
   } else {
-    const int chunk = o.chunk > 0 ? o.chunk : (route == 0 ? 32 : 4);
+    const int chunk = o.chunk > 0 ? o.chunk : (route == 1 ? 4 : 32);
     hipGraphExec_t exec = nullptr;
     int st = get_graph(p, route, chunk, trace, xbest, ap, &exec);
     if (st) return st;
     CHK(hipEventRecord(p->ev_start, p->stream));
-    launch_init(p->n, x0, p->x, p->m, p->v, p->parts_xx, p->grid, p->st, o.alpha, p->stream);
+    launch_init(p->n, x0, p->x, p->m, p->v, p->parts_xx, p->grid, p->st, o.alpha, ap.minimise,
+                p->stream);
     CHK(hipGetLastError());
     if ((st = replay_until_stop(p, exec, chunk, total))) return st;
   }
@@ -945,6 +952,10 @@ int cond_plan_run(cond_plan_t* p, const cond_opts_t* o, const double* x0_max, co
     std::fill(p->kcnt, p->kcnt + COND_K_COUNT, 0LL);
     std::fill(p->kbytes, p->kbytes + COND_K_COUNT, 0.0);
   }
+  // the sigma_min route: Algorithm 2 when the plan holds the LU, or the
+  // SpMV-only ablation, which any plan can run
+  const bool lu_route = p->want_min && oo.sigma_min_method == COND_MIN_LU;
+  const bool spmv_route = oo.sigma_min_method == COND_MIN_SPMV;
   RouteResult rmax, rmin;
   if (run_max) {
     if ((st = run_route(p, 0, oo, x0_max, trace_max, x_best_max, rmax))) return st;
@@ -953,12 +964,13 @@ int cond_plan_run(cond_plan_t* p, const cond_opts_t* o, const double* x0_max, co
     out->status_max = rmax.status;
     out->ms_max = rmax.ms;
     if (rmax.flags & COND_F_MAXITER) out->flags |= COND_F_MAXITER;
-  } else if (!(p->want_min && oo.sigma_min_method == COND_MIN_LU)) {
+  } else if (!lu_route && !spmv_route) {
     return fail(COND_EINVAL, "null sigma_max start and no sigma_min run");
   }
-  if (p->want_min && oo.sigma_min_method == COND_MIN_LU) {
-    if ((st = run_route(p, 1, oo, x0_min, trace_min, x_best_min, rmin))) return st;
-    out->sigma_min = 1.0 / rmin.sigma;  // the run maximises ||A^-1 x|| / ||x||
+  if (lu_route || spmv_route) {
+    if ((st = run_route(p, lu_route ? 1 : 2, oo, x0_min, trace_min, x_best_min, rmin))) return st;
+    // the LU run maximises ||A^-1 x|| / ||x||; the ablation minimises ||A x|| / ||x||
+    out->sigma_min = lu_route ? 1.0 / rmin.sigma : rmin.sigma;
     out->iters_min = rmin.iters;
     out->status_min = rmin.status;
     out->ms_min = rmin.ms;

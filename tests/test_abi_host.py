@@ -222,3 +222,40 @@ def test_interleave_starts_layout():
     np.testing.assert_array_equal(v[8:16], s0[:, 1])
     np.testing.assert_array_equal(v[16:24], s1[:, 0])
     assert v.size == 8 * 5
+
+
+def test_device_arguments_checked_before_the_library():
+    # every pointer handed to the C ABI is checked first: a wrong dtype,
+    # length, layout or device raises ValueError before any launch (the plan
+    # is not even bound here, so a call that got through would fail with
+    # COND_ESTATE from the library instead)
+    import torch
+
+    a = hydromech2d(5, seed=1)
+    p = pa.Plan(a.n, a.rowptr, a.col, a.val, sigma_min_method=pa.COND_MIN_NONE)
+    good = torch.zeros(a.n, dtype=torch.float64)
+    bad = [torch.zeros(a.n, dtype=torch.float32),        # dtype
+           torch.zeros(a.n - 1, dtype=torch.float64),    # too short
+           torch.zeros(2 * a.n, dtype=torch.float64)[::2],  # strided
+           good,                                         # host memory
+           np.zeros(a.n)]                                # not a tensor
+    for x in bad:
+        with pytest.raises(ValueError):
+            p.run(x)
+        with pytest.raises(ValueError):
+            p.spmv(x)
+        with pytest.raises(ValueError):
+            p.inverse_apply(x)
+        with pytest.raises(ValueError):
+            pa.estimate_cond(a.n, a.rowptr, a.col, a.val, x)
+    with pytest.raises(ValueError):
+        p.run(None, None)
+    p.close()
+    mats = [hydromech2d(s, seed=s) for s in (5, 6)]
+    b = pa.Batch([(m.n, m.rowptr, m.col, m.val) for m in mats])
+    rows = int(b.row0[-1])
+    for x in (torch.zeros(rows, dtype=torch.float64), torch.zeros(8 * rows, dtype=torch.float64),
+              torch.zeros(8 * rows, dtype=torch.float32)):
+        with pytest.raises(ValueError):
+            b.run(x)
+    b.close()

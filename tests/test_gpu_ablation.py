@@ -1,0 +1,90 @@
+"""The SpMV-only sigma_min ablation (COND_MIN_SPMV) against the oracle.
+
+Not the paper's method: Projected Adam descending on log||A v|| - log||v||
+with products by A and A^T only, keeping the smallest ||A x|| / ||x||. The
+oracle is ``oracle.ablation.minimise_by_spmv``. Bars: the traced values in
+lockstep (1e-10), the same stopping update under the stop rule and the
+step-size floor, and the closed form on a well-conditioned diagonal matrix.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import PAOptions, estimate_cond as oracle_estimate
+from oracle.ablation import minimise_by_spmv
+from oracle.estimate import forward_apply
+from synth import diag_csr, hydromech2d, scaled_banded, start_vector
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2409_11515_amd as pa
+
+    pa._binding.lib()
+    return torch
+
+
+def _gpu_min(torch, a, seed, **kw):
+    import paper_2409_11515_amd as pa
+
+    p = pa.Plan(a.n, a.rowptr, a.col, a.val, sigma_min_method=pa.COND_MIN_SPMV).bind()
+    x0 = torch.as_tensor(start_vector(a.n, seed), device="cuda")
+    r = p.run(None, x0, trace=True, **kw)
+    p.close()
+    return r
+
+
+def _oracle_min(a, seed, **kw):
+    apply, evaluate = forward_apply(a.n, a.rowptr, a.col, a.val)
+    return minimise_by_spmv(apply, evaluate, start_vector(a.n, seed), PAOptions(**kw))
+
+
+def test_spmv_min_diagonal_closed_form(torch_cuda):
+    rng = np.random.default_rng(200)
+    n = 60
+    d = rng.choice([-1.0, 1.0], n) * 10.0 ** rng.uniform(0, 2, n)
+    a = diag_csr(d, rng.permutation(n), rng.permutation(n))
+    kw = dict(max_iter=20000, alpha_min=1e-4, stop_rtol=1e-9, stop_window=50)
+    g = _gpu_min(torch_cuda, a, 1, **kw)
+    o = _oracle_min(a, 1, **kw)
+    assert g["sigma_min"] == pytest.approx(np.abs(d).min(), rel=1e-12)
+    assert g["iters_min"] == o.iters
+    np.testing.assert_allclose(g["trace_min"], o.trace, rtol=1e-10)
+
+
+@pytest.mark.parametrize("side,seed", [(9, 1), (24, 3)])
+def test_spmv_min_lockstep_hm(torch_cuda, side, seed):
+    # the hydro-mechanical systems: the ablation stays far above sigma_min
+    # (the LU route's value) but both sides take the same path
+    a = hydromech2d(side, seed=seed)
+    kw = dict(max_iter=3000, stop_rtol=1e-7, stop_window=25)
+    g = _gpu_min(torch_cuda, a, seed, **kw)
+    o = _oracle_min(a, seed, **kw)
+    assert g["iters_min"] == o.iters
+    np.testing.assert_allclose(g["trace_min"][:200], o.trace[:200], rtol=1e-10)
+    assert g["sigma_min"] == pytest.approx(o.sigma, rel=1e-6)
+    if side == 9:
+        lu = oracle_estimate(a.n, a.rowptr, a.col, a.val, start_vector(a.n, seed),
+                             opts=PAOptions(max_iter=3000))
+        assert g["sigma_min"] >= lu["sigma_min"] * (1 - 1e-12)
+
+
+def test_spmv_min_with_sigma_max_gives_kappa(torch_cuda):
+    import paper_2409_11515_amd as pa
+
+    torch = torch_cuda
+    a = scaled_banded(2000, seed=5, col_decades=1, row_decades=1)
+    p = pa.Plan(a.n, a.rowptr, a.col, a.val, sigma_min_method=pa.COND_MIN_SPMV).bind()
+    x0 = torch.as_tensor(start_vector(a.n, 2), device="cuda")
+    r = p.run(x0, x0, max_iter=400)
+    p.close()
+    o = oracle_estimate(a.n, a.rowptr, a.col, a.val, start_vector(a.n, 2),
+                        opts=PAOptions(max_iter=400), min_method="spmv")
+    assert r["sigma_max"] == pytest.approx(o["sigma_max"], rel=1e-10)
+    assert r["sigma_min"] == pytest.approx(o["sigma_min"], rel=1e-10)
+    assert r["kappa"] == pytest.approx(o["kappa"], rel=1e-10)
