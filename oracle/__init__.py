@@ -18,6 +18,9 @@ the method:
 * ``ablation`` -- not the paper's method: sigma_min by descending on
                   ||A x|| / ||x|| with products alone (the comparison that
                   shows why the paper needs Algorithm 2);
+* ``bounds``   -- the error bounds of an approximate solution that the paper
+                  derives from kappa (section "Error estimates and
+                  conditioning");
 * ``exact``    -- closed forms and extended-precision singular values used to
                   pin the oracle itself.
 """
@@ -26,3 +29,4 @@ from .csr import validate_csr, transpose_csr, spmv, spmv_abs  # noqa: F401
 from .padam import PAOptions, PAResult, projected_adam  # noqa: F401
 from .inverse import LUInverse  # noqa: F401
 from .estimate import estimate_cond, forward_apply  # noqa: F401
+from .bounds import error_bounds  # noqa: F401
