@@ -335,6 +335,34 @@ int cond_cnn_activation(const cond_cnn_t* net, int32_t layer, int32_t batch, int
                         float* host);
 void cond_cnn_destroy(cond_cnn_t* net);
 
+/* ------------------------------------------------------------ error bounds
+ * What the paper computes kappa for (section "Error estimates and
+ * conditioning"): bounds on the error of an approximate solution x_hat of
+ * A x = b from its residual b_hat - b = A x_hat - b, kappa = kappa_2(A) and
+ * ||A||_2 = sigma_max (both from cond_plan_run). All norms are 2-norms. */
+typedef struct {
+  double res_norm;          /* ||A x_hat - b|| */
+  double b_norm, x_norm;    /* ||b||, ||x_hat|| */
+  double rel_residual;      /* ||A x_hat - b|| / ||b|| */
+  double err_x_lower;       /* Theorem "Bounds on the relative error ||x_hat - x|| / ||x||": */
+  double err_x_upper;       /*   rel_residual / kappa <= . <= kappa rel_residual */
+  double err_xhat_lower;    /* Theorem "Bounds on the relative error ||x_hat - x|| / ||x_hat||": */
+  double err_xhat_upper;    /*   ||r|| / (||A|| ||x_hat||) <= . <= kappa ||r|| / (||A|| ||x_hat||) =: epsilon */
+  double err_x_tight;       /* Theorem "Tight upper bound of the error": epsilon / (1 - epsilon)
+                               bounds ||x_hat - x|| / ||x||; +inf when epsilon >= 1 */
+  double roundoff_floor;    /* Theorem "Numerical singularity of a matrix": 2 eps kappa /
+                               (1 - kappa eps), eps = 2^-52; +inf when kappa eps >= 1 */
+} cond_bounds_t;
+
+/* Bounds for x_hat and b (device arrays of length n, on the plan's device;
+ * ordered after the work the caller queued on the plan's stream) with the
+ * plan's A. kappa >= 1 and norm_a > 0, both finite, else COND_EINVAL;
+ * COND_ENUMERIC when b or x_hat is zero or a norm is not finite. The
+ * residual's partial sums use the plan's workspace; returns after the result
+ * is on the host. */
+int cond_plan_error_bounds(cond_plan_t* plan, const double* x_hat, const double* b, double kappa,
+                           double norm_a, cond_bounds_t* out);
+
 /* create + bind (library-owned memory) + run + destroy. */
 int cond_estimate(const cond_csr_t* A, const cond_opts_t* o, const double* x0_max,
                   const double* x0_min, void* stream, cond_result_t* out);

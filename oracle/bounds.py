@@ -44,6 +44,8 @@ def error_bounds(n, rowptr, col, val, x_hat, b, kappa, norm_a, eps_mach=EPS_MACH
     res_norm = math.sqrt(float(r @ r))
     b_norm = math.sqrt(float(b @ b))
     x_norm = math.sqrt(float(x_hat @ x_hat))
+    if not (b_norm > 0.0 and x_norm > 0.0):
+        raise ValueError("b and x_hat must be non-zero")
     rel_res = res_norm / b_norm
     eps = kappa * res_norm / (norm_a * x_norm)
     out = {

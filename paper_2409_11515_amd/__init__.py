@@ -254,6 +254,19 @@ class Plan:
               "plan_inverse_apply")
         return r, s
 
+    def error_bounds(self, x_hat, b, kappa, norm_a) -> dict:
+        """Bounds on the error of x_hat as a solution of A x = b (CUDA float64
+        tensors of n entries) from kappa and ||A|| = sigma_max: the four
+        theorems of section "Error estimates and conditioning"."""
+        from ._binding import BoundsT
+
+        px = _vec(x_hat, self.n, "x_hat")
+        pb = _vec(b, self.n, "b")
+        out = BoundsT()
+        check(lib().cond_plan_error_bounds(self._h, px, pb, float(kappa), float(norm_a),
+                                           C.byref(out)), "plan_error_bounds")
+        return {f: getattr(out, f) for f, _ in BoundsT._fields_}
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().cond_plan_destroy(self._h)

@@ -51,6 +51,12 @@ class OptsT(C.Structure):
                 ("alpha_min", C.c_double), ("alpha_decay", C.c_double)]
 
 
+class BoundsT(C.Structure):
+    _fields_ = [(f, C.c_double) for f in (
+        "res_norm", "b_norm", "x_norm", "rel_residual", "err_x_lower", "err_x_upper",
+        "err_xhat_lower", "err_xhat_upper", "err_x_tight", "roundoff_floor")]
+
+
 class ResultT(C.Structure):
     _fields_ = [("sigma_max", C.c_double), ("sigma_min", C.c_double), ("kappa", C.c_double),
                 ("iters_max", C.c_int64), ("iters_min", C.c_int64), ("flags", C.c_uint32),
@@ -73,7 +79,7 @@ EXPORTS = (
     "cond_batch_info", "cond_batch_bind", "cond_batch_run", "cond_batch_destroy",
     "cond_cnn_param_count", "cond_cnn_create", "cond_cnn_set_params", "cond_cnn_get_params",
     "cond_cnn_predict", "cond_cnn_gradients", "cond_cnn_train_step", "cond_cnn_activation",
-    "cond_cnn_destroy",
+    "cond_cnn_destroy", "cond_plan_error_bounds",
 )
 
 BATCH_K = 8

@@ -693,6 +693,59 @@ __global__ __launch_bounds__(kBlock) void pass2_k(int n, double* __restrict__ x,
   }
 }
 
+// ------------------------------------------------------------- residual
+// Error bounds of an approximate solution: r = A x_hat - b row by row (16
+// lanes per row, a block's rows a contiguous range), with block partials of
+// r.r, x_hat.x_hat and b.b in fixed slots; reduce3_k adds each set of
+// partials in slot order (one block), so the three sums do not depend on
+// timing.
+template <typename IT>
+__global__ __launch_bounds__(kBlock) void residual_k(int n, const IT* __restrict__ rowptr,
+                                                     const int* __restrict__ col,
+                                                     const double* __restrict__ val,
+                                                     const double* __restrict__ x,
+                                                     const double* __restrict__ b,
+                                                     double* __restrict__ parts) {
+#pragma clang fp contract(off)
+  constexpr int kRowLanes = 16;
+  const int lb = logical_block();
+  long long r0, r1;
+  block_range(n, lb, r0, r1);
+  const int sub = threadIdx.x & (kRowLanes - 1);
+  const int grp = threadIdx.x / kRowLanes;
+  double ar = 0.0, ax = 0.0, ab = 0.0;
+  for (long long i = r0 + grp; i < r1; i += kBlock / kRowLanes) {
+    const IT p0 = rowptr[i], p1 = rowptr[i + 1];
+    double acc = 0.0;
+    for (IT e = p0 + sub; e < p1; e += kRowLanes) acc += val[e] * x[col[e]];
+#pragma unroll
+    for (int off = kRowLanes / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kRowLanes);
+    if (sub == 0) {
+      const double bi = b[i], xi = x[i];
+      const double ri = acc - bi;
+      ar += ri * ri;
+      ax += xi * xi;
+      ab += bi * bi;
+    }
+  }
+  const double sr = block_sum(ar);
+  const double sx = block_sum(ax);
+  const double sb = block_sum(ab);
+  if (threadIdx.x == 0) {
+    parts[lb] = sr;
+    parts[kMaxParts + lb] = sx;
+    parts[2 * kMaxParts + lb] = sb;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void reduce3_k(const double* __restrict__ parts, int np,
+                                                    double* __restrict__ out) {
+  for (int k = 0; k < 3; ++k) {
+    const double v = sum_parts(parts + static_cast<long long>(k) * kMaxParts, np);
+    if (threadIdx.x == 0) out[k] = v;
+  }
+}
+
 __global__ void fill_k(long long n, unsigned long long* p, unsigned long long bits) {
   for (long long i = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<long long>(gridDim.x) * blockDim.x)
@@ -763,6 +816,18 @@ void launch_pass1(int n, const double* x, const double* w, double* m, double* v,
 void launch_pass2(int n, double* x, const double* d, const double* parts_xd, int grid,
                   double* parts_xx, RunState* st, const AdamParams& p, hipStream_t s) {
   pass2_k<<<grid, kBlock, 0, s>>>(n, x, d, parts_xd, grid, parts_xx, st, p);
+}
+
+void launch_residual(int n, const void* rowptr, int idx64, const int* col, const double* val,
+                     const double* x, const double* b, double* parts, double* sums, int grid,
+                     hipStream_t s) {
+  if (idx64)
+    residual_k<long long><<<grid, kBlock, 0, s>>>(n, static_cast<const long long*>(rowptr), col,
+                                                  val, x, b, parts);
+  else
+    residual_k<int><<<grid, kBlock, 0, s>>>(n, static_cast<const int*>(rowptr), col, val, x, b,
+                                            parts);
+  reduce3_k<<<1, kBlock, 0, s>>>(parts, grid, sums);
 }
 
 void launch_fill(int n, double* p, unsigned long long bits, hipStream_t s) {

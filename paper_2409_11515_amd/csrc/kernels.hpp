@@ -136,6 +136,11 @@ void launch_pass1(int n, const double* x, const double* w, double* m, double* v,
                   hipStream_t s);
 void launch_pass2(int n, double* x, const double* d, const double* parts_xd, int grid,
                   double* parts_xx, RunState* st, const AdamParams& p, hipStream_t s);
+// r = A x - b: parts (3 * kMaxParts doubles) receives the block partials of
+// r.r, x.x and b.b; sums (3 doubles) their totals, added in slot order.
+void launch_residual(int n, const void* rowptr, int idx64, const int* col, const double* val,
+                     const double* x, const double* b, double* parts, double* sums, int grid,
+                     hipStream_t s);
 void launch_fill(int n, double* p, unsigned long long bits, hipStream_t s);
 void launch_zero_u32(unsigned* p, int count, hipStream_t s);
 

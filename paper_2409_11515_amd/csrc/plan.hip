@@ -15,6 +15,7 @@
 
 #include "condest.h"
 #include "internal.hpp"
+#include "bounds.hpp"
 #include "kernels.hpp"
 
 namespace condest {
@@ -1136,6 +1137,29 @@ int cond_plan_inverse_apply(cond_plan_t* p, const double* x, double* r, double* 
   CHK(hipMemcpyAsync(&hs, p->st_free, sizeof(RunState), hipMemcpyDeviceToHost, st));
   CHK(hipStreamSynchronize(st));
   if (hs.abort_wait) return fail(COND_ETIMEOUT, "triangular-solve wait timed out");
+  return COND_OK;
+}
+
+int cond_plan_error_bounds(cond_plan_t* p, const double* x_hat, const double* b, double kappa,
+                           double norm_a, cond_bounds_t* out) {
+  if (!p || !x_hat || !b || !out) return fail(COND_EINVAL, "null argument");
+  if (!p->bound) return fail(COND_ESTATE, "plan not bound");
+  if (!(kappa >= 1.0) || !std::isfinite(kappa) || !(norm_a > 0.0) || !std::isfinite(norm_a))
+    return fail(COND_EINVAL, "kappa must be >= 1 and norm_a > 0, both finite");
+  int st;
+  if ((st = join_user_stream(p))) return st;
+  // the partials go to three of the run's partial arrays, the sums to the fourth
+  static_assert(kMaxParts * 8 % kAlign == 0, "partial arrays are contiguous");
+  double* parts = p->parts_x;
+  if (p->parts_y != parts + kMaxParts || p->parts_xd != parts + 2 * kMaxParts)
+    return fail(COND_ESTATE, "partial arrays are not contiguous");
+  launch_residual(p->n, p->dA.rowptr, p->dA.idx64, p->dA.col, p->dA.val, x_hat, b, parts,
+                  p->parts_xx, p->grid, p->stream);
+  CHK(hipGetLastError());
+  double sums[3];
+  CHK(hipMemcpyAsync(sums, p->parts_xx, sizeof(sums), hipMemcpyDeviceToHost, p->stream));
+  CHK(hipStreamSynchronize(p->stream));
+  if ((st = fill_bounds(sums, kappa, norm_a, out))) return fail(st, "zero or non-finite norm");
   return COND_OK;
 }
 
