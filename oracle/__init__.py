@@ -18,6 +18,8 @@ the method:
 * ``ablation`` -- not the paper's method: sigma_min by descending on
                   ||A x|| / ||x|| with products alone (the comparison that
                   shows why the paper needs Algorithm 2);
+* ``scaling``  -- column scaling A D_col^-1 (section "Row and Column
+                  Scaling") and kappa_2 of the scaled matrix;
 * ``bounds``   -- the error bounds of an approximate solution that the paper
                   derives from kappa (section "Error estimates and
                   conditioning");
@@ -30,3 +32,4 @@ from .padam import PAOptions, PAResult, projected_adam  # noqa: F401
 from .inverse import LUInverse  # noqa: F401
 from .estimate import estimate_cond, forward_apply  # noqa: F401
 from .bounds import error_bounds  # noqa: F401
+from .scaling import column_norms, scale_columns, estimate_cond_col_scaled  # noqa: F401
