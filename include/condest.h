@@ -69,6 +69,7 @@ extern "C" {
                               numerical singularity) */
 #define COND_F_MAXITER 2u  /* a run ended at max_iter rather than by the stop rule */
 #define COND_F_SINGULAR 4u /* exactly singular (zero pivot) */
+#define COND_F_COLSCALED 8u /* the estimate is of A D_col^-1 (opts.scaling) */
 
 /* ------------------------------------------------------------------- types */
 
@@ -119,7 +120,19 @@ typedef struct {
                           0 <= alpha_min <= alpha */
   double alpha_decay;  /* factor of each decrease, 0 < alpha_decay < 1 (default
                           0.5); used only when alpha_min > 0 */
+  int32_t scaling;     /* COND_SCALE_NONE (default): estimate kappa_2(A).
+                          COND_SCALE_COL: estimate kappa_2(A D_col^-1), the
+                          column-scaled matrix of section "Row and Column Scaling"
+                          (D_col = diag of the column 2-norms of A), from the same
+                          plan: the products scale on the fly and the sigma_min
+                          run reuses A's LU, since (A D^-1)^-1 = D A^-1. A plan
+                          with a zero column refuses it (COND_EINVAL). May change
+                          from run to run */
 } cond_opts_t;
+
+/* cond_opts_t.scaling */
+#define COND_SCALE_NONE 0
+#define COND_SCALE_COL 1
 
 typedef struct {
   double sigma_max, sigma_min, kappa;
@@ -252,6 +265,16 @@ int cond_plan_solve_replay(const cond_plan_t* plan, const double* x, double* r, 
  * against the oracle): y = A x; y = A^T x; r = A^-1 x and s = A^-T r
  * (Algorithm 2). Asynchronous on the plan's stream. */
 int cond_plan_spmv(cond_plan_t* plan, int transpose, const double* x, double* y);
+/* flags of cond_plan_spmv's `transpose` argument: bit 0 = A^T; bit 1 = the
+ * column-scaled matrix, y = (A D^-1) x or (A D^-1)^T x */
+#define COND_SPMV_T 1
+#define COND_SPMV_COLSCALED 2
+
+/* The column norms of A, d_j = ||A[:, j]||_2 (section "Row and Column
+ * Scaling", D_col), computed on the device as row norms of the stored A^T,
+ * into the device array d (n doubles, caller-owned). Returns after d is
+ * written. */
+int cond_plan_column_norms(cond_plan_t* plan, double* d);
 int cond_plan_inverse_apply(cond_plan_t* plan, const double* x, double* r, double* s);
 
 /* ---------------------------------------------------- batched multi-start

@@ -22,6 +22,8 @@ from ._binding import (  # noqa: F401
     COND_MIN_LU,
     COND_MIN_NONE,
     COND_MIN_SPMV,
+    COND_SCALE_COL,
+    COND_SCALE_NONE,
     CondError,
     HostCsr,
     ResultT,
@@ -235,14 +237,25 @@ class Plan:
               "plan_solve_replay")
         return r, s
 
-    def spmv(self, x, transpose=False):
+    def spmv(self, x, transpose=False, col_scaled=False):
+        """y = A x (A^T x with transpose); with col_scaled the matrix is the
+        column-scaled A D_col^-1."""
         import torch
 
         px = _vec(x, self.n)
         y = torch.empty_like(x)
-        check(lib().cond_plan_spmv(self._h, 1 if transpose else 0, px, y.data_ptr()),
-              "plan_spmv")
+        flags = (1 if transpose else 0) | (2 if col_scaled else 0)
+        check(lib().cond_plan_spmv(self._h, flags, px, y.data_ptr()), "plan_spmv")
         return y
+
+    def column_norms(self):
+        """The column 2-norms of A (D_col of column scaling), on the device."""
+        import torch
+
+        d = torch.empty(self.n, dtype=torch.float64, device=self.workspace.device
+                        if self.workspace is not None else "cuda")
+        check(lib().cond_plan_column_norms(self._h, d.data_ptr()), "plan_column_norms")
+        return d
 
     def inverse_apply(self, x):
         import torch

@@ -27,6 +27,9 @@ COND_ETIMEOUT = -7
 COND_MIN_LU = 0
 COND_MIN_SPMV = 1
 COND_MIN_NONE = 2
+COND_SCALE_NONE = 0
+COND_SCALE_COL = 1
+COND_F_COLSCALED = 8
 COND_F_NUMSING = 1
 COND_F_MAXITER = 2
 COND_F_SINGULAR = 4
@@ -48,7 +51,7 @@ class OptsT(C.Structure):
                 ("eps", C.c_double), ("max_iter", C.c_int64), ("stop_rtol", C.c_double),
                 ("stop_window", C.c_int64), ("sigma_min_method", C.c_int32), ("chunk", C.c_int32),
                 ("col_perm", C.c_void_p), ("pivot_tol", C.c_double), ("profile", C.c_int32),
-                ("alpha_min", C.c_double), ("alpha_decay", C.c_double)]
+                ("alpha_min", C.c_double), ("alpha_decay", C.c_double), ("scaling", C.c_int32)]
 
 
 class BoundsT(C.Structure):
@@ -79,7 +82,7 @@ EXPORTS = (
     "cond_batch_info", "cond_batch_bind", "cond_batch_run", "cond_batch_destroy",
     "cond_cnn_param_count", "cond_cnn_create", "cond_cnn_set_params", "cond_cnn_get_params",
     "cond_cnn_predict", "cond_cnn_gradients", "cond_cnn_train_step", "cond_cnn_activation",
-    "cond_cnn_destroy", "cond_plan_error_bounds",
+    "cond_cnn_destroy", "cond_plan_error_bounds", "cond_plan_column_norms",
 )
 
 BATCH_K = 8
@@ -142,6 +145,8 @@ def lib():
     L.cond_cnn_activation.argtypes = [vp, i32, i32, i32, vp]
     L.cond_cnn_destroy.argtypes = [vp]
     L.cond_cnn_destroy.restype = None
+    L.cond_plan_column_norms.argtypes = [vp, vp]
+    L.cond_plan_error_bounds.argtypes = [vp, vp, vp, dbl, dbl, C.POINTER(BoundsT)]
     for name in EXPORTS:
         getattr(L, name)  # raises AttributeError if a declared symbol is missing
     _lib = L

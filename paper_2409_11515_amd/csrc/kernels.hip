@@ -134,11 +134,17 @@ __global__ __launch_bounds__(kBlock) void normalise_k(int n, double* __restrict_
 constexpr int kStreamCap = 2048;
 constexpr int kTileRows = 256;
 
-template <typename IT>
+//
+// Column scaling (SC): y = R A C x with C = diag(cs) applied to the gathered
+// x (cs may be null: no column factor) and R = diag(rs) to each row's sum (rs
+// may be null). A D^-1 is then cs = 1/d on A, and (A D^-1)^T = D^-1 A^T is
+// rs = 1/d on the stored A^T.
+template <typename IT, bool SC>
 __global__ __launch_bounds__(kBlock) void spmv_stream_k(
     int ntiles, const int* __restrict__ tiles, const IT* __restrict__ rowptr,
     const int* __restrict__ col, const double* __restrict__ val, const double* __restrict__ x,
-    double* __restrict__ y, double* __restrict__ parts, const RunState* st) {
+    double* __restrict__ y, double* __restrict__ parts, const RunState* st,
+    const double* __restrict__ cs, const double* __restrict__ rs) {
   if (st && st->stop_req) return;
   __shared__ double prod[kStreamCap];
   __shared__ IT rp_sh[kTileRows + 1];
@@ -155,22 +161,29 @@ __global__ __launch_bounds__(kBlock) void spmv_stream_k(
     const IT ne = rp_sh[cnt] - e0;
     if (ne <= kStreamCap) {
 #pragma unroll 4
-      for (int e = threadIdx.x; e < static_cast<int>(ne); e += kBlock)
-        prod[e] = val[e0 + e] * x[col[e0 + e]];
+      for (int e = threadIdx.x; e < static_cast<int>(ne); e += kBlock) {
+        const int c = col[e0 + e];
+        prod[e] = val[e0 + e] * ((SC && cs) ? x[c] * cs[c] : x[c]);
+      }
       __syncthreads();
       if (threadIdx.x < cnt) {
         const int a = static_cast<int>(rp_sh[threadIdx.x] - e0);
         const int b = static_cast<int>(rp_sh[threadIdx.x + 1] - e0);
         double s = 0.0;
         for (int e = a; e < b; ++e) s += prod[e];
+        if (SC && rs) s *= rs[ra + threadIdx.x];
         y[ra + threadIdx.x] = s;
         sq += s * s;
       }
     } else {
       // one long row: every thread takes a strided share, then a block sum
       double acc = 0.0;
-      for (IT e = e0 + threadIdx.x; e < e0 + ne; e += kBlock) acc += val[e] * x[col[e]];
+      for (IT e = e0 + threadIdx.x; e < e0 + ne; e += kBlock) {
+        const int c = col[e];
+        acc += val[e] * ((SC && cs) ? x[c] * cs[c] : x[c]);
+      }
       acc = block_sum(acc);
+      if (SC && rs) acc *= rs[ra];
       if (threadIdx.x == 0) {
         y[ra] = acc;
         sq += acc * acc;
@@ -182,6 +195,65 @@ __global__ __launch_bounds__(kBlock) void spmv_stream_k(
     const double s = block_sum(sq);
     if (threadIdx.x == 0) parts[lb] = s;
   }
+}
+
+// ------------------------------------------------------------ row norms
+// out[i] = ||row i||_2 (16 lanes per row); on the stored A^T these are the
+// column norms of A, the D_col of column scaling.
+template <typename IT>
+__global__ __launch_bounds__(kBlock) void row_norms_k(int n, const IT* __restrict__ rowptr,
+                                                      const double* __restrict__ val,
+                                                      double* __restrict__ out) {
+  constexpr int kRowLanes = 16;
+  const int sub = threadIdx.x & (kRowLanes - 1);
+  const long long stride = static_cast<long long>(gridDim.x) * (kBlock / kRowLanes);
+  for (long long i = blockIdx.x * static_cast<long long>(kBlock / kRowLanes) + threadIdx.x / kRowLanes;
+       i < n; i += stride) {
+    double acc = 0.0;
+    for (IT e = rowptr[i] + sub; e < rowptr[i + 1]; e += kRowLanes) acc += val[e] * val[e];
+#pragma unroll
+    for (int off = kRowLanes / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kRowLanes);
+    if (sub == 0) out[i] = sqrt(acc);
+  }
+}
+
+// dinv = 1/d; dz[k] = d[perm[k]] (perm may be null: no dz), the factor of
+// the solves' reversed-order vector.
+__global__ __launch_bounds__(kBlock) void scale_prep_k(int n, const double* __restrict__ d,
+                                                       double* __restrict__ dinv,
+                                                       const int* __restrict__ perm,
+                                                       double* __restrict__ dz) {
+  for (long long i = blockIdx.x * static_cast<long long>(kBlock) + threadIdx.x; i < n;
+       i += static_cast<long long>(gridDim.x) * kBlock) {
+    dinv[i] = 1.0 / d[i];
+    if (perm) dz[i] = d[perm[i]];
+  }
+}
+
+// The sigma_min run of the column-scaled matrix: (A D^-1)^-1 = D A^-1. The
+// solve's output z (r = A^-1 x in reversed pivot order) becomes z <- dz z,
+// i.e. D r, whose squared norm goes to the partials; zz = dz z (= D D r) is
+// the right-hand side of the transposed solves, since (D A^-1)^T = A^-T D.
+__global__ __launch_bounds__(kBlock) void scale_sumsq_k(int n, double* __restrict__ z,
+                                                        const double* __restrict__ dz,
+                                                        double* __restrict__ zz,
+                                                        double* __restrict__ parts,
+                                                        const RunState* st) {
+#pragma clang fp contract(off)
+  if (st->stop_req) return;
+  const int lb = logical_block();
+  long long r0, r1;
+  block_range(n, lb, r0, r1);
+  double acc = 0.0;
+  for (long long i = r0 + threadIdx.x; i < r1; i += kBlock) {
+    const double f = dz[i];
+    const double zi = z[i] * f;
+    z[i] = zi;
+    zz[i] = zi * f;
+    acc += zi * zi;
+  }
+  const double s = block_sum(acc);
+  if (threadIdx.x == 0) parts[lb] = s;
 }
 
 // ---------------------------------------------------------------- sumsq
@@ -782,13 +854,47 @@ void launch_normalise(int n, double* x, const double* parts_xx, int grid, double
 }
 
 void launch_spmv(const DevCsr& a, const double* x, double* y, double* parts_y, int grid,
-                 const RunState* st, hipStream_t s) {
-  if (a.idx64)
-    spmv_stream_k<long long><<<grid, kBlock, 0, s>>>(
-        a.ntiles, a.tiles, static_cast<const long long*>(a.rowptr), a.col, a.val, x, y, parts_y, st);
+                 const RunState* st, hipStream_t s, const double* cs, const double* rs) {
+  const bool sc = cs || rs;
+  const long long* rp64 = static_cast<const long long*>(a.rowptr);
+  const int* rp32 = static_cast<const int*>(a.rowptr);
+  if (a.idx64 && sc)
+    spmv_stream_k<long long, true><<<grid, kBlock, 0, s>>>(a.ntiles, a.tiles, rp64, a.col, a.val,
+                                                           x, y, parts_y, st, cs, rs);
+  else if (a.idx64)
+    spmv_stream_k<long long, false><<<grid, kBlock, 0, s>>>(a.ntiles, a.tiles, rp64, a.col, a.val,
+                                                            x, y, parts_y, st, nullptr, nullptr);
+  else if (sc)
+    spmv_stream_k<int, true><<<grid, kBlock, 0, s>>>(a.ntiles, a.tiles, rp32, a.col, a.val, x, y,
+                                                     parts_y, st, cs, rs);
   else
-    spmv_stream_k<int><<<grid, kBlock, 0, s>>>(a.ntiles, a.tiles, static_cast<const int*>(a.rowptr),
-                                               a.col, a.val, x, y, parts_y, st);
+    spmv_stream_k<int, false><<<grid, kBlock, 0, s>>>(a.ntiles, a.tiles, rp32, a.col, a.val, x, y,
+                                                      parts_y, st, nullptr, nullptr);
+}
+
+void launch_row_norms(const DevCsr& a, double* out, hipStream_t s) {
+  long long blocks = (static_cast<long long>(a.n) + kBlock / 16 - 1) / (kBlock / 16);
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  if (a.idx64)
+    row_norms_k<long long><<<static_cast<int>(blocks), kBlock, 0, s>>>(
+        a.n, static_cast<const long long*>(a.rowptr), a.val, out);
+  else
+    row_norms_k<int><<<static_cast<int>(blocks), kBlock, 0, s>>>(
+        a.n, static_cast<const int*>(a.rowptr), a.val, out);
+}
+
+void launch_scale_prep(int n, const double* d, double* dinv, const int* perm, double* dz,
+                       hipStream_t s) {
+  long long blocks = (static_cast<long long>(n) + kBlock - 1) / kBlock;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  scale_prep_k<<<static_cast<int>(blocks), kBlock, 0, s>>>(n, d, dinv, perm, dz);
+}
+
+void launch_scale_sumsq(int n, double* z, const double* dz, double* zz, double* parts, int grid,
+                        const RunState* st, hipStream_t s) {
+  scale_sumsq_k<<<grid, kBlock, 0, s>>>(n, z, dz, zz, parts, st);
 }
 
 void launch_sumsq(int n, const double* z, double* parts, int grid, const RunState* st,

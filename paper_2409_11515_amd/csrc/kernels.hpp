@@ -123,8 +123,18 @@ void launch_init(int n, const double* x0, double* x, double* m, double* v, doubl
 void launch_normalise(int n, double* x, const double* parts_xx, int grid, double* parts_x,
                       RunState* st, double* const* resets, int nresets, unsigned* tickets,
                       int ntickets, hipStream_t s);
+// y = R A C x with C = diag(cs), R = diag(rs) when given (null: identity).
 void launch_spmv(const DevCsr& a, const double* x, double* y, double* parts_y, int grid,
-                 const RunState* st, hipStream_t s);
+                 const RunState* st, hipStream_t s, const double* cs = nullptr,
+                 const double* rs = nullptr);
+// out[i] = 2-norm of row i (column norms of A when a is the stored A^T).
+void launch_row_norms(const DevCsr& a, double* out, hipStream_t s);
+// dinv = 1/d and, when perm is given, dz[k] = d[perm[k]].
+void launch_scale_prep(int n, const double* d, double* dinv, const int* perm, double* dz,
+                       hipStream_t s);
+// z <- dz z with partials of its squared norm, and zz = dz z (after the scaling).
+void launch_scale_sumsq(int n, double* z, const double* dz, double* zz, double* parts, int grid,
+                        const RunState* st, hipStream_t s);
 void launch_sumsq(int n, const double* z, double* parts, int grid, const RunState* st,
                   hipStream_t s);
 void launch_trsv(const DevTri& t, const double* rhs, const int* rhs_perm, double* out,

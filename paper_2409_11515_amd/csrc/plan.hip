@@ -53,12 +53,14 @@ enum TriSlot {
 
 struct GraphKey {
   int route = -1;
+  int scaled = 0;
   int chunk = 0;
   const void* trace = nullptr;
   const void* xbest = nullptr;
   AdamParams p{};
   bool operator==(const GraphKey& o) const {
-    return route == o.route && chunk == o.chunk && trace == o.trace && xbest == o.xbest &&
+    return route == o.route && scaled == o.scaled && chunk == o.chunk && trace == o.trace &&
+           xbest == o.xbest &&
            std::memcmp(&p, &o.p, sizeof(p)) == 0;
   }
 };
@@ -375,6 +377,11 @@ struct cond_plan {
   int* d_scat_r = nullptr;    // r[col_perm[n-1-k]] = result of the reversed U solve
   double *x = nullptr, *m = nullptr, *v = nullptr, *d = nullptr, *y = nullptr, *w = nullptr;
   double *c = nullptr, *z = nullptr, *h = nullptr, *wv = nullptr;
+  // column scaling: D_col (column norms), its inverse, and D_col in the
+  // solves' reversed pivot order (dz[k] = d[col_perm[n-1-k]])
+  double *dcol = nullptr, *dinv = nullptr, *dz = nullptr;
+  bool has_zero_col = false;
+  bool scale_ready = false;
   double *parts_x = nullptr, *parts_y = nullptr, *parts_xd = nullptr, *parts_xx = nullptr;
   RunState* st = nullptr;
   RunState* st_free = nullptr;
@@ -401,6 +408,7 @@ struct cond_plan {
     size_t tri[4][kTriSlots];
     size_t row_perm, rev, scat_s, scat_r;
     size_t vec[10];
+    size_t scal[3];
     size_t parts[4];
     size_t st, st_free, tickets;
   } o{};
@@ -450,6 +458,7 @@ void plan_layout(cond_plan* p) {
   }
   const int nvec = p->want_min ? 10 : 6;
   for (int k = 0; k < nvec; ++k) p->o.vec[k] = L.take(n * 8);
+  for (int k = 0; k < 3; ++k) p->o.scal[k] = L.take(n * 8);
   for (int k = 0; k < 4; ++k) p->o.parts[k] = L.take(kMaxParts * 8);
   p->o.st = L.take(sizeof(RunState));
   p->o.st_free = L.take(sizeof(RunState));
@@ -551,6 +560,8 @@ int check_opts(const cond_opts_t* o) {
   if (!(o->alpha_min >= 0) || o->alpha_min > o->alpha ||
       (o->alpha_min > 0 && !(o->alpha_decay > 0 && o->alpha_decay < 1)))
     return fail(COND_EINVAL, "invalid step-size floor or decay");
+  if (o->scaling != COND_SCALE_NONE && o->scaling != COND_SCALE_COL)
+    return fail(COND_EINVAL, "unknown scaling");
   if (o->sigma_min_method != COND_MIN_LU && o->sigma_min_method != COND_MIN_SPMV &&
       o->sigma_min_method != COND_MIN_NONE)
     return fail(COND_EINVAL, "unknown sigma_min method");
@@ -590,17 +601,24 @@ struct Prof {
 // One iteration of the chosen route, enqueued on the plan stream: 0 the
 // sigma_max run (M = A), 1 the sigma_min run of Algorithm 2 (M = A^-1), 2 the
 // SpMV-only sigma_min ablation (M = A, minimising; ap.minimise is set).
-void enqueue_iteration(cond_plan* p, int route, double* trace, double* xbest, const AdamParams& ap) {
+// With `scaled` the matrix is A D^-1 (column scaling): the products take the
+// factor 1/d on the fly, and the sigma_min run multiplies the solve's output
+// by D twice (see scale_sumsq_k), so A's own LU serves.
+void enqueue_iteration(cond_plan* p, int route, bool scaled, double* trace, double* xbest,
+                       const AdamParams& ap) {
   hipStream_t s = p->stream;
   const int n = p->n, g = p->grid;
   const double dn = n;
+  const double scale_bytes = scaled ? 8.0 * dn : 0.0;
   if (route != 1) {
     { Prof pr(p, COND_K_NORMALISE, 16.0 * dn);
       launch_normalise(n, p->x, p->parts_xx, g, p->parts_x, p->st, nullptr, 0, nullptr, 0, s); }
-    { Prof pr(p, COND_K_SPMV_A, spmv_bytes(p->dA));
-      launch_spmv(p->dA, p->x, p->y, p->parts_y, g, p->st, s); }
-    { Prof pr(p, COND_K_SPMV_AT, spmv_bytes(p->dAt));
-      launch_spmv(p->dAt, p->y, p->w, nullptr, g, p->st, s); }
+    { Prof pr(p, COND_K_SPMV_A, spmv_bytes(p->dA) + scale_bytes);
+      launch_spmv(p->dA, p->x, p->y, p->parts_y, g, p->st, s, scaled ? p->dinv : nullptr,
+                  nullptr); }
+    { Prof pr(p, COND_K_SPMV_AT, spmv_bytes(p->dAt) + scale_bytes);
+      launch_spmv(p->dAt, p->y, p->w, nullptr, g, p->st, s, nullptr,
+                  scaled ? p->dinv : nullptr); }
   } else {
     const double nl = static_cast<double>(p->lu->l_rows.nnz());
     const double nu = static_cast<double>(p->lu->u_rows.nnz());
@@ -613,11 +631,17 @@ void enqueue_iteration(cond_plan* p, int route, double* trace, double* xbest, co
       launch_trsv(p->dL, p->x, p->d_row_perm, p->c, nullptr, nullptr, p->tickets + 0, p->st, s); }
     { Prof pr(p, COND_K_TRSV_U, 12.0 * nu + rp + 36.0 * dn);
       launch_trsv(p->dU, p->c, p->d_rev, p->z, nullptr, nullptr, p->tickets + 1, p->st, s); }
-    { Prof pr(p, COND_K_SUMSQ, 8.0 * dn);
-      launch_sumsq(n, p->z, p->parts_y, g, p->st, s); }
+    // scaled: z <- D z (= D r) and c <- D z (the transposed solves' input;
+    // c, the L solve's output, is free once the U solve has run)
+    { Prof pr(p, COND_K_SUMSQ, scaled ? 32.0 * dn : 8.0 * dn);
+      if (scaled)
+        launch_scale_sumsq(n, p->z, p->dz, p->c, p->parts_y, g, p->st, s);
+      else
+        launch_sumsq(n, p->z, p->parts_y, g, p->st, s); }
     // s = A^-T r: U^T h = Q^T r = z, L^T wv = h, s = P^T wv (wv kept reversed)
     { Prof pr(p, COND_K_TRSV_UT, 12.0 * nu + rp + 36.0 * dn);
-      launch_trsv(p->dUt, p->z, p->d_rev, p->h, nullptr, nullptr, p->tickets + 2, p->st, s); }
+      launch_trsv(p->dUt, scaled ? p->c : p->z, p->d_rev, p->h, nullptr, nullptr, p->tickets + 2,
+                  p->st, s); }
     { Prof pr(p, COND_K_TRSV_LT, 12.0 * nl + rp + 40.0 * dn);
       launch_trsv(p->dLt, p->h, p->d_rev, p->wv, p->w, p->d_scat_s, p->tickets + 3, p->st, s); }
   }
@@ -642,10 +666,11 @@ int collect_profile(cond_plan* p) {
   return COND_OK;
 }
 
-int get_graph(cond_plan* p, int route, int chunk, double* trace, double* xbest,
+int get_graph(cond_plan* p, int route, bool scaled, int chunk, double* trace, double* xbest,
               const AdamParams& ap, hipGraphExec_t* out) {
   GraphKey k;
   k.route = route;
+  k.scaled = scaled ? 1 : 0;
   k.chunk = chunk;
   k.trace = trace;
   k.xbest = xbest;
@@ -660,7 +685,7 @@ int get_graph(cond_plan* p, int route, int chunk, double* trace, double* xbest,
   }
   hipGraph_t graph = nullptr;
   CHK(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
-  for (int it = 0; it < chunk; ++it) enqueue_iteration(p, route, trace, xbest, ap);
+  for (int it = 0; it < chunk; ++it) enqueue_iteration(p, route, scaled, trace, xbest, ap);
   hipError_t e = hipStreamEndCapture(p->stream, &graph);
   if (e != hipSuccess) return fail(COND_EHIP, std::string("capture: ") + hipGetErrorString(e));
   e = hipGraphInstantiate(&p->exec[route], graph, nullptr, nullptr, 0);
@@ -713,6 +738,18 @@ int join_user_stream(cond_plan* p) {
   return COND_OK;
 }
 
+// Column norms and the factors of the column-scaled matrix, computed once
+// per bind on the first call that needs them.
+int ensure_scaling(cond_plan* p) {
+  if (p->has_zero_col) return fail(COND_EINVAL, "A has a zero column: no column scaling");
+  if (p->scale_ready) return COND_OK;
+  launch_row_norms(p->dAt, p->dcol, p->stream);
+  launch_scale_prep(p->n, p->dcol, p->dinv, p->want_min ? p->d_scat_r : nullptr, p->dz, p->stream);
+  CHK(hipGetLastError());
+  p->scale_ready = true;
+  return COND_OK;
+}
+
 struct RouteResult {
   double sigma = 0.0;
   long long iters = 0;
@@ -725,6 +762,7 @@ int run_route(cond_plan* p, int route, const cond_opts_t& o, const double* x0, d
               double* xbest, RouteResult& rr) {
   AdamParams ap = params_of(o);
   ap.minimise = route == 2 ? 1 : 0;
+  const bool scaled = o.scaling == COND_SCALE_COL;
   const long long total = o.max_iter + 1;  // the last pass only evaluates x_T
   if (o.profile) {
     // eager launches with an event pair around each kernel; poll every iteration
@@ -735,7 +773,7 @@ int run_route(cond_plan* p, int route, const cond_opts_t& o, const double* x0, d
     p->profiling = true;
     int st = COND_OK;
     for (long long it = 0; it < total && st == COND_OK; ++it) {
-      enqueue_iteration(p, route, trace, xbest, ap);
+      enqueue_iteration(p, route, scaled, trace, xbest, ap);
       if (hipMemcpyAsync(p->h_state, p->st, sizeof(RunState), hipMemcpyDeviceToHost,
                          p->stream) != hipSuccess ||
           hipStreamSynchronize(p->stream) != hipSuccess) {
@@ -750,7 +788,7 @@ int run_route(cond_plan* p, int route, const cond_opts_t& o, const double* x0, d
   } else {
     const int chunk = o.chunk > 0 ? o.chunk : (route == 1 ? 4 : 32);
     hipGraphExec_t exec = nullptr;
-    int st = get_graph(p, route, chunk, trace, xbest, ap, &exec);
+    int st = get_graph(p, route, scaled, chunk, trace, xbest, ap, &exec);
     if (st) return st;
     CHK(hipEventRecord(p->ev_start, p->stream));
     launch_init(p->n, x0, p->x, p->m, p->v, p->parts_xx, p->grid, p->st, o.alpha, ap.minimise,
@@ -790,6 +828,11 @@ int cond_plan_create(const cond_csr_t* A, const cond_opts_t* o, cond_plan_t** ou
     transpose(p->a, p->at);
     p->tiles_a = make_tiles(p->a);
     p->tiles_at = make_tiles(p->at);
+    for (int32_t j = 0; j < p->at.n && !p->has_zero_col; ++j) {
+      bool nz = false;
+      for (int64_t e = p->at.rowptr[j]; e < p->at.rowptr[j + 1] && !nz; ++e) nz = p->at.val[e] != 0.0;
+      p->has_zero_col = !nz;
+    }
     p->n = p->a.n;
     p->opts = *o;
     p->opts.col_perm = nullptr;
@@ -900,6 +943,10 @@ int cond_plan_bind(cond_plan_t* p, void* workspace, size_t bytes, void* stream) 
   double** vecs[10] = {&p->x, &p->m, &p->v, &p->d, &p->y, &p->w, &p->c, &p->z, &p->h, &p->wv};
   const int nvec = p->want_min ? 10 : 6;
   for (int k = 0; k < nvec; ++k) *vecs[k] = at_off<double>(p, p->o.vec[k]);
+  p->dcol = at_off<double>(p, p->o.scal[0]);
+  p->dinv = at_off<double>(p, p->o.scal[1]);
+  p->dz = at_off<double>(p, p->o.scal[2]);
+  p->scale_ready = false;
   p->parts_x = at_off<double>(p, p->o.parts[0]);
   p->parts_y = at_off<double>(p, p->o.parts[1]);
   p->parts_xd = at_off<double>(p, p->o.parts[2]);
@@ -952,6 +999,10 @@ int cond_plan_run(cond_plan_t* p, const cond_opts_t* o, const double* x0_max, co
     std::fill(p->kms, p->kms + COND_K_COUNT, 0.0);
     std::fill(p->kcnt, p->kcnt + COND_K_COUNT, 0LL);
     std::fill(p->kbytes, p->kbytes + COND_K_COUNT, 0.0);
+  }
+  if (oo.scaling == COND_SCALE_COL) {
+    if ((st = ensure_scaling(p))) return st;
+    out->flags |= COND_F_COLSCALED;
   }
   // the sigma_min route: Algorithm 2 when the plan holds the LU, or the
   // SpMV-only ablation, which any plan can run
@@ -1109,8 +1160,30 @@ int cond_plan_spmv(cond_plan_t* p, int transpose, const double* x, double* y) {
   if (!p->bound) return fail(COND_ESTATE, "plan not bound");
   int st0 = join_user_stream(p);
   if (st0) return st0;
-  launch_spmv(transpose ? p->dAt : p->dA, x, y, nullptr, p->grid, nullptr, p->stream);
+  if (transpose & ~(COND_SPMV_T | COND_SPMV_COLSCALED)) return fail(COND_EINVAL, "unknown spmv flags");
+  const bool tr = transpose & COND_SPMV_T;
+  const bool scaled = transpose & COND_SPMV_COLSCALED;
+  if (scaled && (st0 = ensure_scaling(p))) return st0;
+  const double* cs = scaled && !tr ? p->dinv : nullptr;
+  const double* rs = scaled && tr ? p->dinv : nullptr;
+  launch_spmv(tr ? p->dAt : p->dA, x, y, nullptr, p->grid, nullptr, p->stream, cs, rs);
   CHK(hipGetLastError());
+  CHK(hipStreamSynchronize(p->stream));
+  return COND_OK;
+}
+
+int cond_plan_column_norms(cond_plan_t* p, double* d) {
+  if (!p || !d) return fail(COND_EINVAL, "null argument");
+  if (!p->bound) return fail(COND_ESTATE, "plan not bound");
+  int st = join_user_stream(p);
+  if (st) return st;
+  if (p->has_zero_col) {
+    launch_row_norms(p->dAt, p->dcol, p->stream);  // the norms exist, the scaling does not
+    CHK(hipGetLastError());
+  } else if ((st = ensure_scaling(p))) {
+    return st;
+  }
+  CHK(hipMemcpyAsync(d, p->dcol, static_cast<size_t>(p->n) * 8, hipMemcpyDeviceToDevice, p->stream));
   CHK(hipStreamSynchronize(p->stream));
   return COND_OK;
 }
