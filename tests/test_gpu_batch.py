@@ -118,3 +118,29 @@ def test_batch_autotuner_picks_a_candidate(torch_cuda):
     b = pa.Batch([(m.n, m.rowptr, m.col, m.val) for m in mats]).bind()
     assert b.tile_rows in (32, 64, 128, 256) and b.grid in (1024, 2048, 4096)
     b.close()
+
+
+def test_c4_shaped_batch_matches_oracle(torch_cuda):
+    """Systems of the batched workload itself (64-system draw, sides 51-401),
+    six of them including two above 200, under the autotuned schedule and the
+    bench's options: for two starts of every system the oracle's run stops at
+    the same update and reaches the same best value."""
+    import paper_2409_11515_amd as pa
+
+    torch = torch_cuda
+    specs = hm_batch_specs()  # the batched workload's draw
+    pick = [8, 1, 9, 15, 11, 13]  # sides 64, 81, 84, 107, 203, 219
+    mats = [hydromech2d(specs[i][0], log_eta=specs[i][1], log_k=specs[i][2]) for i in pick]
+    assert sum(m.n > 6 * 200 * 200 for m in mats) == 2
+    starts = [start_block(m.n, 8, 3000 + i) for i, m in enumerate(mats)]
+    b = pa.Batch([(m.n, m.rowptr, m.col, m.val) for m in mats]).bind()  # autotuned
+    opts = dict(max_iter=6000, stop_rtol=1e-6, stop_window=25, alpha=1e-2, alpha_min=2.5e-3,
+                alpha_decay=0.5)
+    r = b.run(torch.as_tensor(pa.interleave_starts(starts), device="cuda"), **opts)
+    b.close()
+    for i, m in enumerate(mats):
+        apply, evaluate = forward_apply(m.n, m.rowptr, m.col, m.val)
+        for k in (2, 7):
+            o = projected_adam(apply, evaluate, starts[i][k], PAOptions(**opts))
+            assert r["pair_iters"][i, k] == o.iters, (i, k)
+            assert r["pair_best"][i, k] == pytest.approx(o.sigma, rel=1e-9)

@@ -4,7 +4,8 @@ and triangular-solve schedule).
 
 - 1001x1001-node hydro-mechanical system (n = 6,012,006, nnz = 39,984,010):
   every row of A x and A^T x against the oracle's products, within 1e-12 of
-  (|A||x|)_i componentwise.
+  (|A||x|)_i componentwise; the first 20 updates of the sigma_max run in
+  lockstep with the oracle (traced values to 1e-10).
 - 201x201-node system (n = 242,406): Algorithm 2's two solves by their
   componentwise backward error (a property that holds at any size), and the
   whole estimate with the benchmark's options against the oracle's, stored
@@ -41,23 +42,48 @@ def _dev(torch, x):
     return torch.as_tensor(np.ascontiguousarray(x, np.float64), device="cuda")
 
 
-def test_spmv_full_size_every_row(torch_cuda):
+@pytest.fixture(scope="module")
+def hm1001(torch_cuda):
     import paper_2409_11515_amd as pa
 
-    torch = torch_cuda
     a = hydromech2d(1001, seed=2)
     assert a.n == 6012006
     p = pa.Plan(a.n, a.rowptr, a.col, a.val, sigma_min_method=pa.COND_MIN_NONE).bind()
+    yield a, p
+    p.close()
+
+
+def test_spmv_full_size_every_row(torch_cuda, hm1001):
+    torch = torch_cuda
+    a, p = hm1001
     # magnitudes over ten decades, so that no row's sum is dominated by luck
     x = start_vector(a.n, 5) * 10.0 ** np.random.default_rng(3).uniform(-5, 5, a.n)
     y = p.spmv(_dev(torch, x)).cpu().numpy()
     err = np.abs(y - oracle_spmv(a.rowptr, a.col, a.val, x))
     assert np.all(err <= 1e-12 * spmv_abs(a.rowptr, a.col, a.val, x) + 1e-300)
     yt = p.spmv(_dev(torch, x), transpose=True).cpu().numpy()
-    p.close()
     tr, tc, tv = transpose_csr(a.n, a.rowptr, a.col, a.val)
     errt = np.abs(yt - oracle_spmv(tr, tc, tv, x))
     assert np.all(errt <= 1e-12 * spmv_abs(tr, tc, tv, x) + 1e-300)
+
+
+def test_sigma_max_full_size_lockstep(torch_cuda, hm1001):
+    # the sigma_max run on the 6M-row system in the bench's launch
+    # configuration and first step: its first 20 traced values against the
+    # oracle's run from the same start (one oracle update costs ~0.3 s here)
+    from oracle import PAOptions
+    from oracle.estimate import forward_apply
+    from oracle.padam import projected_adam
+
+    torch = torch_cuda
+    a, p = hm1001
+    x0 = start_vector(a.n, 11)
+    g = p.run(_dev(torch, x0), trace=True, max_iter=20, alpha=4e-2)
+    apply, evaluate = forward_apply(a.n, a.rowptr, a.col, a.val)
+    o = projected_adam(apply, evaluate, x0, PAOptions(max_iter=20, alpha=4e-2))
+    assert g["iters_max"] == o.iters == 20
+    np.testing.assert_allclose(g["trace_max"], o.trace, rtol=1e-10)
+    assert g["sigma_max"] == pytest.approx(o.sigma, rel=1e-10)
 
 
 @pytest.fixture(scope="module")
