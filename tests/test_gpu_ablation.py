@@ -2,9 +2,11 @@
 
 Not the paper's method: Projected Adam descending on log||A v|| - log||v||
 with products by A and A^T only, keeping the smallest ||A x|| / ||x||. The
-oracle is ``oracle.ablation.minimise_by_spmv``. Bars: the traced values in
-lockstep (1e-10), the same stopping update under the stop rule and the
-step-size floor, and the closed form on a well-conditioned diagonal matrix.
+oracle is ``oracle.ablation.minimise_by_spmv``. Bars: on a well-conditioned
+diagonal matrix the closed form, the same stopping update under the stop
+rule and step-size floor and the whole trace in lockstep (1e-10); on the
+hydro-mechanical systems, where the descent amplifies rounding differences,
+lockstep over the first 25 updates and the upper-bound property.
 """
 
 import numpy as np
@@ -59,19 +61,22 @@ def test_spmv_min_diagonal_closed_form(torch_cuda):
 
 @pytest.mark.parametrize("side,seed", [(9, 1), (24, 3)])
 def test_spmv_min_lockstep_hm(torch_cuda, side, seed):
-    # the hydro-mechanical systems: the ablation stays far above sigma_min
-    # (the LU route's value) but both sides take the same path
+    # On the hydro-mechanical systems the descent does not settle: it
+    # amplifies any rounding difference about tenfold every few updates (the
+    # oracle against itself from a start perturbed by 1e-15: 6e-13 apart
+    # after 25 updates, 5e-9 after 50, 3e-3 after 100). So the two sides are
+    # held in lockstep over the first 25 updates only; beyond that each
+    # stays an upper bound of sigma_min (the LU route's value), far above it.
     a = hydromech2d(side, seed=seed)
-    kw = dict(max_iter=3000, stop_rtol=1e-7, stop_window=25)
+    kw = dict(max_iter=400)
     g = _gpu_min(torch_cuda, a, seed, **kw)
     o = _oracle_min(a, seed, **kw)
-    assert g["iters_min"] == o.iters
-    np.testing.assert_allclose(g["trace_min"][:200], o.trace[:200], rtol=1e-10)
-    assert g["sigma_min"] == pytest.approx(o.sigma, rel=1e-6)
-    if side == 9:
-        lu = oracle_estimate(a.n, a.rowptr, a.col, a.val, start_vector(a.n, seed),
-                             opts=PAOptions(max_iter=3000))
-        assert g["sigma_min"] >= lu["sigma_min"] * (1 - 1e-12)
+    assert g["iters_min"] == o.iters == 400
+    np.testing.assert_allclose(g["trace_min"][:25], o.trace[:25], rtol=1e-10)
+    lu = oracle_estimate(a.n, a.rowptr, a.col, a.val, start_vector(a.n, seed),
+                         opts=PAOptions(max_iter=3000))
+    assert g["sigma_min"] >= lu["sigma_min"] * (1 - 1e-12)
+    assert o.sigma >= lu["sigma_min"] * (1 - 1e-12)
 
 
 def test_spmv_min_with_sigma_max_gives_kappa(torch_cuda):
