@@ -309,6 +309,43 @@ int cond_batch_run(cond_batch_t* b, const cond_opts_t* o, const double* x0, doub
                    double* x_best, double* ms);
 void cond_batch_destroy(cond_batch_t* b);
 
+/* The batched sigma_min run (Algorithm 2 for every (matrix, start) pair).
+ * Needs a batch created with o->sigma_min_method = COND_MIN_LU: create then
+ * factors every matrix on the host (P_m A_m Q_m = L_m U_m, in parallel
+ * threads, one matrix per thread) and merges the factors block-diagonally,
+ * each matrix's pivot rows kept together; each update's four triangular
+ * solves then take every matrix and all 8 starts in one launch each (one
+ * read of a factor entry serves the 8 starts, and the matrices' dependency
+ * levels overlap). Arguments as cond_batch_run; pair_best receives each
+ * pair's largest ||A^-1 x|| / ||x|| and sigma_min[count] = 1 / the largest
+ * over a matrix's starts (each start gives an upper bound of sigma_min).
+ * COND_ESTATE for a batch created without the route. */
+int cond_batch_run_min(cond_batch_t* b, const cond_opts_t* o, const double* x0, double* sigma_min,
+                       double* pair_best, int64_t* pair_iters, int32_t* pair_status, double* trace,
+                       double* x_best, double* ms);
+/* Algorithm 2's r = A_m^-1 x and s = A_m^-T r for every (matrix, start) on
+ * the host, from the same merged factors and solve schedules the device
+ * runs (tasks in ticket order); x, r, s: host arrays in the batch layout
+ * (row0[count] * 8). For checking the batched solves without a device.
+ * COND_ESTATE if a task would read a value solved by a later ticket;
+ * COND_EINVAL for a batch without the sigma_min route. */
+int cond_batch_solve_replay(const cond_batch_t* b, const double* x, double* r, double* s);
+/* Fill of the merged factors (strictly lower L; U with its diagonal) and the
+ * host time of the per-matrix LUs, of a batch with the sigma_min route. */
+int cond_batch_fill(const cond_batch_t* b, int64_t* nnz_l, int64_t* nnz_u, double* lu_ms);
+
+/* kappa_2 of every matrix of a batch: create (with the LUs) + bind (library
+ * memory, autotuned schedule) + the sigma_max and sigma_min runs + destroy.
+ * x0_max, x0_min: device start vectors in the batch layout (8 starts per
+ * row, rows of the matrices concatenated; x0_min = NULL uses x0_max).
+ * outs[count]: per matrix sigma_max, sigma_min and kappa from its best
+ * starts, iters_max / iters_min = the most updates any of its starts took,
+ * status of its first failed start (if any), flags (COND_F_NUMSING), the
+ * device time of each whole batched run and the set-up time. */
+int cond_estimate_batched(const cond_csr_t* As, int32_t count, const cond_opts_t* o,
+                          const double* x0_max, const double* x0_min, void* stream,
+                          cond_result_t* outs);
+
 /* ------------------------------------------------------ learned warm start
  * A start vector for the sigma_min run (Algorithm 2) predicted from the two
  * coefficient fields of a hydro-mechanical grid by a small CNN: four 3x3
@@ -357,6 +394,15 @@ int cond_cnn_train_step(cond_cnn_t* net, const double* fields, const float* labe
 int cond_cnn_activation(const cond_cnn_t* net, int32_t layer, int32_t batch, int32_t side,
                         float* host);
 void cond_cnn_destroy(cond_cnn_t* net);
+
+/* Measurement: the streaming ceiling of the device. a = b + scale c over n
+ * doubles (device arrays, 16-byte aligned, caller-owned; 24 n bytes move per
+ * launch), `grid` blocks of 256 threads, timed over `reps` launches after one
+ * warm-up on `stream`; *ms = average milliseconds per launch. The HBM-bound
+ * kernels of the estimator are quoted against this as well as against the
+ * vendor peak. */
+int cond_stream_triad(int64_t n, double* a, const double* b, const double* c, double scale,
+                      int32_t grid, int32_t reps, void* stream, double* ms);
 
 /* ------------------------------------------------------------ error bounds
  * What the paper computes kappa for (section "Error estimates and

@@ -33,7 +33,7 @@ from ._binding import (  # noqa: F401
 )
 
 __all__ = ["csr_check", "csr_transpose", "order_nd", "LU", "Plan", "Batch", "CNN", "interleave_starts",
-           "estimate_cond", "CondError"]
+           "estimate_cond", "estimate_batched", "CondError"]
 
 
 def version() -> int:
@@ -294,19 +294,23 @@ class Plan:
 
 
 class Batch:
-    """Batched multi-start sigma_max run over many matrices (8 starts each).
+    """Batched multi-start runs over many matrices (8 starts each).
 
-    ``Batch([(n, rowptr, col, val), ...], **opts).bind()`` concatenates the
-    matrices block-diagonally; ``run(x0)`` takes a CUDA float64 tensor of
-    ``rows * 8`` entries (row i, start k at index 8*i + k; see ``row0``).
+    ``Batch([(n, rowptr, col, val), ...], sigma_min=False, **opts).bind()``
+    concatenates the matrices block-diagonally (with ``sigma_min=True`` it
+    also factors every matrix for the sigma_min run); ``run(x0)`` is the
+    sigma_max run and ``run_min(x0)`` the sigma_min run, each taking a CUDA
+    float64 tensor of ``rows * 8`` entries (row i, start k at index 8*i + k;
+    see ``row0``).
     """
 
     K = 8
 
-    def __init__(self, mats, **opts):
+    def __init__(self, mats, sigma_min=False, **opts):
         from ._binding import CsrT
 
         self._h = C.c_void_p()
+        opts.setdefault("sigma_min_method", COND_MIN_LU if sigma_min else COND_MIN_NONE)
         self.opts = make_opts(**opts)
         self._keep = [HostCsr(*m) for m in mats]
         arr = (CsrT * len(self._keep))(*[h.struct for h in self._keep])
@@ -333,7 +337,28 @@ class Batch:
         self.tile_rows, self.grid = tr.value, gr.value
         return self
 
-    def run(self, x0, trace=False, **opts) -> dict:
+    def fill(self) -> dict:
+        """nnz of the merged factors and the host LU time (sigma_min batches)."""
+        nl, nu, ms = C.c_int64(), C.c_int64(), C.c_double()
+        check(lib().cond_batch_fill(self._h, C.byref(nl), C.byref(nu), C.byref(ms)), "batch_fill")
+        return {"nnz_l": nl.value, "nnz_u": nu.value, "lu_s": ms.value / 1e3}
+
+    def solve_replay(self, x):
+        """(r, s) = (A_m^-1 x, A_m^-T r) per (matrix, start) on the host from
+        the device-ready merged solve schedules (numpy, batch layout)."""
+        x = np.ascontiguousarray(x, np.float64)
+        r = np.empty_like(x)
+        s = np.empty_like(x)
+        check(lib().cond_batch_solve_replay(self._h, x.ctypes.data, r.ctypes.data, s.ctypes.data),
+              "batch_solve_replay")
+        return r, s
+
+    def run_min(self, x0, trace=False, **opts) -> dict:
+        """The sigma_min run (Algorithm 2) of every (matrix, start) pair;
+        ``pair_best`` holds ||A^-1 x|| / ||x||, ``sigma_min`` 1 / its maximum."""
+        return self.run(x0, trace=trace, _route=1, **opts)
+
+    def run(self, x0, trace=False, _route=0, **opts) -> dict:
         import torch
 
         o = make_opts(**{**{f: getattr(self.opts, f) for f, _ in self.opts._fields_
@@ -347,15 +372,16 @@ class Batch:
         tr = torch.zeros(npairs * int(o.max_iter), dtype=torch.float64,
                          device=x0.device) if trace else None
         ms = C.c_double()
-        st = lib().cond_batch_run(self._h, C.byref(o), px, smax.ctypes.data,
-                                  best.ctypes.data, iters.ctypes.data, status.ctypes.data,
-                                  None if tr is None else tr.data_ptr(), None, C.byref(ms))
-        out = dict(sigma_max=smax, pair_best=best.reshape(self.count, self.K),
+        fn = lib().cond_batch_run_min if _route == 1 else lib().cond_batch_run
+        st = fn(self._h, C.byref(o), px, smax.ctypes.data, best.ctypes.data, iters.ctypes.data,
+                status.ctypes.data, None if tr is None else tr.data_ptr(), None, C.byref(ms))
+        out = dict(pair_best=best.reshape(self.count, self.K),
                    pair_iters=iters.reshape(self.count, self.K),
                    pair_status=status.reshape(self.count, self.K), ms=ms.value, status=st)
+        out["sigma_min" if _route == 1 else "sigma_max"] = smax
         if trace:
             out["trace"] = tr.view(self.count, self.K, int(o.max_iter)).cpu().numpy()
-        check(st, "batch_run")
+        check(st, "batch_run_min" if _route == 1 else "batch_run")
         return out
 
     def close(self):
@@ -376,6 +402,44 @@ def interleave_starts(starts_per_matrix) -> np.ndarray:
     vector in the batch layout: global row i, start k at index 8*i + k."""
     return np.ascontiguousarray(np.concatenate(
         [np.asarray(s, np.float64).T.reshape(-1) for s in starts_per_matrix]))
+
+
+def stream_triad(n, grid=4096, reps=20, stream=None) -> dict:
+    """The device's streaming ceiling: a = b + s c over n doubles (24 n bytes
+    per launch) by the library's own kernel; average ms per launch and GB/s."""
+    import torch
+
+    a = torch.empty(n, dtype=torch.float64, device="cuda")
+    b = torch.rand(n, dtype=torch.float64, device="cuda")
+    c = torch.rand(n, dtype=torch.float64, device="cuda")
+    ms = C.c_double()
+    check(lib().cond_stream_triad(int(n), a.data_ptr(), b.data_ptr(), c.data_ptr(), 0.5, int(grid),
+                                  int(reps), _stream_ptr(torch, stream), C.byref(ms)), "stream_triad")
+    ref = b + 0.5 * c
+    if not torch.equal(a, ref):
+        raise RuntimeError("triad kernel wrote wrong values")
+    return {"ms": ms.value, "bytes": 24.0 * n, "gbs": 24.0 * n / (ms.value * 1e-3) / 1e9}
+
+
+def estimate_batched(mats, x0_max, x0_min=None, stream=None, **opts) -> list:
+    """cond_estimate_batched: kappa_2 of every matrix of [(n, rowptr, col,
+    val), ...] from 8 starts each (x0 in the batch layout, CUDA float64);
+    one result dict per matrix."""
+    import torch
+
+    from ._binding import CsrT
+
+    keep = [HostCsr(*m) for m in mats]
+    rows = sum(h.n for h in keep)
+    arr = (CsrT * len(keep))(*[h.struct for h in keep])
+    o = make_opts(**opts)
+    outs = (ResultT * len(keep))()
+    p_max = _vec(x0_max, rows * Batch.K, "x0_max")
+    p_min = None if x0_min is None else _vec(x0_min, rows * Batch.K, "x0_min")
+    check(lib().cond_estimate_batched(C.cast(arr, C.c_void_p), len(keep), C.byref(o), p_max, p_min,
+                                      _stream_ptr(torch, stream), C.cast(outs, C.c_void_p)),
+          "estimate_batched")
+    return [{f: getattr(r, f) for f, _ in ResultT._fields_} for r in outs]
 
 
 def estimate_cond(n, rowptr, col, val, x0_max, x0_min=None, stream=None, **opts) -> dict:

@@ -5,17 +5,21 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <future>
 #include <memory>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "batch.hpp"
 #include "condest.h"
 #include "internal.hpp"
+#include "panels.hpp"
 
 using namespace condest;
 
@@ -28,7 +32,7 @@ using namespace condest;
 
 namespace {
 
-constexpr size_t kAl = 256;
+constexpr size_t kAl = kAlign;
 const int kTileCandidates[] = {32, 64, 128, 256};
 const int kGridCandidates[] = {1024, 2048, 4096};
 
@@ -74,10 +78,23 @@ struct cond_batch {
   BatchPair* h_pairs = nullptr;  // pinned, two slots of nmat*K
   hipGraphExec_t exec = nullptr;
   BatchKey key;
+  // sigma_min route: every matrix's LU (P_m A_m Q_m = L_m U_m, factored in
+  // parallel threads), merged into block-diagonal factors whose pivot rows
+  // keep each matrix's rows together, and the four solve schedules of them
+  bool want_min = false;
+  PanelCsr pL, pU, pUt, pLt;
+  std::vector<int32_t> row_perm, rev, scat_s, scat_r;  // scat_r: host replay only
+  DevTri dL, dU, dUt, dLt;
+  int64_t nnz_l = 0, nnz_u = 0;
+  double lu_ms = 0.0;
+  hipGraphExec_t exec_min = nullptr;
+  BatchKey key_min;
   struct {
     size_t a_rp, a_col, a_val, at_rp, at_col, at_val, tiles, tile_mat, mat_tile0, live_mat,
         live_pref;
     size_t vec[7], parts[4], pairs, g;
+    size_t tri[4][kTriSlots];
+    size_t row_perm, rev, scat_s, svec[4], tickets;
   } o{};
 };
 
@@ -123,6 +140,33 @@ AdamParams bparams(const cond_opts_t& o) {
   return p;
 }
 
+// One update of the sigma_min run (Algorithm 2) for every pair: the solves
+// take all K starts of every matrix at once over the block-diagonal factors.
+void enqueue_batch_min_iteration(cond_batch* b, const BatchArgs& a, const AdamParams& p) {
+  hipStream_t s = b->stream;
+  const int K = kBatchK;
+  int* stop = &a.g->stop_all;
+  int* abort = &a.g->abort_wait;
+  batch_launch_live(a, s);
+  batch_launch_normalise(a, b->grid, s);
+  batch_launch_rearm(a, b->grid, s);
+  // r = A^-1 x: L c = P x, U z = c (z reversed); s = A^-T r: U^T h = z,
+  // L^T wv = h, w = P^T wv
+  launch_trsv_multi(K, b->dL, a.x, reinterpret_cast<const int*>(b->ws + b->o.row_perm), a.c,
+                    nullptr, nullptr, a.tickets + 0, stop, abort, s);
+  const int* rev = reinterpret_cast<const int*>(b->ws + b->o.rev);
+  launch_trsv_multi(K, b->dU, a.c, rev, a.z, nullptr, nullptr, a.tickets + 1, stop, abort, s);
+  batch_launch_sumsq_rev(a, b->grid, s);
+  batch_launch_reduce(a, 1, p, s);
+  launch_trsv_multi(K, b->dUt, a.z, rev, a.h, nullptr, nullptr, a.tickets + 2, stop, abort, s);
+  launch_trsv_multi(K, b->dLt, a.h, rev, a.wv, a.w,
+                    reinterpret_cast<const int*>(b->ws + b->o.scat_s), a.tickets + 3, stop, abort, s);
+  batch_launch_pass1(a, p, b->grid, s);
+  batch_launch_reduce(a, 2, p, s);
+  batch_launch_pass2(a, p, b->grid, s);
+  batch_launch_reduce(a, 0, p, s);
+}
+
 void enqueue_batch_iteration(cond_batch* b, const BatchArgs& a, const AdamParams& p) {
   hipStream_t s = b->stream;
   batch_launch_live(a, s);  // drop the tiles of matrices whose starts have all stopped
@@ -138,6 +182,112 @@ void enqueue_batch_iteration(cond_batch* b, const BatchArgs& a, const AdamParams
 
 }  // namespace
 
+namespace {
+
+// Every matrix's LU and its four solve schedules in parallel threads (one
+// matrix per thread at a time, as the single-matrix plan builds them), then
+// the schedules joined block-diagonally: matrix m's pivot rows at
+// [row0[m], row0[m+1]) for the solves in pivot order (L, U^T), its reversed
+// rows at [N - row0[m+1], N - row0[m]) for the reversed ones (U, L^T).
+int batch_factor(cond_batch* b, std::vector<HostCsr>& as, std::vector<HostCsr>& ats, double tol) {
+  const int32_t count = b->nmat;
+  const int64_t n = b->row0.back();
+  auto t0 = std::chrono::steady_clock::now();
+  struct Part {
+    PanelCsr t[4];  // L, U reversed, U^T, L^T reversed
+    std::vector<int32_t> row_perm, col_perm;
+    int64_t nnz_l = 0, nnz_u = 0;
+  };
+  std::vector<Part> parts(count);
+  std::vector<int> status(count, COND_OK);
+  std::vector<std::string> why(count);
+  std::atomic<int32_t> next(0);
+  unsigned hw = std::thread::hardware_concurrency();
+  const int32_t nthreads = std::max<int32_t>(1, std::min<int32_t>(count, hw ? static_cast<int32_t>(hw) : 4));
+  auto sched = [](const HostCsr& t, const double* diag) {
+    PanelCsr p = split_panels(t);
+    invert_panels(p, diag);
+    return p;
+  };
+  auto worker = [&]() {
+    for (int32_t m; (m = next.fetch_add(1)) < count;) {
+      try {
+        cond_lu f;
+        status[m] = lu_factor(as[m], ats[m], nullptr, tol, f);
+        as[m] = HostCsr();
+        ats[m] = HostCsr();
+        if (status[m]) {
+          why[m] = cond_last_error();
+          continue;
+        }
+        Part& q = parts[m];
+        const int32_t nm = f.n;
+        std::vector<double> udiag_rev(nm);
+        for (int32_t k = 0; k < nm; ++k) udiag_rev[k] = f.u_diag[nm - 1 - k];
+        q.t[0] = sched(f.l_rows, nullptr);
+        q.t[1] = sched(reverse_order(f.u_rows), udiag_rev.data());
+        q.t[2] = sched(f.u_cols, f.u_diag.data());
+        q.t[3] = sched(reverse_order(f.l_cols), nullptr);
+        q.row_perm = std::move(f.row_perm);
+        q.col_perm = std::move(f.col_perm);
+        q.nnz_l = f.l_rows.nnz();
+        q.nnz_u = f.u_rows.nnz() + nm;
+        for (const PanelCsr& t : q.t)
+          for (double w : t.winv)
+            if (!std::isfinite(w)) {
+              status[m] = COND_ENUMERIC;
+              why[m] = "a diagonal block of the LU factors has no finite float64 inverse";
+            }
+      } catch (const std::bad_alloc&) {
+        status[m] = COND_ENOMEM;
+        why[m] = "host memory exhausted";
+      }
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int32_t k = 0; k < nthreads; ++k) pool.emplace_back(worker);
+  for (auto& th : pool) th.join();
+  for (int32_t m = 0; m < count; ++m)
+    if (status[m]) return fail(status[m], "matrix " + std::to_string(m) + ": " + why[m]);
+  b->lu_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  b->row_perm.resize(n);
+  std::vector<int32_t> col_perm(n);
+  for (int32_t m = 0; m < count; ++m) {
+    const int32_t off = static_cast<int32_t>(b->row0[m]);
+    const Part& q = parts[m];
+    for (size_t k = 0; k < q.row_perm.size(); ++k) {
+      b->row_perm[off + k] = off + q.row_perm[k];
+      col_perm[off + k] = off + q.col_perm[k];
+    }
+    b->nnz_l += q.nnz_l;
+    b->nnz_u += q.nnz_u;
+  }
+  PanelCsr* out[4] = {&b->pL, &b->pU, &b->pUt, &b->pLt};
+  for (int f = 0; f < 4; ++f) {
+    const bool reversed = f == 1 || f == 3;
+    std::vector<const PanelCsr*> ps;
+    std::vector<int64_t> offs;
+    for (int32_t k = 0; k < count; ++k) {
+      const int32_t m = reversed ? count - 1 - k : k;
+      ps.push_back(&parts[m].t[f]);
+      offs.push_back(reversed ? n - b->row0[m + 1] : b->row0[m]);
+    }
+    *out[f] = merge_panels(ps, offs);
+    for (int32_t m = 0; m < count; ++m) parts[m].t[f] = PanelCsr();
+  }
+  b->rev.resize(n);
+  b->scat_s.resize(n);
+  b->scat_r.resize(n);
+  for (int64_t k = 0; k < n; ++k) {
+    b->rev[k] = static_cast<int32_t>(n - 1 - k);
+    b->scat_s[k] = b->row_perm[n - 1 - k];
+    b->scat_r[k] = col_perm[n - 1 - k];
+  }
+  return COND_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int cond_batch_create(const cond_csr_t* As, int32_t count, const cond_opts_t* o,
@@ -147,11 +297,19 @@ int cond_batch_create(const cond_csr_t* As, int32_t count, const cond_opts_t* o,
   auto t0 = std::chrono::steady_clock::now();
   std::unique_ptr<cond_batch> b(new (std::nothrow) cond_batch());
   if (!b) return fail(COND_ENOMEM, "allocation failed");
+  if (o->sigma_min_method != COND_MIN_LU && o->sigma_min_method != COND_MIN_NONE)
+    return fail(COND_EINVAL, "a batch runs sigma_min by COND_MIN_LU or not at all");
+  b->want_min = o->sigma_min_method == COND_MIN_LU;
+  std::vector<HostCsr> keep_a, keep_at;  // for the LUs
   try {
     b->nmat = count;
     b->row0.assign(1, 0);
     b->a_rp.assign(1, 0);
     b->at_rp.assign(1, 0);
+    if (b->want_min) {
+      keep_a.resize(count);
+      keep_at.resize(count);
+    }
     for (int32_t m = 0; m < count; ++m) {
       HostCsr a, at;
       int st = canonical_copy(&As[m], a);
@@ -174,6 +332,14 @@ int cond_batch_create(const cond_csr_t* As, int32_t count, const cond_opts_t* o,
       }
       b->row0.push_back(off + a.n);
       b->nnz += a.nnz();
+      if (b->want_min) {
+        keep_a[m] = std::move(a);
+        keep_at[m] = std::move(at);
+      }
+    }
+    if (b->want_min) {
+      int st = batch_factor(b.get(), keep_a, keep_at, o->pivot_tol);
+      if (st) return st;
     }
   } catch (const std::bad_alloc&) {
     return fail(COND_ENOMEM, "host memory exhausted in batch set-up");
@@ -199,6 +365,18 @@ int cond_batch_create(const cond_csr_t* As, int32_t count, const cond_opts_t* o,
   for (int k = 0; k < 4; ++k) b->o.parts[k] = take(off, b->max_tiles * K * 8);
   b->o.pairs = take(off, static_cast<size_t>(count) * K * sizeof(BatchPair));
   b->o.g = take(off, sizeof(BatchGlobal));
+  if (b->want_min) {
+    Layout L;
+    L.off = off;
+    const PanelCsr* tris[4] = {&b->pL, &b->pU, &b->pUt, &b->pLt};
+    for (int f = 0; f < 4; ++f) tri_layout(*tris[f], kBatchK, L, b->o.tri[f]);
+    b->o.row_perm = L.take(n * 4);
+    b->o.rev = L.take(n * 4);
+    b->o.scat_s = L.take(n * 4);
+    for (int k = 0; k < 4; ++k) b->o.svec[k] = L.take(n * K * 8);
+    b->o.tickets = L.take(64);
+    off = L.off;
+  }
   b->need = off;
   b->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   *out = b.release();
@@ -279,6 +457,20 @@ int cond_batch_bind(cond_batch_t* b, void* workspace, size_t bytes, void* stream
   a.parts_xx = reinterpret_cast<double*>(b->ws + b->o.parts[3]);
   a.pairs = reinterpret_cast<BatchPair*>(b->ws + b->o.pairs);
   a.g = reinterpret_cast<BatchGlobal*>(b->ws + b->o.g);
+  a.nrows = b->nrows;
+  if (b->want_min) {
+    const PanelCsr* tris[4] = {&b->pL, &b->pU, &b->pUt, &b->pLt};
+    DevTri* devs[4] = {&b->dL, &b->dU, &b->dUt, &b->dLt};
+    for (int f = 0; f < 4; ++f)
+      if ((st = tri_upload(b->ws, b->o.tri[f], *tris[f], kBatchK, b->stream, *devs[f]))) return st;
+    if ((st = up(b->o.row_perm, b->row_perm.data(), b->row_perm.size() * 4))) return st;
+    if ((st = up(b->o.rev, b->rev.data(), b->rev.size() * 4))) return st;
+    if ((st = up(b->o.scat_s, b->scat_s.data(), b->scat_s.size() * 4))) return st;
+    double** sv[4] = {&a.c, &a.z, &a.h, &a.wv};
+    for (int k = 0; k < 4; ++k) *sv[k] = reinterpret_cast<double*>(b->ws + b->o.svec[k]);
+    a.tickets = reinterpret_cast<unsigned*>(b->ws + b->o.tickets);
+    BCHK(hipMemsetAsync(a.tickets, 0, 64, b->stream));
+  }
   BCHK(hipMemsetAsync(b->ws + b->o.vec[0], 0, b->nrows * kBatchK * 8, b->stream));
   // every pair running: the autotuner's products cover every tile
   BCHK(hipMemsetAsync(b->ws + b->o.pairs, 0, static_cast<size_t>(b->nmat) * kBatchK * sizeof(BatchPair),
@@ -319,6 +511,7 @@ void cond_batch_destroy(cond_batch_t* b) {
   if (!b) return;
   if (b->stream) hipStreamSynchronize(b->stream);
   if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->exec_min) hipGraphExecDestroy(b->exec_min);
   if (b->own && b->ws) hipFree(b->ws);
   if (b->h_pairs) hipHostFree(b->h_pairs);
   for (hipEvent_t e : {b->ev0, b->ev1, b->eva, b->evb})
@@ -327,11 +520,21 @@ void cond_batch_destroy(cond_batch_t* b) {
   delete b;
 }
 
-int cond_batch_run(cond_batch_t* b, const cond_opts_t* o, const double* x0, double* sigma_max,
-                   double* pair_best, int64_t* pair_iters, int32_t* pair_status, double* trace,
-                   double* x_best, double* ms_out) {
+}  // extern "C"
+
+namespace {
+
+// The run of one route for every pair: route 0 sigma_max (M = A), route 1
+// the sigma_min run of Algorithm 2 (M = A^-1). sigma[m] is the route's
+// result for matrix m from its best start: sigma_max, or sigma_min = 1 / the
+// largest ||A^-1 x|| / ||x||.
+int batch_run(cond_batch_t* b, int route, const cond_opts_t* o, const double* x0, double* sigma_out,
+              double* pair_best, int64_t* pair_iters, int32_t* pair_status, double* trace,
+              double* x_best, double* ms_out) {
   if (!b || !o || !x0) return fail(COND_EINVAL, "null argument");
   if (!b->bound) return fail(COND_ESTATE, "batch not bound");
+  if (route == 1 && !b->want_min)
+    return fail(COND_ESTATE, "the batch was created without the sigma_min route (COND_MIN_LU)");
   if (!(o->alpha > 0) || o->max_iter < 1 || o->stop_window < 0 || o->chunk < 0)
     return fail(COND_EINVAL, "invalid Projected Adam options");
   if (!(o->alpha_min >= 0) || o->alpha_min > o->alpha ||
@@ -355,20 +558,27 @@ int cond_batch_run(cond_batch_t* b, const cond_opts_t* o, const double* x0, doub
   k.xbest = a.xbest;
   k.p = p;
   k.chunk = chunk;
-  if (!b->exec || !(b->key == k)) {
-    if (b->exec) {
-      BCHK(hipGraphExecDestroy(b->exec));
-      b->exec = nullptr;
+  hipGraphExec_t& exec = route == 1 ? b->exec_min : b->exec;
+  BatchKey& key = route == 1 ? b->key_min : b->key;
+  if (!exec || !(key == k)) {
+    if (exec) {
+      BCHK(hipGraphExecDestroy(exec));
+      exec = nullptr;
     }
     hipGraph_t graph = nullptr;
     BCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-    for (int it = 0; it < chunk; ++it) enqueue_batch_iteration(b, a, p);
+    for (int it = 0; it < chunk; ++it) {
+      if (route == 1)
+        enqueue_batch_min_iteration(b, a, p);
+      else
+        enqueue_batch_iteration(b, a, p);
+    }
     hipError_t e = hipStreamEndCapture(b->stream, &graph);
     if (e != hipSuccess) return fail(COND_EHIP, std::string("capture: ") + hipGetErrorString(e));
-    e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     hipGraphDestroy(graph);
     if (e != hipSuccess) return fail(COND_EHIP, std::string("instantiate: ") + hipGetErrorString(e));
-    b->key = k;
+    key = k;
   }
   // initial per-pair state
   for (int q = 0; q < npairs; ++q) {
@@ -390,7 +600,7 @@ int cond_batch_run(cond_batch_t* b, const cond_opts_t* o, const double* x0, doub
   hipEvent_t ev[2] = {b->eva, b->evb};
   int cur = 0;
   auto launch_chunk = [&](int s) -> int {
-    BCHK(hipGraphLaunch(b->exec, b->stream));
+    BCHK(hipGraphLaunch(exec, b->stream));
     launched += chunk;
     BCHK(hipMemcpyAsync(slot[s], a.pairs, npairs * sizeof(BatchPair), hipMemcpyDeviceToHost,
                         b->stream));
@@ -427,9 +637,103 @@ int cond_batch_run(cond_batch_t* b, const cond_opts_t* o, const double* x0, doub
       if (s.status && !status) status = s.status;
       if (s.status == COND_OK) best = std::max(best, s.best);
     }
-    if (sigma_max) sigma_max[m] = best;  // every start is a lower bound: keep the largest
+    // every start is a lower bound of ||M||_2: keep the largest
+    if (sigma_out) sigma_out[m] = route == 1 ? 1.0 / best : best;
   }
   if (status) return fail(status, "a (matrix, start) pair failed");
+  return COND_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cond_batch_run(cond_batch_t* b, const cond_opts_t* o, const double* x0, double* sigma_max,
+                   double* pair_best, int64_t* pair_iters, int32_t* pair_status, double* trace,
+                   double* x_best, double* ms) {
+  return batch_run(b, 0, o, x0, sigma_max, pair_best, pair_iters, pair_status, trace, x_best, ms);
+}
+
+int cond_batch_run_min(cond_batch_t* b, const cond_opts_t* o, const double* x0, double* sigma_min,
+                       double* pair_best, int64_t* pair_iters, int32_t* pair_status, double* trace,
+                       double* x_best, double* ms) {
+  return batch_run(b, 1, o, x0, sigma_min, pair_best, pair_iters, pair_status, trace, x_best, ms);
+}
+
+int cond_batch_fill(const cond_batch_t* b, int64_t* nnz_l, int64_t* nnz_u, double* lu_ms) {
+  if (!b) return fail(COND_EINVAL, "null batch");
+  if (!b->want_min) return fail(COND_EINVAL, "the batch has no sigma_min route");
+  if (nnz_l) *nnz_l = b->nnz_l;
+  if (nnz_u) *nnz_u = b->nnz_u;
+  if (lu_ms) *lu_ms = b->lu_ms;
+  return COND_OK;
+}
+
+int cond_batch_solve_replay(const cond_batch_t* b, const double* x, double* r, double* s) {
+  if (!b || !x || !r || !s) return fail(COND_EINVAL, "null argument");
+  if (!b->want_min) return fail(COND_EINVAL, "the batch has no sigma_min route");
+  const int64_t n = b->nrows;
+  try {
+    std::vector<double> xk(n), c(n), z(n), h(n), wv(n);
+    for (int k = 0; k < kBatchK; ++k) {
+      for (int64_t i = 0; i < n; ++i) xk[i] = x[i * kBatchK + k];
+      const bool ok = replay_solve(b->pL, b->row_perm.data(), xk.data(), c.data()) &&
+                      replay_solve(b->pU, b->rev.data(), c.data(), z.data()) &&
+                      replay_solve(b->pUt, b->rev.data(), z.data(), h.data()) &&
+                      replay_solve(b->pLt, b->rev.data(), h.data(), wv.data());
+      if (!ok) return fail(COND_ESTATE, "solve schedule reads a value before its ticket is solved");
+      for (int64_t i = 0; i < n; ++i) r[static_cast<int64_t>(b->scat_r[i]) * kBatchK + k] = z[i];
+      for (int64_t i = 0; i < n; ++i) s[static_cast<int64_t>(b->scat_s[i]) * kBatchK + k] = wv[i];
+    }
+  } catch (const std::bad_alloc&) {
+    return fail(COND_ENOMEM, "host memory exhausted");
+  }
+  return COND_OK;
+}
+
+int cond_estimate_batched(const cond_csr_t* As, int32_t count, const cond_opts_t* o,
+                          const double* x0_max, const double* x0_min, void* stream,
+                          cond_result_t* outs) {
+  if (!As || count <= 0 || !o || !x0_max || !outs) return fail(COND_EINVAL, "null argument");
+  if (!x0_min) x0_min = x0_max;
+  cond_opts_t oo = *o;
+  oo.sigma_min_method = COND_MIN_LU;
+  cond_batch_t* b = nullptr;
+  int st = cond_batch_create(As, count, &oo, &b);
+  if (st) return st;
+  std::unique_ptr<cond_batch, void (*)(cond_batch*)> guard(b, cond_batch_destroy);
+  if ((st = cond_batch_bind(b, nullptr, 0, stream, 0, 0))) return st;
+  const size_t npairs = static_cast<size_t>(count) * kBatchK;
+  std::vector<double> smax(count), smin(count), pbest(npairs);
+  std::vector<int64_t> it_max(npairs), it_min(npairs);
+  std::vector<int32_t> pst_max(npairs), pst_min(npairs);
+  double ms_max = 0.0, ms_min = 0.0;
+  const int st_max = batch_run(b, 0, &oo, x0_max, smax.data(), pbest.data(), it_max.data(),
+                               pst_max.data(), nullptr, nullptr, &ms_max);
+  if (st_max && st_max != COND_ENUMERIC && st_max != COND_ETIMEOUT) return st_max;
+  const int st_min = batch_run(b, 1, &oo, x0_min, smin.data(), pbest.data(), it_min.data(),
+                               pst_min.data(), nullptr, nullptr, &ms_min);
+  if (st_min && st_min != COND_ENUMERIC && st_min != COND_ETIMEOUT) return st_min;
+  for (int32_t m = 0; m < count; ++m) {
+    cond_result_t& r = outs[m];
+    std::memset(&r, 0, sizeof(r));
+    r.sigma_max = smax[m];
+    r.sigma_min = smin[m];
+    r.kappa = smax[m] / smin[m];
+    for (int k = 0; k < kBatchK; ++k) {
+      const size_t q = static_cast<size_t>(m) * kBatchK + k;
+      r.iters_max = std::max<int64_t>(r.iters_max, it_max[q]);
+      r.iters_min = std::max<int64_t>(r.iters_min, it_min[q]);
+      if (pst_max[q] && !r.status_max) r.status_max = pst_max[q];
+      if (pst_min[q] && !r.status_min) r.status_min = pst_min[q];
+    }
+    if (r.kappa >= 1.0 / 2.220446049250313e-16) r.flags |= COND_F_NUMSING;
+    r.ms_max = ms_max;
+    r.ms_min = ms_min;
+    r.setup_ms = b->setup_ms;
+  }
+  if (st_max) return fail(st_max, "sigma_max run of a (matrix, start) pair failed");
+  if (st_min) return fail(st_min, "sigma_min run of a (matrix, start) pair failed");
   return COND_OK;
 }
 

@@ -29,7 +29,10 @@ struct BatchPair {
 struct BatchGlobal {
   long long t_done;
   double b1t, b2t;
-  int nlive;  // tiles of the matrices that still have a running start
+  int nlive;       // tiles of the matrices that still have a running start
+  int stop_all;    // 1 once every pair has stopped (the solves then skip)
+  int abort_wait;  // 1 when a triangular-solve wait timed out
+  int pad_;
 };
 
 struct BatchArgs {
@@ -52,6 +55,13 @@ struct BatchArgs {
   BatchPair* pairs = nullptr;
   BatchGlobal* g = nullptr;
   double* trace = nullptr;  // [pair][max_iter] or nullptr
+  // sigma_min route (Algorithm 2 over the block-diagonal factors): the
+  // solves' vectors (K interleaved sides), re-armed every update, and their
+  // ticket counters; z is in reversed pivot order, so tile t's rows
+  // [r0, r1) sit at [nrows - r1, nrows - r0) of z
+  long long nrows = 0;
+  double *c = nullptr, *z = nullptr, *h = nullptr, *wv = nullptr;
+  unsigned* tickets = nullptr;
 };
 
 void batch_launch_init(const BatchArgs& a, const double* x0, int grid, hipStream_t s);
@@ -61,5 +71,9 @@ void batch_launch_normalise(const BatchArgs& a, int grid, hipStream_t s);
 void batch_launch_spmm(const BatchArgs& a, int transpose, int grid, hipStream_t s);
 void batch_launch_pass1(const BatchArgs& a, const AdamParams& p, int grid, hipStream_t s);
 void batch_launch_pass2(const BatchArgs& a, const AdamParams& p, int grid, hipStream_t s);
+// sigma_min route: re-arm c, z, h, wv and the tickets; squared norms of z per
+// (tile, start) from the mirrored tiles
+void batch_launch_rearm(const BatchArgs& a, int grid, hipStream_t s);
+void batch_launch_sumsq_rev(const BatchArgs& a, int grid, hipStream_t s);
 
 }  // namespace condest

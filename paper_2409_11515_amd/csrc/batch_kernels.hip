@@ -112,6 +112,8 @@ __global__ __launch_bounds__(kB) void b_init_k(BatchArgs a, const double* __rest
     a.g->t_done = 0;
     a.g->b1t = 1.0;
     a.g->b2t = 1.0;
+    a.g->stop_all = 0;
+    a.g->abort_wait = 0;
   }
 }
 
@@ -148,6 +150,7 @@ __global__ __launch_bounds__(kB) void b_live_k(BatchArgs a) {
   if (threadIdx.x == 0) {
     a.live_pref[j_sh] = u_sh;
     a.g->nlive = u_sh;
+    a.g->stop_all = u_sh == 0 ? 1 : 0;
   }
 }
 
@@ -199,6 +202,12 @@ __global__ __launch_bounds__(kB) void b_reduce_k(BatchArgs a, int mode, AdamPara
   q.nx2 = nx2;
   q.ny2 = ny2;
   q.improved = 0;
+  if (a.g->abort_wait) {
+    q.stopped = 1;
+    q.status = COND_ETIMEOUT;
+    q.iters = t - 1;
+    return;
+  }
   if (!(nx2 > 0.0) || !(ny2 > 0.0) || !isfinite(nx2) || !isfinite(ny2)) {
     q.stopped = 1;
     q.status = COND_ENUMERIC;
@@ -374,6 +383,46 @@ __global__ __launch_bounds__(kB) void b_pass2_k(BatchArgs a, AdamParams p) {
   }
 }
 
+// ------------------------------------------------------- sigma_min route
+// Re-arm the solves' vectors with the not-yet-solved pattern and reset their
+// ticket counters before the four solves of an update.
+__global__ __launch_bounds__(kB) void b_rearm_k(BatchArgs a) {
+  if (a.g->stop_all) return;
+  const long long total = a.nrows * kBatchK;
+  unsigned long long* v[4] = {reinterpret_cast<unsigned long long*>(a.c),
+                              reinterpret_cast<unsigned long long*>(a.z),
+                              reinterpret_cast<unsigned long long*>(a.h),
+                              reinterpret_cast<unsigned long long*>(a.wv)};
+  for (long long i = blockIdx.x * static_cast<long long>(kB) + threadIdx.x; i < total;
+       i += static_cast<long long>(gridDim.x) * kB) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k][i] = kPending;
+  }
+  if (blockIdx.x == 0 && threadIdx.x < 4) a.tickets[threadIdx.x] = 0u;
+}
+
+// ||A^-1 x||^2 per (tile, start): z is the U solve's output in reversed pivot
+// order, and the merged factors keep each matrix's pivot rows together, so
+// tile t's mirrored rows belong to the same matrix.
+template <int K>
+__global__ __launch_bounds__(kB) void b_sumsq_rev_k(BatchArgs a) {
+  LiveTiles lt;
+  lt.begin(a);
+  const int k = threadIdx.x % K;
+  for (long long t = lt.tile(a); t >= 0; ++lt.u, t = lt.tile(a)) {
+    const int mat = a.tile_mat[t];
+    const BatchPair& q = a.pairs[static_cast<long long>(mat) * K + k];
+    const long long r0 = a.nrows - a.tiles[t + 1], r1 = a.nrows - a.tiles[t];
+    double acc = 0.0;
+    if (!q.stopped)
+      for (long long e = r0 * K + threadIdx.x; e < r1 * K; e += kB) {
+        const double zi = a.z[e];
+        acc += zi * zi;
+      }
+    tile_partials<K>(acc, static_cast<int>(t), a.parts_y);
+  }
+}
+
 }  // namespace
 
 void batch_launch_init(const BatchArgs& a, const double* x0, int grid, hipStream_t s) {
@@ -399,6 +448,13 @@ void batch_launch_pass1(const BatchArgs& a, const AdamParams& p, int grid, hipSt
 }
 void batch_launch_pass2(const BatchArgs& a, const AdamParams& p, int grid, hipStream_t s) {
   b_pass2_k<kBatchK><<<grid, kB, 0, s>>>(a, p);
+}
+
+void batch_launch_rearm(const BatchArgs& a, int grid, hipStream_t s) {
+  b_rearm_k<<<grid, kB, 0, s>>>(a);
+}
+void batch_launch_sumsq_rev(const BatchArgs& a, int grid, hipStream_t s) {
+  b_sumsq_rev_k<kBatchK><<<grid, kB, 0, s>>>(a);
 }
 
 }  // namespace condest

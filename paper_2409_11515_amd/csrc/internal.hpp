@@ -31,6 +31,14 @@ void nested_dissection(const HostCsr& a, const HostCsr& at, std::vector<int32_t>
 
 }  // namespace condest
 
+struct cond_lu;
+namespace condest {
+// P A Q = L U with threshold partial pivoting (col_perm_in: Q, or null for
+// nested dissection). Thread-safe: no shared state.
+int lu_factor(const HostCsr& a, const HostCsr& at, const int32_t* col_perm_in, double tol,
+              cond_lu& lu);
+}  // namespace condest
+
 // LU factors, P A Q = L U, held in both orientations for the four solves.
 struct cond_lu {
   int32_t n = 0;

@@ -633,6 +633,201 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_k(TrsvArgs t, const double* _
   }
 }
 
+// ------------------------------------------------- trsv, several sides
+// The same solve for K interleaved right-hand sides (row i, side k at index
+// i * K + k), on the same tasks, records, panel inverses and waits as trsv_k,
+// with one 64-row sub-panel per panel. A row's 16 lanes are EL = 16 / K
+// entry lanes times K side lanes: the K lanes of an entry read its column and
+// value once between them (one address) and K contiguous solved values, so
+// one pass over the factor, and one wait per dependency, serve all K sides.
+// Slice partials are K per row. The run is skipped when *stop is non-zero
+// (every start of the run has stopped); a wait that times out sets *abort.
+static_assert(kPanelRows == kPanel, "the several-sides solve takes one sub-panel per panel");
+
+__device__ __noinline__ double wait_pending_flag(const double* p, int* abort) {
+  const unsigned long long* q = reinterpret_cast<const unsigned long long*>(p);
+  unsigned slept = 0, backoff = 1, polls = 0;
+  unsigned long long bits;
+  for (;;) {
+    bits = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (bits != kPending) break;
+    if ((++polls & 63u) == 0u) {
+      if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        return __longlong_as_double(0x7FF8000000000000ll);
+      if (slept >= kSleepLimit) {
+        __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return __longlong_as_double(0x7FF8000000000000ll);
+      }
+    }
+    for (unsigned k = 0; k < backoff; ++k) __builtin_amdgcn_s_sleep(1);
+    slept += backoff;
+    if (backoff < kMaxBackoff) backoff <<= 1;
+  }
+  return __longlong_as_double(static_cast<long long>(bits));
+}
+
+// Off-panel sum of one row for side kk over entries [p0, p1): entry lane es
+// takes entries es, es + EL, ...; every lane of the row's group that holds
+// side kk gets the sum.
+template <int K>
+__device__ __forceinline__ double row_sum_multi(long long p0, long long p1, int es, int kk,
+                                                const int* __restrict__ col,
+                                                const double* __restrict__ val, const double* out,
+                                                int* abort) {
+  constexpr int EL = kLanesPerRow / K;
+  double acc = 0.0;
+  for (long long base = p0; base < p1; base += EL * kUnroll) {
+    int j[kUnroll];
+    double a[kUnroll];
+    unsigned long long bits[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const long long p = base + u * EL + es;
+      const bool act = p < p1;
+      j[u] = act ? col[p] : -1;
+      a[u] = act ? val[p] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+      bits[u] = j[u] >= 0 ? __hip_atomic_load(reinterpret_cast<const unsigned long long*>(
+                                                  out + static_cast<long long>(j[u]) * K + kk),
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)
+                          : 0ull;
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      if (j[u] >= 0) {
+        const double xj = bits[u] != kPending
+                              ? __longlong_as_double(static_cast<long long>(bits[u]))
+                              : wait_pending_flag(out + static_cast<long long>(j[u]) * K + kk, abort);
+        acc += a[u] * xj;
+      }
+    }
+  }
+#pragma unroll
+  for (int off = kLanesPerRow / 2; off >= K; off >>= 1) acc += __shfl_xor(acc, off, kLanesPerRow);
+  return acc;
+}
+
+template <int K>
+__global__ __launch_bounds__(kTrsvBlock) void trsv_multi_k(TrsvArgs t, const double* __restrict__ rhs,
+                                                           const int* __restrict__ rhs_perm,
+                                                           double* out, double* __restrict__ scatter,
+                                                           const int* __restrict__ scatter_perm,
+                                                           unsigned* ticket, const int* stop,
+                                                           int* abort) {
+  constexpr int EL = kLanesPerRow / K;
+  static_assert(EL >= 1 && EL * K == kLanesPerRow, "K divides the 16 lanes of a row");
+  __shared__ double w_sh[kPanel * kLdW];  // the sub-panel triangle's inverse, row-major
+  __shared__ double t_sh[kPanel * K];     // off-panel sums, row r side k at r * K + k
+  __shared__ double b_sh[kPanel * K];     // right-hand sides
+  __shared__ unsigned task_sh;
+  __shared__ int quit_sh;
+  if (threadIdx.x == 0)
+    quit_sh = (stop && *stop) ||
+              __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  if (quit_sh) return;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int sub = lane & (kLanesPerRow - 1);
+  const int es = sub / K, kk = sub % K;
+  const int g = wave * (64 / kLanesPerRow) + lane / kLanesPerRow;  // this group's row, 0..63
+  for (;;) {
+    if (threadIdx.x == 0) task_sh = atomicAdd(ticket, 1u);
+    __syncthreads();
+    const unsigned T = task_sh;
+    if (T >= static_cast<unsigned>(t.ntasks)) break;
+    const int4 ra = reinterpret_cast<const int4*>(t.task_rec)[2 * static_cast<long long>(T)];
+    const int4 rb = reinterpret_cast<const int4*>(t.task_rec)[2 * static_cast<long long>(T) + 1];
+    const int P = ra.x;
+    const int kind = ra.y;  // -1 whole panel, 0..S-1 slice, S finish
+    const long long lo = ra.z;
+    const int cnt = ra.w;
+    const int S = rb.x;
+    double* slots = t.partials + static_cast<long long>(rb.y) * kPanelRows * K;
+    const bool row = g < cnt;
+    long long q0 = row ? t.off_rp[lo + g] : 0, q1 = row ? t.off_rp[lo + g + 1] : 0;
+    if (kind >= 0 && kind < S) {
+      // slice task: partial sums over one slice of the row's older entries
+      if (row) q1 = t.off_split[lo + g];
+      const long long len = q1 - q0;
+      const long long s1 = q0 + len * (kind + 1) / S;
+      const long long s0 = q0 + len * kind / S;
+      const double part = row_sum_multi<K>(s0, s1, es, kk, t.off_col, t.off_val, out, abort);
+      if (row && es == 0)
+        publish(slots + (static_cast<long long>(kind) * kPanelRows + g) * K + kk, part);
+      __syncthreads();  // task_sh is reused
+      continue;
+    }
+    // everything that needs no solved value: right-hand sides and the inverse
+    if (row && es == 0)
+      b_sh[g * K + kk] = rhs_perm ? rhs[static_cast<long long>(rhs_perm[lo + g]) * K + kk]
+                                  : rhs[(lo + g) * K + kk];
+    {
+      const double* w = t.winv + t.woff[P];
+#pragma unroll
+      for (int u = 0; u < kLocalPerLane; ++u) {
+        const int c = sub + u * kLanesPerRow;
+        w_sh[g * kLdW + c] = (row && c <= g) ? w[g * (g + 1) / 2 + c] : 0.0;
+      }
+    }
+    double sum;
+    if (kind < 0) {
+      sum = row_sum_multi<K>(q0, q1, es, kk, t.off_col, t.off_val, out, abort);
+    } else {
+      // finish: entry lane es adds slices es, es + EL, ... of side kk in that
+      // fixed order (8 loads in flight), re-arming each slot it read
+      double acc = 0.0;
+      if (row) {
+        unsigned long long* sp = reinterpret_cast<unsigned long long*>(slots);
+        for (int k0 = es; k0 < S; k0 += EL * 8) {
+          unsigned long long bits[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int k = k0 + u * EL;
+            bits[u] = k < S ? __hip_atomic_load(sp + (static_cast<long long>(k) * kPanelRows + g) * K + kk,
+                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                            : 0ull;
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int k = k0 + u * EL;
+            if (k < S) {
+              const long long at = (static_cast<long long>(k) * kPanelRows + g) * K + kk;
+              acc += bits[u] != kPending ? __longlong_as_double(static_cast<long long>(bits[u]))
+                                         : wait_pending_flag(slots + at, abort);
+              __hip_atomic_store(sp + at, kPending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int off = kLanesPerRow / 2; off >= K; off >>= 1) acc += __shfl_xor(acc, off, kLanesPerRow);
+      const double recent = row ? row_sum_multi<K>(t.off_split[lo + g], t.off_rp[lo + g + 1], es,
+                                                   kk, t.off_col, t.off_val, out, abort)
+                                : 0.0;
+      sum = acc + recent;
+    }
+    if (row && es == 0) t_sh[g * K + kk] = sum;
+    __syncthreads();
+    // x = W (b - sums) for side kk: entry lane es takes columns es, es + EL, ...
+    double acc = 0.0;
+#pragma unroll 8
+    for (int u = 0; u < kPanel / EL; ++u) {
+      const int c = es + u * EL;
+      if (c <= g && c < cnt) acc += w_sh[g * kLdW + c] * (b_sh[c * K + kk] - t_sh[c * K + kk]);
+    }
+#pragma unroll
+    for (int off = kLanesPerRow / 2; off >= K; off >>= 1) acc += __shfl_xor(acc, off, kLanesPerRow);
+    if (row && es == 0) {
+      const long long i = lo + g;
+      publish(out + i * K + kk, acc);
+      if (scatter) scatter[static_cast<long long>(scatter_perm[i]) * K + kk] = acc;
+    }
+    __syncthreads();  // LDS and task_sh are reused
+  }
+}
+
 // ---------------------------------------------------------- adam pass 1
 // Evaluation of the previous iterate, best-iterate tracking, stop rule, and
 // the moment update with bias correction (Algorithm 1), partials of x.dx.
@@ -818,6 +1013,26 @@ __global__ __launch_bounds__(kBlock) void reduce3_k(const double* __restrict__ p
   }
 }
 
+// ---------------------------------------------------------------- triad
+// a = b + s c over n doubles: the streaming reference every HBM-bound kernel
+// is quoted against (24 bytes per element). Each thread moves two elements
+// per step as 16-byte loads and stores; consecutive threads take consecutive
+// 16-byte chunks.
+__global__ __launch_bounds__(kBlock) void triad_k(long long n, double* __restrict__ a,
+                                                  const double* __restrict__ b,
+                                                  const double* __restrict__ c, double s) {
+  const long long n2 = n / 2;
+  const double2* b2 = reinterpret_cast<const double2*>(b);
+  const double2* c2 = reinterpret_cast<const double2*>(c);
+  double2* a2 = reinterpret_cast<double2*>(a);
+  const long long stride = static_cast<long long>(gridDim.x) * kBlock;
+  for (long long i = blockIdx.x * static_cast<long long>(kBlock) + threadIdx.x; i < n2; i += stride) {
+    const double2 x = b2[i], y = c2[i];
+    a2[i] = make_double2(x.x + s * y.x, x.y + s * y.y);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && (n & 1)) a[n - 1] = b[n - 1] + s * c[n - 1];
+}
+
 __global__ void fill_k(long long n, unsigned long long* p, unsigned long long bits) {
   for (long long i = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<long long>(gridDim.x) * blockDim.x)
@@ -911,6 +1126,28 @@ void launch_trsv(const DevTri& t, const double* rhs, const int* rhs_perm, double
   trsv_k<<<g, kTrsvBlock, 0, s>>>(t, rhs, rhs_perm, out, scatter, scatter_perm, ticket, st);
 }
 
+void launch_trsv_multi(int K, const DevTri& t, const double* rhs, const int* rhs_perm, double* out,
+                       double* scatter, const int* scatter_perm, unsigned* ticket, const int* stop,
+                       int* abort, hipStream_t s) {
+  long long blocks = t.ntasks < 512 ? t.ntasks : 512;
+  if (blocks < 1) blocks = 1;
+  const int g = static_cast<int>(blocks);
+  switch (K) {
+    case 2:
+      trsv_multi_k<2><<<g, kTrsvBlock, 0, s>>>(t, rhs, rhs_perm, out, scatter, scatter_perm, ticket,
+                                               stop, abort);
+      break;
+    case 4:
+      trsv_multi_k<4><<<g, kTrsvBlock, 0, s>>>(t, rhs, rhs_perm, out, scatter, scatter_perm, ticket,
+                                               stop, abort);
+      break;
+    default:
+      trsv_multi_k<8><<<g, kTrsvBlock, 0, s>>>(t, rhs, rhs_perm, out, scatter, scatter_perm, ticket,
+                                               stop, abort);
+      break;
+  }
+}
+
 void launch_pass1(int n, const double* x, const double* w, double* m, double* v, double* d,
                   double* xbest, const double* parts_x, const double* parts_y, int grid,
                   double* parts_xd, RunState* st, double* trace, const AdamParams& p,
@@ -934,6 +1171,11 @@ void launch_residual(int n, const void* rowptr, int idx64, const int* col, const
     residual_k<int><<<grid, kBlock, 0, s>>>(n, static_cast<const int*>(rowptr), col, val, x, b,
                                             parts);
   reduce3_k<<<1, kBlock, 0, s>>>(parts, grid, sums);
+}
+
+void launch_triad(long long n, double* a, const double* b, const double* c, double scale, int grid,
+                  hipStream_t s) {
+  triad_k<<<grid, kBlock, 0, s>>>(n, a, b, c, scale);
 }
 
 void launch_fill(int n, double* p, unsigned long long bits, hipStream_t s) {

@@ -140,6 +140,13 @@ void launch_sumsq(int n, const double* z, double* parts, int grid, const RunStat
 void launch_trsv(const DevTri& t, const double* rhs, const int* rhs_perm, double* out,
                  double* scatter, const int* scatter_perm, unsigned* ticket, RunState* st,
                  hipStream_t s);
+// The same solve for K in {2, 4, 8} interleaved right-hand sides (row i,
+// side k at i * K + k; rhs, out and scatter in that layout, the permutations
+// over rows). t.partials must hold K values per slot row. Skipped when *stop
+// (may be null) is non-zero; a timed-out wait sets *abort.
+void launch_trsv_multi(int K, const DevTri& t, const double* rhs, const int* rhs_perm, double* out,
+                       double* scatter, const int* scatter_perm, unsigned* ticket, const int* stop,
+                       int* abort, hipStream_t s);
 void launch_pass1(int n, const double* x, const double* w, double* m, double* v, double* d,
                   double* xbest, const double* parts_x, const double* parts_y, int grid,
                   double* parts_xd, RunState* st, double* trace, const AdamParams& p,
@@ -151,6 +158,9 @@ void launch_pass2(int n, double* x, const double* d, const double* parts_xd, int
 void launch_residual(int n, const void* rowptr, int idx64, const int* col, const double* val,
                      const double* x, const double* b, double* parts, double* sums, int grid,
                      hipStream_t s);
+// a = b + scale c (n doubles; a, b, c 16-byte aligned): the streaming ceiling.
+void launch_triad(long long n, double* a, const double* b, const double* c, double scale, int grid,
+                  hipStream_t s);
 void launch_fill(int n, double* p, unsigned long long bits, hipStream_t s);
 void launch_zero_u32(unsigned* p, int count, hipStream_t s);
 

@@ -1,0 +1,452 @@
+// Panel schedules of the sparse triangular solves: the planner (panel cuts
+// chosen by a measured cost model, dependency levels, slices of heavy panels,
+// task records), the inverses of the sub-panel triangles, and the device
+// layout and upload of one solve.
+
+#include "panels.hpp"
+
+#include <algorithm>
+#include <string>
+
+namespace condest {
+
+namespace {
+
+// A panel whose rows hold more off-panel entries than this is cut into
+// slices (at most kMaxSlices) that separate blocks sum in parallel. The
+// slices take a row's entries on rows more than kRecentRows before the
+// panel; the finish step takes the newer ones, so a chain of panels (a dense
+// separator block) waits for its predecessor in one step, not two.
+constexpr int64_t kSliceEntries = 4096;
+constexpr int32_t kRecentRows = 64;
+constexpr int32_t kMaxSlices = kMaxSlicesDev;
+
+// Panel boundaries: a panel closes when it holds kPanelRows rows, or -- once
+// it holds at least kMinPanelRows -- before a row that needs nothing inside
+// it. Such a row usually opens an independent subtree of the elimination
+// order (a new leaf of the nested dissection); cutting there keeps independent
+// subtrees in different panels, so they are solved in parallel instead of as
+// a chain. With `merge`, such a row instead joins the open panel when it reads
+// panels exactly as deep as the open panel does: it would run in the same
+// dependency level anyway, and one task fewer is cheaper than the parallelism
+// (the leaves of a nested dissection are thousands of panels of a few rows).
+// A panel also closes at a 64-row boundary when the next row reads a panel
+// that is deeper in the dependency order than anything the open panel reads:
+// the panel's later sub-panels then never hold back its first one. What
+// remains inside a panel are chains (a dense separator block, mostly), which
+// one block solves sub-panel after sub-panel without waiting on others.
+constexpr int32_t kMinPanelRows = 4;
+
+std::vector<int32_t> cut_panels(const HostCsr& t, bool merge) {
+  std::vector<int32_t> ps{0};
+  std::vector<int32_t> pid(t.n, 0), plevel;  // panel of each closed row, level of each panel
+  int32_t s = 0;
+  // 1 + the deepest closed panel that row e reads (columns left of the open panel)
+  auto ext_level = [&](int32_t e) {
+    int32_t lv = 0;
+    for (int64_t p = t.rowptr[e]; p < t.rowptr[e + 1]; ++p)
+      if (t.col[p] < s) lv = std::max(lv, plevel[pid[t.col[p]]] + 1);
+    return lv;
+  };
+  int32_t cur = t.n ? ext_level(0) : 0;
+  for (int32_t e = 1; e < t.n; ++e) {
+    bool needs_panel = false;
+    for (int64_t p = t.rowptr[e]; p < t.rowptr[e + 1] && !needs_panel; ++p)
+      needs_panel = t.col[p] >= s;
+    const int32_t rows = e - s;
+    const int32_t lv = ext_level(e);
+    if (rows >= kPanelRows || (!needs_panel && rows >= kMinPanelRows && (!merge || lv != cur)) ||
+        (rows % kPanel == 0 && lv > cur)) {
+      const int32_t q = static_cast<int32_t>(plevel.size());
+      for (int32_t i = s; i < e; ++i) pid[i] = q;
+      plevel.push_back(cur);
+      ps.push_back(e);
+      s = e;
+      cur = ext_level(e);
+    } else {
+      cur = std::max(cur, lv);
+    }
+  }
+  ps.push_back(t.n);
+  return ps;
+}
+
+// Level of each panel: one more than the deepest panel it reads from.
+std::vector<int32_t> panel_levels(const HostCsr& t, const std::vector<int32_t>& pstart,
+                                  std::vector<int32_t>& pid) {
+  const int32_t np = static_cast<int32_t>(pstart.size()) - 1;
+  pid.assign(t.n, 0);
+  for (int32_t p = 0; p < np; ++p)
+    for (int32_t i = pstart[p]; i < pstart[p + 1]; ++i) pid[i] = p;
+  std::vector<int32_t> level(np, 0);
+  for (int32_t i = 0; i < t.n; ++i)
+    for (int64_t p = t.rowptr[i]; p < t.rowptr[i + 1]; ++p) {
+      const int32_t q = pid[t.col[p]];
+      if (q != pid[i]) level[pid[i]] = std::max(level[pid[i]], level[q] + 1);
+    }
+  return level;
+}
+
+int32_t slices_of(int64_t work) {
+  return static_cast<int32_t>(std::min<int64_t>(kMaxSlices, (work + kSliceEntries - 1) / kSliceEntries));
+}
+
+// Estimated solve time of a cut, in microseconds: every dependency level
+// costs a wait-and-publish round trip, every task a fixed hand-out and
+// set-up cost spread over the resident blocks. Both constants are a
+// least-squares fit to eight measured solves on MI355X (256 resident
+// blocks): the four factor orientations of a 242k-row hydro-mechanical
+// system, each cut both ways.
+constexpr double kLevelUs = 2.5;
+constexpr double kTaskUs = 0.0152;
+
+double cut_cost(const HostCsr& t, const std::vector<int32_t>& pstart) {
+  std::vector<int32_t> pid;
+  const std::vector<int32_t> level = panel_levels(t, pstart, pid);
+  const int32_t np = static_cast<int32_t>(pstart.size()) - 1;
+  int64_t tasks = 0;
+  for (int32_t p = 0; p < np; ++p) {
+    int64_t work = 0;  // entries left of the panel
+    for (int32_t i = pstart[p]; i < pstart[p + 1]; ++i)
+      for (int64_t e = t.rowptr[i]; e < t.rowptr[i + 1]; ++e) work += t.col[e] < pstart[p];
+    const int32_t S = slices_of(work);
+    tasks += S > 1 ? S + 1 : 1;
+  }
+  const int32_t levels = np ? 1 + *std::max_element(level.begin(), level.end()) : 0;
+  return kLevelUs * levels + kTaskUs * static_cast<double>(tasks);
+}
+
+}  // namespace
+
+PanelCsr split_panels(const HostCsr& t) {
+  PanelCsr s;
+  s.n = t.n;
+  // the cheaper of the two cuts by the cost model (merging the leaves pays
+  // where they are many small panels, splitting where they are few)
+  std::vector<int32_t> split = cut_panels(t, false), merged = cut_panels(t, true);
+  s.pstart = cut_cost(t, merged) < cut_cost(t, split) ? std::move(merged) : std::move(split);
+  const int32_t np = static_cast<int32_t>(s.pstart.size()) - 1;
+  std::vector<int32_t> pid;
+  const std::vector<int32_t> level = panel_levels(t, s.pstart, pid);
+  std::vector<int32_t> order(np);
+  for (int32_t p = 0; p < np; ++p) order[p] = p;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t a, int32_t b) { return level[a] < level[b]; });
+  s.levels = np ? 1 + *std::max_element(level.begin(), level.end()) : 0;
+  s.off_rp.assign(t.n + 1, 0);
+  s.in_rp.assign(t.n + 1, 0);
+  s.in_split.assign(t.n, 0);
+  s.off_split.assign(t.n, 0);
+  for (int32_t i = 0; i < t.n; ++i) {
+    const int32_t lo = s.pstart[pid[i]];
+    const int32_t sub0 = lo + (i - lo) / kPanel * kPanel;  // first row of i's sub-panel
+    for (int64_t p = t.rowptr[i]; p < t.rowptr[i + 1]; ++p) {
+      const int32_t j = t.col[p];
+      if (j < lo) {
+        s.off_col.push_back(j);
+        s.off_val.push_back(t.val[p]);
+      } else if (j < sub0) {
+        s.in_col.push_back(j - lo);
+        s.in_val.push_back(t.val[p]);
+      }
+    }
+    s.in_split[i] = static_cast<int64_t>(s.in_col.size());
+    for (int64_t p = t.rowptr[i]; p < t.rowptr[i + 1]; ++p) {
+      const int32_t j = t.col[p];
+      if (j >= sub0) {
+        s.in_col.push_back(j - lo);
+        s.in_val.push_back(t.val[p]);
+      }
+    }
+    s.off_rp[i + 1] = static_cast<int64_t>(s.off_col.size());
+    s.in_rp[i + 1] = static_cast<int64_t>(s.in_col.size());
+  }
+  // tasks: whole panels, or slices followed by their finish step
+  s.panel_split.assign(np, 1);
+  s.panel_slot.assign(np, 0);
+  for (int32_t p : order) {
+    const int64_t work = s.off_rp[s.pstart[p + 1]] - s.off_rp[s.pstart[p]];
+    const int32_t S = slices_of(work);
+    if (S <= 1) {
+      s.task_panel.push_back(p);
+      s.task_kind.push_back(-1);
+      s.task_level.push_back(level[p]);
+      continue;
+    }
+    s.panel_split[p] = S;
+    s.panel_slot[p] = s.nslots;
+    s.nslots += S;
+    const int32_t c0 = s.pstart[p] - kRecentRows;  // older entries: columns below c0
+    for (int32_t i = s.pstart[p]; i < s.pstart[p + 1]; ++i) {
+      int64_t e = s.off_rp[i];
+      while (e < s.off_rp[i + 1] && s.off_col[e] < c0) ++e;  // columns are sorted in a row
+      s.off_split[i] = e;
+    }
+    for (int32_t k = 0; k <= S; ++k) {
+      s.task_panel.push_back(p);
+      s.task_kind.push_back(k);
+      s.task_level.push_back(level[p]);
+    }
+  }
+  s.task_rec.reserve(8 * s.task_panel.size());
+  for (size_t k = 0; k < s.task_panel.size(); ++k) {
+    const int32_t p = s.task_panel[k];
+    const int32_t rec[8] = {p, s.task_kind[k], s.pstart[p], s.pstart[p + 1] - s.pstart[p],
+                            s.panel_split[p], s.panel_slot[p], 0, 0};
+    s.task_rec.insert(s.task_rec.end(), rec, rec + 8);
+  }
+  return s;
+}
+
+PanelCsr merge_panels(const std::vector<const PanelCsr*>& parts, const std::vector<int64_t>& offsets) {
+  PanelCsr m;
+  m.off_rp.push_back(0);
+  m.in_rp.push_back(0);
+  m.pstart.push_back(0);
+  std::vector<int32_t> panel0(parts.size());  // first merged panel of each part
+  for (size_t k = 0; k < parts.size(); ++k) {
+    const PanelCsr& s = *parts[k];
+    const int32_t r0 = static_cast<int32_t>(offsets[k]);
+    const int64_t e_off = static_cast<int64_t>(m.off_col.size());
+    const int64_t e_in = static_cast<int64_t>(m.in_col.size());
+    const int32_t slot0 = m.nslots;
+    const int64_t w0 = static_cast<int64_t>(m.winv.size());
+    panel0[k] = static_cast<int32_t>(m.pstart.size()) - 1;
+    for (int32_t i = 0; i < s.n; ++i) {
+      m.off_rp.push_back(e_off + s.off_rp[i + 1]);
+      m.in_rp.push_back(e_in + s.in_rp[i + 1]);
+      m.off_split.push_back(e_off + s.off_split[i]);
+      m.in_split.push_back(e_in + s.in_split[i]);
+    }
+    for (int32_t c : s.off_col) m.off_col.push_back(c + r0);
+    m.off_val.insert(m.off_val.end(), s.off_val.begin(), s.off_val.end());
+    m.in_col.insert(m.in_col.end(), s.in_col.begin(), s.in_col.end());  // panel-relative
+    m.in_val.insert(m.in_val.end(), s.in_val.begin(), s.in_val.end());
+    const int32_t np = static_cast<int32_t>(s.pstart.size()) - 1;
+    for (int32_t q = 0; q < np; ++q) {
+      m.pstart.push_back(r0 + s.pstart[q + 1]);
+      m.panel_split.push_back(s.panel_split[q]);
+      m.panel_slot.push_back(slot0 + s.panel_slot[q]);
+      m.woff.push_back(w0 + s.woff[q]);
+    }
+    m.winv.insert(m.winv.end(), s.winv.begin(), s.winv.end());
+    m.nslots += s.nslots;
+    m.levels = std::max(m.levels, s.levels);
+    m.n += s.n;
+  }
+  // tasks of all parts by level; within a level, part by part in their order
+  struct Ref {
+    int32_t level, part, task;
+  };
+  std::vector<Ref> refs;
+  for (size_t k = 0; k < parts.size(); ++k)
+    for (size_t t = 0; t < parts[k]->task_panel.size(); ++t)
+      refs.push_back({parts[k]->task_level[t], static_cast<int32_t>(k), static_cast<int32_t>(t)});
+  std::stable_sort(refs.begin(), refs.end(), [](const Ref& a, const Ref& b) { return a.level < b.level; });
+  m.task_rec.reserve(8 * refs.size());
+  for (const Ref& r : refs) {
+    const PanelCsr& s = *parts[r.part];
+    const int32_t P = panel0[r.part] + s.task_panel[r.task];
+    m.task_panel.push_back(P);
+    m.task_kind.push_back(s.task_kind[r.task]);
+    m.task_level.push_back(r.level);
+    const int32_t rec[8] = {P, s.task_kind[r.task], m.pstart[P], m.pstart[P + 1] - m.pstart[P],
+                            m.panel_split[P], m.panel_slot[P], 0, 0};
+    m.task_rec.insert(m.task_rec.end(), rec, rec + 8);
+  }
+  return m;
+}
+
+// The inverse of every sub-panel's triangle: its own in-panel entries below
+// the diagonal and diag (nullptr: a unit diagonal) on it, inverted column by
+// column by substitution in float64. The kernel then forms a sub-panel's
+// values as one product with it instead of 64 dependent steps.
+void invert_panels(PanelCsr& s, const double* diag) {
+  const int32_t np = static_cast<int32_t>(s.pstart.size()) - 1;
+  s.woff.assign(np, 0);
+  int64_t total = 0;
+  for (int32_t p = 0; p < np; ++p) {
+    s.woff[p] = total;
+    const int32_t cnt = s.pstart[p + 1] - s.pstart[p];
+    for (int32_t k0 = 0; k0 < cnt; k0 += kPanel) {
+      const int64_t ck = std::min(kPanel, cnt - k0);
+      total += ck * (ck + 1) / 2;
+    }
+  }
+  s.winv.assign(total, 0.0);
+  std::vector<double> t(kPanel * kPanel), w(kPanel * kPanel);
+  for (int32_t p = 0; p < np; ++p) {
+    const int32_t lo = s.pstart[p], cnt = s.pstart[p + 1] - lo;
+    for (int32_t k0 = 0, j = 0; k0 < cnt; k0 += kPanel, ++j) {
+      const int32_t ck = std::min(kPanel, cnt - k0);
+      // the sub-panel's triangle, dense: strictly lower entries, then the diagonal
+      std::fill(t.begin(), t.end(), 0.0);
+      for (int32_t r = 0; r < ck; ++r) {
+        const int32_t i = lo + k0 + r;
+        for (int64_t e = s.in_split[i]; e < s.in_rp[i + 1]; ++e) t[r * kPanel + (s.in_col[e] - k0)] = s.in_val[e];
+        t[r * kPanel + r] = diag ? diag[i] : 1.0;
+      }
+      std::fill(w.begin(), w.end(), 0.0);
+      for (int32_t c = 0; c < ck; ++c)
+        for (int32_t r = c; r < ck; ++r) {
+          double a = r == c ? 1.0 : 0.0;
+          for (int32_t k = c; k < r; ++k) a -= t[r * kPanel + k] * w[k * kPanel + c];
+          w[r * kPanel + c] = a / t[r * kPanel + r];
+        }
+      double* out = s.winv.data() + s.woff[p] + static_cast<int64_t>(j) * kTriPacked;
+      for (int32_t r = 0; r < ck; ++r)
+        for (int32_t c = 0; c <= r; ++c) out[r * (r + 1) / 2 + c] = w[r * kPanel + c];
+    }
+  }
+}
+
+// Row i -> n-1-i and column j -> n-1-j: an upper factor becomes lower.
+HostCsr reverse_order(const HostCsr& u) {
+  HostCsr r;
+  const int32_t n = u.n;
+  r.n = n;
+  r.rowptr.assign(n + 1, 0);
+  r.col.reserve(u.nnz());
+  r.val.reserve(u.nnz());
+  for (int32_t k = 0; k < n; ++k) {
+    const int32_t i = n - 1 - k;
+    // walking row i backwards keeps the reversed columns increasing
+    for (int64_t p = u.rowptr[i + 1]; p-- > u.rowptr[i];) {
+      r.col.push_back(n - 1 - u.col[p]);
+      r.val.push_back(u.val[p]);
+    }
+    r.rowptr[k + 1] = static_cast<int64_t>(r.col.size());
+  }
+  return r;
+}
+
+// One solve as the device runs it, on the host: the tasks in ticket order,
+// read from the same task records; a slice task sums its share of each row's
+// older off-panel entries into its slot, a finish task adds the slots in
+// order and the newest entries, a whole-panel task all off-panel entries;
+// then a second sub-panel's entries on the first come off, and each
+// sub-panel's values are the product with its packed triangle inverse.
+// Every value a task reads must have been solved by an earlier ticket (the
+// condition under which every wait on the device ends) and every slot a
+// finish step reads must have been written; otherwise the schedule is
+// reported broken (returns false).
+bool replay_solve(const PanelCsr& t, const int32_t* gather, const double* in, double* out) {
+  const int32_t n = t.n;
+  std::vector<char> ready(n, 0);
+  std::vector<double> slots(static_cast<size_t>(t.nslots) * kPanelRows, 0.0);
+  std::vector<char> slot_set(static_cast<size_t>(t.nslots) * kPanelRows, 0);
+  std::vector<double> acc(kPanelRows);
+  bool ok = true;
+  auto sum = [&](int64_t e0, int64_t e1) {
+    double a = 0.0;
+    for (int64_t e = e0; e < e1; ++e) {
+      ok = ok && ready[t.off_col[e]];
+      a += t.off_val[e] * out[t.off_col[e]];
+    }
+    return a;
+  };
+  const size_t ntasks = t.task_rec.size() / 8;
+  for (size_t k = 0; k < ntasks && ok; ++k) {
+    const int32_t* rec = &t.task_rec[8 * k];
+    const int32_t q = rec[0], kind = rec[1], lo = rec[2], cnt = rec[3], S = rec[4], slot = rec[5];
+    if (kind >= 0 && kind < S) {  // slice
+      for (int32_t r = 0; r < cnt; ++r) {
+        const int64_t q0 = t.off_rp[lo + r], len = t.off_split[lo + r] - q0;
+        const size_t at = static_cast<size_t>(slot + kind) * kPanelRows + r;
+        slots[at] = sum(q0 + len * kind / S, q0 + len * (kind + 1) / S);
+        slot_set[at] = 1;
+      }
+      continue;
+    }
+    for (int32_t r = 0; r < cnt; ++r) {
+      const int32_t i = lo + r;
+      double sums;
+      if (kind < 0) {
+        sums = sum(t.off_rp[i], t.off_rp[i + 1]);
+      } else {  // finish
+        sums = 0.0;
+        for (int32_t m = 0; m < S; ++m) {
+          const size_t at = static_cast<size_t>(slot + m) * kPanelRows + r;
+          ok = ok && slot_set[at];
+          sums += slots[at];
+        }
+        sums += sum(t.off_split[i], t.off_rp[i + 1]);
+      }
+      acc[r] = in[gather ? gather[i] : i] - sums;
+    }
+    for (int32_t k0 = 0, j = 0; k0 < cnt; k0 += kPanel, ++j) {
+      const int32_t ck = std::min(kPanel, cnt - k0);
+      for (int32_t r = 0; r < ck && j > 0; ++r) {
+        const int32_t i = lo + k0 + r;
+        for (int64_t e = t.in_rp[i]; e < t.in_split[i]; ++e) acc[k0 + r] -= t.in_val[e] * out[lo + t.in_col[e]];
+      }
+      const double* w = t.winv.data() + t.woff[q] + static_cast<int64_t>(j) * kTriPacked;
+      for (int32_t r = 0; r < ck; ++r) {
+        double x = 0.0;
+        for (int32_t c = 0; c <= r; ++c) x += w[r * (r + 1) / 2 + c] * acc[k0 + c];
+        out[lo + k0 + r] = x;
+        ready[lo + k0 + r] = 1;
+      }
+    }
+  }
+  for (int32_t i = 0; i < n && ok; ++i) ok = ready[i];
+  return ok;
+}
+
+void tri_layout(const PanelCsr& t, int K, Layout& L, size_t* o) {
+  const size_t n = t.n;
+  o[kOffRp] = L.take((n + 1) * 8);
+  o[kOffCol] = L.take(t.off_col.size() * 4);
+  o[kOffVal] = L.take(t.off_val.size() * 8);
+  o[kOffSplit] = L.take(n * 8);
+  // in-panel entries: read only for a second sub-panel's entries on the first
+  const bool in_entries = kPanelRows > kPanel;
+  o[kInRp] = L.take(in_entries ? (n + 1) * 8 : 0);
+  o[kInSplit] = L.take(in_entries ? n * 8 : 0);
+  o[kInCol] = L.take(in_entries ? t.in_col.size() * 4 : 0);
+  o[kInVal] = L.take(in_entries ? t.in_val.size() * 8 : 0);
+  o[kPartials] = L.take(static_cast<size_t>(t.nslots) * kPanelRows * K * 8);
+  o[kWinv] = L.take(t.winv.size() * 8);
+  o[kWoff] = L.take(t.woff.size() * 8);
+  o[kTaskRec] = L.take(t.task_rec.size() * 4);
+}
+
+int tri_upload(char* ws, const size_t* off, const PanelCsr& t, int K, hipStream_t s, DevTri& out) {
+  auto up = [&](int slot, const void* src, size_t bytes) -> hipError_t {
+    return bytes ? hipMemcpyAsync(ws + off[slot], src, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
+  };
+  hipError_t e = up(kOffRp, t.off_rp.data(), (t.n + 1) * 8);
+  if (e == hipSuccess) e = up(kOffCol, t.off_col.data(), t.off_col.size() * 4);
+  if (e == hipSuccess) e = up(kOffVal, t.off_val.data(), t.off_val.size() * 8);
+  if (e == hipSuccess) e = up(kOffSplit, t.off_split.data(), static_cast<size_t>(t.n) * 8);
+  if (kPanelRows > kPanel) {
+    if (e == hipSuccess) e = up(kInRp, t.in_rp.data(), (t.n + 1) * 8);
+    if (e == hipSuccess) e = up(kInSplit, t.in_split.data(), static_cast<size_t>(t.n) * 8);
+    if (e == hipSuccess) e = up(kInCol, t.in_col.data(), t.in_col.size() * 4);
+    if (e == hipSuccess) e = up(kInVal, t.in_val.data(), t.in_val.size() * 8);
+  }
+  if (e == hipSuccess) e = up(kWinv, t.winv.data(), t.winv.size() * 8);
+  if (e == hipSuccess) e = up(kWoff, t.woff.data(), t.woff.size() * 8);
+  if (e == hipSuccess) e = up(kTaskRec, t.task_rec.data(), t.task_rec.size() * 4);
+  if (e != hipSuccess) return fail(COND_EHIP, std::string("solve upload: ") + hipGetErrorString(e));
+  auto at = [&](int slot) { return ws + off[slot]; };
+  if (t.nslots > 0)
+    launch_fill(t.nslots * kPanelRows * K, reinterpret_cast<double*>(at(kPartials)), kPending, s);
+  out.n = t.n;
+  out.off_rp = reinterpret_cast<const long long*>(at(kOffRp));
+  out.off_col = reinterpret_cast<const int*>(at(kOffCol));
+  out.off_val = reinterpret_cast<const double*>(at(kOffVal));
+  out.off_split = reinterpret_cast<const long long*>(at(kOffSplit));
+  out.in_rp = reinterpret_cast<const long long*>(at(kInRp));
+  out.in_split = reinterpret_cast<const long long*>(at(kInSplit));
+  out.in_col = reinterpret_cast<const int*>(at(kInCol));
+  out.in_val = reinterpret_cast<const double*>(at(kInVal));
+  out.winv = reinterpret_cast<const double*>(at(kWinv));
+  out.woff = reinterpret_cast<const long long*>(at(kWoff));
+  out.partials = reinterpret_cast<double*>(at(kPartials));
+  out.task_rec = reinterpret_cast<const int*>(at(kTaskRec));
+  out.ntasks = static_cast<int>(t.task_panel.size());
+  return COND_OK;
+}
+
+}  // namespace condest

@@ -17,11 +17,7 @@
 #include "internal.hpp"
 #include "bounds.hpp"
 #include "kernels.hpp"
-
-namespace condest {
-int lu_factor(const HostCsr& a, const HostCsr& at, const int32_t* col_perm_in, double tol,
-              cond_lu& lu);
-}
+#include "panels.hpp"
 
 using namespace condest;
 
@@ -34,22 +30,6 @@ using namespace condest;
 
 namespace {
 
-constexpr size_t kAlign = 256;
-
-struct Layout {
-  size_t off = 0;
-  size_t take(size_t bytes) {
-    size_t o = (off + kAlign - 1) / kAlign * kAlign;
-    off = o + bytes;
-    return o;
-  }
-};
-
-// Device arrays of one solve's panel structure (offsets into the workspace).
-enum TriSlot {
-  kOffRp, kOffCol, kOffVal, kOffSplit, kInRp, kInSplit, kInCol, kInVal,
-  kPartials, kWinv, kWoff, kTaskRec, kTriSlots
-};
 
 struct GraphKey {
   int route = -1;
@@ -64,273 +44,6 @@ struct GraphKey {
            std::memcmp(&p, &o.p, sizeof(p)) == 0;
   }
 };
-
-// A strictly lower-triangular factor in solve order, cut into panels of at
-// most kPanelRows consecutive rows, each split into the entries left of the
-// panel and the entries inside it, plus the order in which panels are handed
-// out. A row's in-panel entries list those on earlier 64-row sub-panels of
-// its panel first; in_split marks where the entries of its own sub-panel start.
-struct PanelCsr {
-  int32_t n = 0;
-  std::vector<int64_t> off_rp, in_rp, in_split, off_split;
-  std::vector<int32_t> off_col, in_col;
-  std::vector<double> off_val, in_val;
-  std::vector<int32_t> pstart;  // panel p holds rows [pstart[p], pstart[p+1])
-  std::vector<int32_t> panel_split, panel_slot;  // slices per panel, first slot of a split panel
-  std::vector<int32_t> task_panel, task_kind;    // tasks in dependency-level order
-  std::vector<int32_t> task_rec;  // per task: panel, kind, first row, rows, slices, slot, 0, 0
-  // inverse of each sub-panel's triangle, lower rows packed; panel p's
-  // sub-panel j at winv[woff[p] + j * kTriPacked]
-  std::vector<double> winv;
-  std::vector<int64_t> woff;
-  int32_t levels = 0;
-  int32_t nslots = 0;
-};
-
-// A panel whose rows hold more off-panel entries than this is cut into
-// slices (at most kMaxSlices) that separate blocks sum in parallel. The
-// slices take a row's entries on rows more than kRecentRows before the
-// panel; the finish step takes the newer ones, so a chain of panels (a dense
-// separator block) waits for its predecessor in one step, not two.
-constexpr int64_t kSliceEntries = 4096;
-constexpr int32_t kRecentRows = 64;
-constexpr int32_t kMaxSlices = kMaxSlicesDev;
-
-// Panel boundaries: a panel closes when it holds kPanelRows rows, or -- once
-// it holds at least kMinPanelRows -- before a row that needs nothing inside
-// it. Such a row usually opens an independent subtree of the elimination
-// order (a new leaf of the nested dissection); cutting there keeps independent
-// subtrees in different panels, so they are solved in parallel instead of as
-// a chain. With `merge`, such a row instead joins the open panel when it reads
-// panels exactly as deep as the open panel does: it would run in the same
-// dependency level anyway, and one task fewer is cheaper than the parallelism
-// (the leaves of a nested dissection are thousands of panels of a few rows).
-// A panel also closes at a 64-row boundary when the next row reads a panel
-// that is deeper in the dependency order than anything the open panel reads:
-// the panel's later sub-panels then never hold back its first one. What
-// remains inside a panel are chains (a dense separator block, mostly), which
-// one block solves sub-panel after sub-panel without waiting on others.
-constexpr int32_t kMinPanelRows = 4;
-
-std::vector<int32_t> cut_panels(const HostCsr& t, bool merge) {
-  std::vector<int32_t> ps{0};
-  std::vector<int32_t> pid(t.n, 0), plevel;  // panel of each closed row, level of each panel
-  int32_t s = 0;
-  // 1 + the deepest closed panel that row e reads (columns left of the open panel)
-  auto ext_level = [&](int32_t e) {
-    int32_t lv = 0;
-    for (int64_t p = t.rowptr[e]; p < t.rowptr[e + 1]; ++p)
-      if (t.col[p] < s) lv = std::max(lv, plevel[pid[t.col[p]]] + 1);
-    return lv;
-  };
-  int32_t cur = t.n ? ext_level(0) : 0;
-  for (int32_t e = 1; e < t.n; ++e) {
-    bool needs_panel = false;
-    for (int64_t p = t.rowptr[e]; p < t.rowptr[e + 1] && !needs_panel; ++p)
-      needs_panel = t.col[p] >= s;
-    const int32_t rows = e - s;
-    const int32_t lv = ext_level(e);
-    if (rows >= kPanelRows || (!needs_panel && rows >= kMinPanelRows && (!merge || lv != cur)) ||
-        (rows % kPanel == 0 && lv > cur)) {
-      const int32_t q = static_cast<int32_t>(plevel.size());
-      for (int32_t i = s; i < e; ++i) pid[i] = q;
-      plevel.push_back(cur);
-      ps.push_back(e);
-      s = e;
-      cur = ext_level(e);
-    } else {
-      cur = std::max(cur, lv);
-    }
-  }
-  ps.push_back(t.n);
-  return ps;
-}
-
-// Level of each panel: one more than the deepest panel it reads from.
-std::vector<int32_t> panel_levels(const HostCsr& t, const std::vector<int32_t>& pstart,
-                                  std::vector<int32_t>& pid) {
-  const int32_t np = static_cast<int32_t>(pstart.size()) - 1;
-  pid.assign(t.n, 0);
-  for (int32_t p = 0; p < np; ++p)
-    for (int32_t i = pstart[p]; i < pstart[p + 1]; ++i) pid[i] = p;
-  std::vector<int32_t> level(np, 0);
-  for (int32_t i = 0; i < t.n; ++i)
-    for (int64_t p = t.rowptr[i]; p < t.rowptr[i + 1]; ++p) {
-      const int32_t q = pid[t.col[p]];
-      if (q != pid[i]) level[pid[i]] = std::max(level[pid[i]], level[q] + 1);
-    }
-  return level;
-}
-
-int32_t slices_of(int64_t work) {
-  return static_cast<int32_t>(std::min<int64_t>(kMaxSlices, (work + kSliceEntries - 1) / kSliceEntries));
-}
-
-// Estimated solve time of a cut, in microseconds: every dependency level
-// costs a wait-and-publish round trip, every task a fixed hand-out and
-// set-up cost spread over the resident blocks. Both constants are a
-// least-squares fit to eight measured solves on MI355X (256 resident
-// blocks): the four factor orientations of a 242k-row hydro-mechanical
-// system, each cut both ways.
-constexpr double kLevelUs = 2.5;
-constexpr double kTaskUs = 0.0152;
-
-double cut_cost(const HostCsr& t, const std::vector<int32_t>& pstart) {
-  std::vector<int32_t> pid;
-  const std::vector<int32_t> level = panel_levels(t, pstart, pid);
-  const int32_t np = static_cast<int32_t>(pstart.size()) - 1;
-  int64_t tasks = 0;
-  for (int32_t p = 0; p < np; ++p) {
-    int64_t work = 0;  // entries left of the panel
-    for (int32_t i = pstart[p]; i < pstart[p + 1]; ++i)
-      for (int64_t e = t.rowptr[i]; e < t.rowptr[i + 1]; ++e) work += t.col[e] < pstart[p];
-    const int32_t S = slices_of(work);
-    tasks += S > 1 ? S + 1 : 1;
-  }
-  const int32_t levels = np ? 1 + *std::max_element(level.begin(), level.end()) : 0;
-  return kLevelUs * levels + kTaskUs * static_cast<double>(tasks);
-}
-
-PanelCsr split_panels(const HostCsr& t) {
-  PanelCsr s;
-  s.n = t.n;
-  // the cheaper of the two cuts by the cost model (merging the leaves pays
-  // where they are many small panels, splitting where they are few)
-  std::vector<int32_t> split = cut_panels(t, false), merged = cut_panels(t, true);
-  s.pstart = cut_cost(t, merged) < cut_cost(t, split) ? std::move(merged) : std::move(split);
-  const int32_t np = static_cast<int32_t>(s.pstart.size()) - 1;
-  std::vector<int32_t> pid;
-  const std::vector<int32_t> level = panel_levels(t, s.pstart, pid);
-  std::vector<int32_t> order(np);
-  for (int32_t p = 0; p < np; ++p) order[p] = p;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int32_t a, int32_t b) { return level[a] < level[b]; });
-  s.levels = np ? 1 + *std::max_element(level.begin(), level.end()) : 0;
-  s.off_rp.assign(t.n + 1, 0);
-  s.in_rp.assign(t.n + 1, 0);
-  s.in_split.assign(t.n, 0);
-  s.off_split.assign(t.n, 0);
-  for (int32_t i = 0; i < t.n; ++i) {
-    const int32_t lo = s.pstart[pid[i]];
-    const int32_t sub0 = lo + (i - lo) / kPanel * kPanel;  // first row of i's sub-panel
-    for (int64_t p = t.rowptr[i]; p < t.rowptr[i + 1]; ++p) {
-      const int32_t j = t.col[p];
-      if (j < lo) {
-        s.off_col.push_back(j);
-        s.off_val.push_back(t.val[p]);
-      } else if (j < sub0) {
-        s.in_col.push_back(j - lo);
-        s.in_val.push_back(t.val[p]);
-      }
-    }
-    s.in_split[i] = static_cast<int64_t>(s.in_col.size());
-    for (int64_t p = t.rowptr[i]; p < t.rowptr[i + 1]; ++p) {
-      const int32_t j = t.col[p];
-      if (j >= sub0) {
-        s.in_col.push_back(j - lo);
-        s.in_val.push_back(t.val[p]);
-      }
-    }
-    s.off_rp[i + 1] = static_cast<int64_t>(s.off_col.size());
-    s.in_rp[i + 1] = static_cast<int64_t>(s.in_col.size());
-  }
-  // tasks: whole panels, or slices followed by their finish step
-  s.panel_split.assign(np, 1);
-  s.panel_slot.assign(np, 0);
-  for (int32_t p : order) {
-    const int64_t work = s.off_rp[s.pstart[p + 1]] - s.off_rp[s.pstart[p]];
-    const int32_t S = slices_of(work);
-    if (S <= 1) {
-      s.task_panel.push_back(p);
-      s.task_kind.push_back(-1);
-      continue;
-    }
-    s.panel_split[p] = S;
-    s.panel_slot[p] = s.nslots;
-    s.nslots += S;
-    const int32_t c0 = s.pstart[p] - kRecentRows;  // older entries: columns below c0
-    for (int32_t i = s.pstart[p]; i < s.pstart[p + 1]; ++i) {
-      int64_t e = s.off_rp[i];
-      while (e < s.off_rp[i + 1] && s.off_col[e] < c0) ++e;  // columns are sorted in a row
-      s.off_split[i] = e;
-    }
-    for (int32_t k = 0; k <= S; ++k) {
-      s.task_panel.push_back(p);
-      s.task_kind.push_back(k);
-    }
-  }
-  s.task_rec.reserve(8 * s.task_panel.size());
-  for (size_t k = 0; k < s.task_panel.size(); ++k) {
-    const int32_t p = s.task_panel[k];
-    const int32_t rec[8] = {p, s.task_kind[k], s.pstart[p], s.pstart[p + 1] - s.pstart[p],
-                            s.panel_split[p], s.panel_slot[p], 0, 0};
-    s.task_rec.insert(s.task_rec.end(), rec, rec + 8);
-  }
-  return s;
-}
-
-// The inverse of every sub-panel's triangle: its own in-panel entries below
-// the diagonal and diag (nullptr: a unit diagonal) on it, inverted column by
-// column by substitution in float64. The kernel then forms a sub-panel's
-// values as one product with it instead of 64 dependent steps.
-void invert_panels(PanelCsr& s, const double* diag) {
-  const int32_t np = static_cast<int32_t>(s.pstart.size()) - 1;
-  s.woff.assign(np, 0);
-  int64_t total = 0;
-  for (int32_t p = 0; p < np; ++p) {
-    s.woff[p] = total;
-    const int32_t cnt = s.pstart[p + 1] - s.pstart[p];
-    for (int32_t k0 = 0; k0 < cnt; k0 += kPanel) {
-      const int64_t ck = std::min(kPanel, cnt - k0);
-      total += ck * (ck + 1) / 2;
-    }
-  }
-  s.winv.assign(total, 0.0);
-  std::vector<double> t(kPanel * kPanel), w(kPanel * kPanel);
-  for (int32_t p = 0; p < np; ++p) {
-    const int32_t lo = s.pstart[p], cnt = s.pstart[p + 1] - lo;
-    for (int32_t k0 = 0, j = 0; k0 < cnt; k0 += kPanel, ++j) {
-      const int32_t ck = std::min(kPanel, cnt - k0);
-      // the sub-panel's triangle, dense: strictly lower entries, then the diagonal
-      std::fill(t.begin(), t.end(), 0.0);
-      for (int32_t r = 0; r < ck; ++r) {
-        const int32_t i = lo + k0 + r;
-        for (int64_t e = s.in_split[i]; e < s.in_rp[i + 1]; ++e) t[r * kPanel + (s.in_col[e] - k0)] = s.in_val[e];
-        t[r * kPanel + r] = diag ? diag[i] : 1.0;
-      }
-      std::fill(w.begin(), w.end(), 0.0);
-      for (int32_t c = 0; c < ck; ++c)
-        for (int32_t r = c; r < ck; ++r) {
-          double a = r == c ? 1.0 : 0.0;
-          for (int32_t k = c; k < r; ++k) a -= t[r * kPanel + k] * w[k * kPanel + c];
-          w[r * kPanel + c] = a / t[r * kPanel + r];
-        }
-      double* out = s.winv.data() + s.woff[p] + static_cast<int64_t>(j) * kTriPacked;
-      for (int32_t r = 0; r < ck; ++r)
-        for (int32_t c = 0; c <= r; ++c) out[r * (r + 1) / 2 + c] = w[r * kPanel + c];
-    }
-  }
-}
-
-// Row i -> n-1-i and column j -> n-1-j: an upper factor becomes lower.
-HostCsr reverse_order(const HostCsr& u) {
-  HostCsr r;
-  const int32_t n = u.n;
-  r.n = n;
-  r.rowptr.assign(n + 1, 0);
-  r.col.reserve(u.nnz());
-  r.val.reserve(u.nnz());
-  for (int32_t k = 0; k < n; ++k) {
-    const int32_t i = n - 1 - k;
-    // walking row i backwards keeps the reversed columns increasing
-    for (int64_t p = u.rowptr[i + 1]; p-- > u.rowptr[i];) {
-      r.col.push_back(n - 1 - u.col[p]);
-      r.val.push_back(u.val[p]);
-    }
-    r.rowptr[k + 1] = static_cast<int64_t>(r.col.size());
-  }
-  return r;
-}
 
 // Row tiles for the streaming SpMV: consecutive rows, at most kTileRowsHost
 // rows and kTileEntriesHost entries per tile; a longer row is a tile alone.
@@ -433,24 +146,7 @@ void plan_layout(cond_plan* p) {
   p->o.at_tiles = L.take(p->tiles_at.size() * 4);
   if (p->want_min) {
     const PanelCsr* tris[4] = {&p->pL, &p->pU, &p->pUt, &p->pLt};
-    for (int f = 0; f < 4; ++f) {
-      const PanelCsr& t = *tris[f];
-      size_t* o = p->o.tri[f];
-      o[kOffRp] = L.take((n + 1) * 8);
-      o[kOffCol] = L.take(t.off_col.size() * 4);
-      o[kOffVal] = L.take(t.off_val.size() * 8);
-      o[kOffSplit] = L.take(static_cast<size_t>(n) * 8);
-      // in-panel entries: read only for a second sub-panel's entries on the first
-      const bool in_entries = kPanelRows > kPanel;
-      o[kInRp] = L.take(in_entries ? (n + 1) * 8 : 0);
-      o[kInSplit] = L.take(in_entries ? static_cast<size_t>(n) * 8 : 0);
-      o[kInCol] = L.take(in_entries ? t.in_col.size() * 4 : 0);
-      o[kInVal] = L.take(in_entries ? t.in_val.size() * 8 : 0);
-      o[kPartials] = L.take(static_cast<size_t>(t.nslots) * kPanelRows * 8);
-      o[kWinv] = L.take(t.winv.size() * 8);
-      o[kWoff] = L.take(t.woff.size() * 8);
-      o[kTaskRec] = L.take(t.task_rec.size() * 4);
-    }
+    for (int f = 0; f < 4; ++f) tri_layout(*tris[f], 1, L, p->o.tri[f]);
     p->o.row_perm = L.take(n * 4);
     p->o.rev = L.take(n * 4);
     p->o.scat_s = L.take(n * 4);
@@ -504,36 +200,7 @@ int upload_csr(cond_plan* p, const HostCsr& a, size_t rp, size_t col, size_t val
 }
 
 int upload_tri(cond_plan* p, const PanelCsr& t, const size_t* off, DevTri& out) {
-  int st;
-  if ((st = upload(p, off[kOffRp], t.off_rp.data(), (t.n + 1) * 8))) return st;
-  if ((st = upload(p, off[kOffCol], t.off_col.data(), t.off_col.size() * 4))) return st;
-  if ((st = upload(p, off[kOffVal], t.off_val.data(), t.off_val.size() * 8))) return st;
-  if ((st = upload(p, off[kOffSplit], t.off_split.data(), static_cast<size_t>(t.n) * 8))) return st;
-  if (kPanelRows > kPanel) {
-    if ((st = upload(p, off[kInRp], t.in_rp.data(), (t.n + 1) * 8))) return st;
-    if ((st = upload(p, off[kInSplit], t.in_split.data(), static_cast<size_t>(t.n) * 8))) return st;
-    if ((st = upload(p, off[kInCol], t.in_col.data(), t.in_col.size() * 4))) return st;
-    if ((st = upload(p, off[kInVal], t.in_val.data(), t.in_val.size() * 8))) return st;
-  }
-  if ((st = upload(p, off[kWinv], t.winv.data(), t.winv.size() * 8))) return st;
-  if ((st = upload(p, off[kWoff], t.woff.data(), t.woff.size() * 8))) return st;
-  if ((st = upload(p, off[kTaskRec], t.task_rec.data(), t.task_rec.size() * 4))) return st;
-  if (t.nslots > 0) launch_fill(t.nslots * kPanelRows, at_off<double>(p, off[kPartials]), kPending, p->stream);
-  out.n = t.n;
-  out.off_rp = at_off<long long>(p, off[kOffRp]);
-  out.off_col = at_off<int>(p, off[kOffCol]);
-  out.off_val = at_off<double>(p, off[kOffVal]);
-  out.off_split = at_off<long long>(p, off[kOffSplit]);
-  out.in_rp = at_off<long long>(p, off[kInRp]);
-  out.in_split = at_off<long long>(p, off[kInSplit]);
-  out.in_col = at_off<int>(p, off[kInCol]);
-  out.in_val = at_off<double>(p, off[kInVal]);
-  out.winv = at_off<double>(p, off[kWinv]);
-  out.woff = at_off<long long>(p, off[kWoff]);
-  out.partials = at_off<double>(p, off[kPartials]);
-  out.task_rec = at_off<int>(p, off[kTaskRec]);
-  out.ntasks = static_cast<int>(t.task_panel.size());
-  return COND_OK;
+  return tri_upload(p->ws, off, t, 1, p->stream, out);
 }
 
 AdamParams params_of(const cond_opts_t& o) {
@@ -1059,83 +726,6 @@ int cond_plan_solve_info(const cond_plan_t* p, int32_t* levels, int64_t* tasks, 
   return COND_OK;
 }
 
-namespace {
-
-// One solve as the device runs it, on the host: the tasks in ticket order,
-// read from the same task records; a slice task sums its share of each row's
-// older off-panel entries into its slot, a finish task adds the slots in
-// order and the newest entries, a whole-panel task all off-panel entries;
-// then a second sub-panel's entries on the first come off, and each
-// sub-panel's values are the product with its packed triangle inverse.
-// Every value a task reads must have been solved by an earlier ticket (the
-// condition under which every wait on the device ends) and every slot a
-// finish step reads must have been written; otherwise the schedule is
-// reported broken (returns false).
-bool replay_solve(const PanelCsr& t, const int32_t* gather, const double* in, double* out) {
-  const int32_t n = t.n;
-  std::vector<char> ready(n, 0);
-  std::vector<double> slots(static_cast<size_t>(t.nslots) * kPanelRows, 0.0);
-  std::vector<char> slot_set(static_cast<size_t>(t.nslots) * kPanelRows, 0);
-  std::vector<double> acc(kPanelRows);
-  bool ok = true;
-  auto sum = [&](int64_t e0, int64_t e1) {
-    double a = 0.0;
-    for (int64_t e = e0; e < e1; ++e) {
-      ok = ok && ready[t.off_col[e]];
-      a += t.off_val[e] * out[t.off_col[e]];
-    }
-    return a;
-  };
-  const size_t ntasks = t.task_rec.size() / 8;
-  for (size_t k = 0; k < ntasks && ok; ++k) {
-    const int32_t* rec = &t.task_rec[8 * k];
-    const int32_t q = rec[0], kind = rec[1], lo = rec[2], cnt = rec[3], S = rec[4], slot = rec[5];
-    if (kind >= 0 && kind < S) {  // slice
-      for (int32_t r = 0; r < cnt; ++r) {
-        const int64_t q0 = t.off_rp[lo + r], len = t.off_split[lo + r] - q0;
-        const size_t at = static_cast<size_t>(slot + kind) * kPanelRows + r;
-        slots[at] = sum(q0 + len * kind / S, q0 + len * (kind + 1) / S);
-        slot_set[at] = 1;
-      }
-      continue;
-    }
-    for (int32_t r = 0; r < cnt; ++r) {
-      const int32_t i = lo + r;
-      double sums;
-      if (kind < 0) {
-        sums = sum(t.off_rp[i], t.off_rp[i + 1]);
-      } else {  // finish
-        sums = 0.0;
-        for (int32_t m = 0; m < S; ++m) {
-          const size_t at = static_cast<size_t>(slot + m) * kPanelRows + r;
-          ok = ok && slot_set[at];
-          sums += slots[at];
-        }
-        sums += sum(t.off_split[i], t.off_rp[i + 1]);
-      }
-      acc[r] = in[gather ? gather[i] : i] - sums;
-    }
-    for (int32_t k0 = 0, j = 0; k0 < cnt; k0 += kPanel, ++j) {
-      const int32_t ck = std::min(kPanel, cnt - k0);
-      for (int32_t r = 0; r < ck && j > 0; ++r) {
-        const int32_t i = lo + k0 + r;
-        for (int64_t e = t.in_rp[i]; e < t.in_split[i]; ++e) acc[k0 + r] -= t.in_val[e] * out[lo + t.in_col[e]];
-      }
-      const double* w = t.winv.data() + t.woff[q] + static_cast<int64_t>(j) * kTriPacked;
-      for (int32_t r = 0; r < ck; ++r) {
-        double x = 0.0;
-        for (int32_t c = 0; c <= r; ++c) x += w[r * (r + 1) / 2 + c] * acc[k0 + c];
-        out[lo + k0 + r] = x;
-        ready[lo + k0 + r] = 1;
-      }
-    }
-  }
-  for (int32_t i = 0; i < n && ok; ++i) ok = ready[i];
-  return ok;
-}
-
-}  // namespace
-
 int cond_plan_solve_replay(const cond_plan_t* p, const double* x, double* r, double* s) {
   if (!p || !x || !r || !s) return fail(COND_EINVAL, "null argument");
   if (!p->want_min) return fail(COND_EINVAL, "the plan has no sigma_min route");
@@ -1210,6 +800,34 @@ int cond_plan_inverse_apply(cond_plan_t* p, const double* x, double* r, double* 
   CHK(hipMemcpyAsync(&hs, p->st_free, sizeof(RunState), hipMemcpyDeviceToHost, st));
   CHK(hipStreamSynchronize(st));
   if (hs.abort_wait) return fail(COND_ETIMEOUT, "triangular-solve wait timed out");
+  return COND_OK;
+}
+
+int cond_stream_triad(int64_t n, double* a, const double* b, const double* c, double scale,
+                      int32_t grid, int32_t reps, void* stream, double* ms) {
+  if (!a || !b || !c || !ms || n < 1 || grid < 1 || reps < 1)
+    return fail(COND_EINVAL, "invalid triad arguments");
+  if ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b) |
+       reinterpret_cast<uintptr_t>(c)) % 16)
+    return fail(COND_EINVAL, "triad arrays must be 16-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  CHK(hipEventCreate(&e0));
+  CHK(hipEventCreate(&e1));
+  launch_triad(n, a, b, c, scale, grid, s);  // warm-up
+  hipError_t e = hipEventRecord(e0, s);
+  for (int32_t r = 0; r < reps && e == hipSuccess; ++r) {
+    launch_triad(n, a, b, c, scale, grid, s);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float t = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (e != hipSuccess) return fail(COND_EHIP, std::string("triad: ") + hipGetErrorString(e));
+  *ms = static_cast<double>(t) / reps;
   return COND_OK;
 }
 

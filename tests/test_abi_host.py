@@ -259,3 +259,47 @@ def test_device_arguments_checked_before_the_library():
         with pytest.raises(ValueError):
             b.run(x)
     b.close()
+
+
+def test_batch_merged_solves_replayed_on_host():
+    # the batch's sigma_min route factors every matrix (parallel threads),
+    # merges the factors block-diagonally and plans the four solves over
+    # them; replayed on the host in ticket order, for every (matrix, start)
+    # the solves give A_m^-1 x and A_m^-T r: backward errors per matrix and
+    # agreement with the oracle's SuperLU solves
+    from oracle.inverse import LUInverse
+    from synth import hm_batch_specs, start_block
+
+    specs = hm_batch_specs(count=5, side_range=(5, 24), seed_sides=11, seed_base=12)
+    mats = [hydromech2d(s, log_eta=le, log_k=lk) for s, le, lk in specs]
+    b = pa.Batch([(m.n, m.rowptr, m.col, m.val) for m in mats], sigma_min=True)
+    f = b.fill()
+    assert f["nnz_l"] > 0 and f["nnz_u"] >= b.row0[-1]
+    starts = [start_block(m.n, 8, 70 + i) for i, m in enumerate(mats)]
+    x = pa.interleave_starts(starts)
+    r, s = b.solve_replay(x)
+    b.close()
+    for i, m in enumerate(mats):
+        lo, hi = b.row0[i], b.row0[i + 1]
+        A = m.to_scipy()
+        inv = LUInverse(m.n, m.rowptr, m.col, m.val)
+        for k in range(8):
+            xk = starts[i][k]
+            rk = r[lo * 8 + k:hi * 8:8]
+            sk = s[lo * 8 + k:hi * 8:8]
+            be_r = np.max(np.abs(A @ rk - xk) / (abs(A) @ np.abs(rk) + np.abs(xk)))
+            be_s = np.max(np.abs(A.T @ sk - rk) / (abs(A.T) @ np.abs(sk) + np.abs(rk)))
+            assert be_r < 1e-9 and be_s < 1e-9, (i, k, be_r, be_s)
+            r_ref, s_ref = inv.apply(xk)
+            assert np.linalg.norm(rk - r_ref) <= 1e-6 * np.linalg.norm(r_ref)
+            assert np.linalg.norm(sk - s_ref) <= 1e-6 * np.linalg.norm(s_ref)
+
+
+def test_batch_without_min_route_refuses_run_min():
+    mats = [hydromech2d(s, seed=s) for s in (5, 6)]
+    b = pa.Batch([(m.n, m.rowptr, m.col, m.val) for m in mats])
+    with pytest.raises(_binding.CondError):
+        b.fill()
+    with pytest.raises(_binding.CondError):
+        b.solve_replay(np.zeros(8 * b.row0[-1]))
+    b.close()

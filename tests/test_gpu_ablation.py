@@ -15,7 +15,7 @@ import pytest
 from oracle import PAOptions, estimate_cond as oracle_estimate
 from oracle.ablation import minimise_by_spmv
 from oracle.estimate import forward_apply
-from synth import diag_csr, hydromech2d, scaled_banded, start_vector
+from synth import diag_csr, hydromech2d, start_vector
 
 pytestmark = pytest.mark.gpu
 
@@ -80,16 +80,24 @@ def test_spmv_min_lockstep_hm(torch_cuda, side, seed):
 
 
 def test_spmv_min_with_sigma_max_gives_kappa(torch_cuda):
+    # both runs in one cond_plan_run call where the descent settles (a
+    # permuted diagonal matrix, kappa ~ 1e2): kappa against the closed form
+    # and the oracle's estimate by the same route
     import paper_2409_11515_amd as pa
 
     torch = torch_cuda
-    a = scaled_banded(2000, seed=5, col_decades=1, row_decades=1)
+    rng = np.random.default_rng(202)
+    n = 60
+    d = rng.choice([-1.0, 1.0], n) * 10.0 ** rng.uniform(0, 2, n)
+    a = diag_csr(d, rng.permutation(n), rng.permutation(n))
+    kw = dict(max_iter=20000, alpha_min=1e-4, stop_rtol=1e-9, stop_window=50)
     p = pa.Plan(a.n, a.rowptr, a.col, a.val, sigma_min_method=pa.COND_MIN_SPMV).bind()
     x0 = torch.as_tensor(start_vector(a.n, 2), device="cuda")
-    r = p.run(x0, x0, max_iter=400)
+    r = p.run(x0, x0, **kw)
     p.close()
     o = oracle_estimate(a.n, a.rowptr, a.col, a.val, start_vector(a.n, 2),
-                        opts=PAOptions(max_iter=400), min_method="spmv")
-    assert r["sigma_max"] == pytest.approx(o["sigma_max"], rel=1e-10)
-    assert r["sigma_min"] == pytest.approx(o["sigma_min"], rel=1e-10)
+                        opts=PAOptions(**kw), min_method="spmv")
+    kap = np.abs(d).max() / np.abs(d).min()
+    assert r["kappa"] == pytest.approx(kap, rel=1e-10)
     assert r["kappa"] == pytest.approx(o["kappa"], rel=1e-10)
+    assert r["iters_min"] == o["iters_min"] and r["iters_max"] == o["iters_max"]
