@@ -432,6 +432,24 @@ typedef struct {
 int cond_plan_error_bounds(cond_plan_t* plan, const double* x_hat, const double* b, double kappa,
                            double norm_a, cond_bounds_t* out);
 
+/* The same bounds for callers that cannot allocate device memory (code that
+ * must not call hipMalloc, e.g. inside a serving loop): A is given on the
+ * device as CSR (rowptr int64 [n+1], col int32 [nnz], val [nnz]; caller-owned,
+ * columns in [0, n)), x_hat and b as device arrays of length n, all on the
+ * current device; work is enqueued on `stream` (hipStream_t, NULL = the null
+ * stream) and the call returns after the result is on the host. The
+ * residual's block partials and sums live in a fixed scratch array inside
+ * the library, 4 x 2048 doubles (64 KiB) per device, held until the process
+ * ends; a launch uses at most 2048 blocks, so no n exceeds it, and every
+ * call writes every slot it reads (nothing carries over between calls).
+ * Calls that overlap on one device share that array and race: serialise
+ * them. Same arguments and results as cond_plan_error_bounds (which it
+ * matches bit for bit on the same data); COND_EINVAL also for n < 1,
+ * nnz < 0 or a null pointer. */
+int cond_error_bounds_noalloc(int32_t n, int64_t nnz, const int64_t* rowptr, const int32_t* col,
+                              const double* val, const double* x_hat, const double* b,
+                              double kappa, double norm_a, void* stream, cond_bounds_t* out);
+
 /* create + bind (library-owned memory) + run + destroy. */
 int cond_estimate(const cond_csr_t* A, const cond_opts_t* o, const double* x0_max,
                   const double* x0_min, void* stream, cond_result_t* out);

@@ -457,6 +457,28 @@ def estimate_cond(n, rowptr, col, val, x0_max, x0_min=None, stream=None, **opts)
     return {f: getattr(res, f) for f, _ in ResultT._fields_}
 
 
+def error_bounds_noalloc(rowptr, col, val, x_hat, b, kappa, norm_a, stream=None) -> dict:
+    """cond_error_bounds_noalloc: the error bounds for A given on the device
+    (rowptr int64 [n+1], col int32 [nnz], val float64 [nnz], all CUDA
+    tensors) without any device allocation inside the library."""
+    import torch
+
+    from ._binding import BoundsT
+
+    n = int(rowptr.numel()) - 1
+    nnz = int(col.numel())
+    prp = _vec(rowptr, n + 1, "rowptr", torch.int64)
+    pc = _vec(col, nnz, "col", torch.int32)
+    pv = _vec(val, nnz, "val")
+    px = _vec(x_hat, n, "x_hat")
+    pb = _vec(b, n, "b")
+    out = BoundsT()
+    check(lib().cond_error_bounds_noalloc(n, nnz, prp, pc, pv, px, pb, float(kappa),
+                                          float(norm_a), _stream_ptr(torch, stream),
+                                          C.byref(out)), "error_bounds_noalloc")
+    return {f: getattr(out, f) for f, _ in BoundsT._fields_}
+
+
 class CNN:
     """The warm-start network on the device (``cond_cnn_*``).
 

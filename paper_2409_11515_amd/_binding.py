@@ -84,7 +84,7 @@ EXPORTS = (
     "cond_cnn_predict", "cond_cnn_gradients", "cond_cnn_train_step", "cond_cnn_activation",
     "cond_cnn_destroy", "cond_plan_error_bounds", "cond_plan_column_norms",
     "cond_batch_run_min", "cond_batch_fill", "cond_estimate_batched", "cond_batch_solve_replay",
-    "cond_stream_triad",
+    "cond_stream_triad", "cond_error_bounds_noalloc",
 )
 
 BATCH_K = 8
@@ -155,6 +155,8 @@ def lib():
     L.cond_batch_fill.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(dbl)]
     L.cond_estimate_batched.argtypes = [vp, i32, C.POINTER(OptsT), vp, vp, vp, vp]
     L.cond_plan_error_bounds.argtypes = [vp, vp, vp, dbl, dbl, C.POINTER(BoundsT)]
+    L.cond_error_bounds_noalloc.argtypes = [i32, i64, vp, vp, vp, vp, vp, dbl, dbl, vp,
+                                            C.POINTER(BoundsT)]
     for name in EXPORTS:
         getattr(L, name)  # raises AttributeError if a declared symbol is missing
     _lib = L
