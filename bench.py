@@ -274,20 +274,108 @@ def bench_batch(w, args):
         if i % 16 == 15:
             print(f"[bench] plain loop: {i+1} matrices", file=sys.stderr, flush=True)
     b_iters = int(rb["pair_iters"].sum())
+    b.close()
+    kap = bench_batch_kappa(mats, starts, rb["sigma_max"], opts, args) if args.kappa_systems else None
+    full = kap is not None and kap["systems"] == len(mats)
+    value = (batched_s + kap["sigma_min_run_s"]) / len(mats) if full else batched_s / len(mats)
     out = {
         "metric": "time-to-kappa (1e-3 rel) per matrix + SpMV HBM GB/s",
-        "value": batched_s / len(mats), "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "value": value, "unit": "s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": batched_s * 1e3, "higher_is_better": False,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "c4batch: 64 hydro-mechanical matrices, sides U{51..401}, "
-                               "8 starts each, sigma_max run", "rows": nrows, "nnz": nnz,
+                               "8 starts each", "rows": nrows, "nnz": nnz,
                    "tile_rows": b.tile_rows, "grid": b.grid, "parallelism": "single GPU"},
+        "value_is": ("batched sigma_max and sigma_min runs of every matrix (kappa), per matrix"
+                     if full else "batched sigma_max run per matrix"),
         "batched_s": batched_s, "plain_loop_s": t_plain, "speedup": t_plain / batched_s,
         "pair_updates": {"batched": b_iters, "plain": plain_iters},
         "sigma_max_rel_diff_max": max_rel, "setup_s": setup_s,
+        "kappa": kap,
     }
-    b.close()
     print(json.dumps(out), flush=True)
+
+
+def bench_batch_kappa(mats, starts_max, sigma_max, opts, args):
+    """Batched sigma_min over the first `kappa_systems` matrices (every
+    matrix's LU on the host in parallel threads, the solves of all of them
+    and their 8 starts in one launch each), kappa per matrix, and the plain
+    loop (one plan and LU per matrix, one sigma_min run per start) on a
+    sample of them against a batch of the same sample."""
+    import torch
+
+    import paper_2409_11515_amd as pa
+    from synth import start_block
+
+    count = min(args.kappa_systems, len(mats))
+    sub = mats[:count]
+    starts = [start_block(m.n, 8, 9000 + i) for i, m in enumerate(sub)]
+    t0 = time.perf_counter()
+    b = pa.Batch([(m.n, m.rowptr, m.col, m.val) for m in sub], sigma_min=True, **opts)
+    create_s = time.perf_counter() - t0
+    fill = b.fill()
+    t0 = time.perf_counter()
+    b.bind()
+    torch.cuda.synchronize()
+    bind_s = time.perf_counter() - t0
+    print(f"[bench] batched sigma_min: {count} matrices, LU + schedules {create_s:.0f}s "
+          f"(LU threads {fill['lu_s']:.0f}s), bind {bind_s:.0f}s, fill {fill['nnz_l'] + fill['nnz_u']:.3g}",
+          file=sys.stderr, flush=True)
+    x0 = torch.as_tensor(pa.interleave_starts(starts), device="cuda")
+    b.run_min(x0, max_iter=30)  # capture the graph
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rm = b.run_min(x0)
+    torch.cuda.synchronize()
+    min_s = time.perf_counter() - t0
+    b.close()
+    kappa = np.asarray(sigma_max[:count]) / rm["sigma_min"]
+    print(f"[bench] batched sigma_min run {min_s:.1f}s, kappa {kappa.min():.3g}..{kappa.max():.3g}",
+          file=sys.stderr, flush=True)
+    # plain loop and a batch on a sample spread over the sizes
+    order = np.argsort([m.n for m in sub])
+    sample = sorted(int(order[k]) for k in np.linspace(0, count - 1, min(args.kappa_sample, count)).astype(int))
+    smats = [sub[i] for i in sample]
+    sb = pa.Batch([(m.n, m.rowptr, m.col, m.val) for m in smats], sigma_min=True, **opts).bind()
+    sx0 = torch.as_tensor(pa.interleave_starts([starts[i] for i in sample]), device="cuda")
+    sb.run_min(sx0, max_iter=30)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rs = sb.run_min(sx0)
+    torch.cuda.synchronize()
+    sample_batched_s = time.perf_counter() - t0
+    sb.close()
+    t_plain = 0.0
+    max_rel = 0.0
+    plain_updates = 0
+    for j, i in enumerate(sample):
+        m = sub[i]
+        p = pa.Plan(m.n, m.rowptr, m.col, m.val, **opts).bind()
+        xs = [torch.as_tensor(starts[i][k], device="cuda") for k in range(8)]
+        p.run(None, xs[0], max_iter=30)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = [p.run(None, xs[k]) for k in range(8)]
+        torch.cuda.synchronize()
+        t_plain += time.perf_counter() - t0
+        plain_updates += sum(r["iters_min"] for r in res)
+        smin = min(r["sigma_min"] for r in res)
+        max_rel = max(max_rel, abs(smin - rs["sigma_min"][j]) / smin,
+                      abs(smin - rm["sigma_min"][i]) / smin)
+        p.close()
+    print(f"[bench] sample of {len(sample)}: plain loop {t_plain:.1f}s, batched {sample_batched_s:.1f}s",
+          file=sys.stderr, flush=True)
+    return {"systems": count, "rows": int(sum(m.n for m in sub)),
+            "fill": fill["nnz_l"] + fill["nnz_u"], "lu_threads_s": fill["lu_s"],
+            "create_s": create_s, "bind_s": bind_s, "sigma_min_run_s": min_s,
+            "pair_updates": int(rm["pair_iters"].sum()),
+            "kappa_min": float(kappa.min()), "kappa_max": float(kappa.max()),
+            "kappa_per_matrix_s": min_s / count,
+            "sample": {"systems": sample, "sides": [int(round((m.n / 6) ** 0.5)) for m in smats],
+                       "plain_loop_s": t_plain, "batched_s": sample_batched_s,
+                       "speedup": t_plain / sample_batched_s, "plain_updates": plain_updates,
+                       "batched_updates": int(rs["pair_iters"].sum()),
+                       "sigma_min_rel_diff_max": max_rel}}
 
 
 def make_matrix(w):
@@ -311,7 +399,7 @@ def _source_hash(kind):
     with open(os.path.join(csrc, "plan.hip")) as f:
         plan = f.read()
     if kind == "trsv":
-        with open(os.path.join(csrc, "panels.hip")) as f:
+        with open(os.path.join(csrc, "panels.cpp")) as f:
             panels = f.read()
         parts = [src[src.index("// ----------------------------------------------------------------- trsv"):
                      src.index("// ------------------------------------------------- trsv, several sides")],
@@ -434,6 +522,10 @@ def main():
     ap.add_argument("--alpha-min", type=float, default=2.5e-3,
                     help="step-size floor: on a plateau alpha halves down to this (0: constant alpha)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kappa-systems", type=int, default=64,
+                    help="c4batch: matrices of the batched sigma_min run (0: sigma_max only)")
+    ap.add_argument("--kappa-sample", type=int, default=6,
+                    help="c4batch: matrices of the plain-loop comparison of the sigma_min run")
     ap.add_argument("--no-hbm-section", dest="hbm_section", action="store_false",
                     help="skip the streaming ceiling and the 1001x1001 SpMV roofline section")
     ap.add_argument("--train-scale", type=float, default=1.0,
@@ -614,10 +706,16 @@ def stream_ceiling():
     """The library's streaming triad over 3 x 2 GiB (24 B per element)."""
     import paper_2409_11515_amd as pa
 
-    r = pa.stream_triad(1 << 28, grid=4096, reps=20)
-    print(f"[bench] stream triad: {r['gbs']:.0f} GB/s", file=sys.stderr, flush=True)
+    best = None
+    for grid in (8192, 32768, 65536):
+        r = pa.stream_triad(1 << 28, grid=grid, reps=20)
+        if best is None or r["gbs"] > best[0]["gbs"]:
+            best = (r, grid)
+    r, grid = best
+    print(f"[bench] stream triad: {r['gbs']:.0f} GB/s ({grid} blocks)", file=sys.stderr, flush=True)
     return {"gbs": r["gbs"], "ms": r["ms"], "bytes": r["bytes"], "peak_frac": r["gbs"] / HBM_PEAK_GBS,
-            "kernel": "a = b + s c, 2 x 8-byte elements per thread and step, 4096 x 256 threads"}
+            "kernel": f"a = b + s c over 3 x 2 GiB, 16-byte accesses, 4 in flight per thread, "
+                      f"best of 8192 / 32768 / 65536 blocks of 256 threads: {grid}"}
 
 
 def hm1001_section(triad_gbs):

@@ -264,6 +264,13 @@ int cond_plan_solve_replay(const cond_plan_t* plan, const double* x, double* r, 
 /* One step of the path at a time, on device vectors of length n (for checks
  * against the oracle): y = A x; y = A^T x; r = A^-1 x and s = A^-T r
  * (Algorithm 2). Asynchronous on the plan's stream. */
+/* Test hook for the failure path: the next sigma_min run or inverse apply
+ * of this plan starts as if one of its triangular-solve waits had already
+ * timed out, so every solve kernel exits at once and the call reports
+ * COND_ETIMEOUT, with no kernel waiting on anything. The call after that
+ * re-arms the solves' slice slots and runs normally, as after a real
+ * time-out. COND_EINVAL for a plan without the sigma_min route. */
+int cond_plan_inject_timeout(cond_plan_t* plan);
 int cond_plan_spmv(cond_plan_t* plan, int transpose, const double* x, double* y);
 /* flags of cond_plan_spmv's `transpose` argument: bit 0 = A^T; bit 1 = the
  * column-scaled matrix, y = (A D^-1) x or (A D^-1)^T x */

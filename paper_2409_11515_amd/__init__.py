@@ -280,6 +280,10 @@ class Plan:
                                            C.byref(out)), "plan_error_bounds")
         return {f: getattr(out, f) for f, _ in BoundsT._fields_}
 
+    def inject_timeout(self):
+        """Test hook: the next sigma_min run or inverse apply starts timed out."""
+        check(lib().cond_plan_inject_timeout(self._h), "plan_inject_timeout")
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().cond_plan_destroy(self._h)

@@ -84,7 +84,7 @@ EXPORTS = (
     "cond_cnn_predict", "cond_cnn_gradients", "cond_cnn_train_step", "cond_cnn_activation",
     "cond_cnn_destroy", "cond_plan_error_bounds", "cond_plan_column_norms",
     "cond_batch_run_min", "cond_batch_fill", "cond_estimate_batched", "cond_batch_solve_replay",
-    "cond_stream_triad", "cond_error_bounds_noalloc",
+    "cond_stream_triad", "cond_error_bounds_noalloc", "cond_plan_inject_timeout",
 )
 
 BATCH_K = 8
@@ -151,6 +151,7 @@ def lib():
     L.cond_batch_run_min.argtypes = [vp, C.POINTER(OptsT), vp, vp, vp, vp, vp, vp, vp,
                                      C.POINTER(dbl)]
     L.cond_batch_solve_replay.argtypes = [vp, vp, vp, vp]
+    L.cond_plan_inject_timeout.argtypes = [vp]
     L.cond_stream_triad.argtypes = [i64, vp, vp, vp, dbl, i32, i32, vp, C.POINTER(dbl)]
     L.cond_batch_fill.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(dbl)]
     L.cond_estimate_batched.argtypes = [vp, i32, C.POINTER(OptsT), vp, vp, vp, vp]

@@ -21,9 +21,9 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libcondest.so")
 
-HIP_SOURCES = ["kernels.hip", "panels.hip", "plan.hip", "batch_kernels.hip", "batch.hip", "cnn.hip",
+HIP_SOURCES = ["kernels.hip", "panels_upload.hip", "plan.hip", "batch_kernels.hip", "batch.hip", "cnn.hip",
                "noalloc.hip"]
-HOST_SOURCES = ["host_csr.cpp", "host_order.cpp", "host_lu.cpp"]
+HOST_SOURCES = ["host_csr.cpp", "host_order.cpp", "host_lu.cpp", "panels.cpp"]
 ARCH = os.environ.get("CONDEST_ARCH", "gfx950")
 
 

@@ -8,6 +8,8 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <future>
 #include <memory>
@@ -20,6 +22,7 @@
 #include "condest.h"
 #include "internal.hpp"
 #include "panels.hpp"
+#include "panels_upload.hpp"
 
 using namespace condest;
 
@@ -87,11 +90,12 @@ struct cond_batch {
   DevTri dL, dU, dUt, dLt;
   int64_t nnz_l = 0, nnz_u = 0;
   double lu_ms = 0.0;
+  bool rearm_slots = false;  // a solve wait timed out: re-arm the slice slots first
   hipGraphExec_t exec_min = nullptr;
   BatchKey key_min;
   struct {
     size_t a_rp, a_col, a_val, at_rp, at_col, at_val, tiles, tile_mat, mat_tile0, live_mat,
-        live_pref;
+        live_pref, mat_live;
     size_t vec[7], parts[4], pairs, g;
     size_t tri[4][kTriSlots];
     size_t row_perm, rev, scat_s, svec[4], tickets;
@@ -152,15 +156,17 @@ void enqueue_batch_min_iteration(cond_batch* b, const BatchArgs& a, const AdamPa
   batch_launch_rearm(a, b->grid, s);
   // r = A^-1 x: L c = P x, U z = c (z reversed); s = A^-T r: U^T h = z,
   // L^T wv = h, w = P^T wv
+  const int* live = a.mat_live;
   launch_trsv_multi(K, b->dL, a.x, reinterpret_cast<const int*>(b->ws + b->o.row_perm), a.c,
-                    nullptr, nullptr, a.tickets + 0, stop, abort, s);
+                    nullptr, nullptr, a.tickets + 0, stop, abort, live, s);
   const int* rev = reinterpret_cast<const int*>(b->ws + b->o.rev);
-  launch_trsv_multi(K, b->dU, a.c, rev, a.z, nullptr, nullptr, a.tickets + 1, stop, abort, s);
+  launch_trsv_multi(K, b->dU, a.c, rev, a.z, nullptr, nullptr, a.tickets + 1, stop, abort, live, s);
   batch_launch_sumsq_rev(a, b->grid, s);
   batch_launch_reduce(a, 1, p, s);
-  launch_trsv_multi(K, b->dUt, a.z, rev, a.h, nullptr, nullptr, a.tickets + 2, stop, abort, s);
+  launch_trsv_multi(K, b->dUt, a.z, rev, a.h, nullptr, nullptr, a.tickets + 2, stop, abort, live, s);
   launch_trsv_multi(K, b->dLt, a.h, rev, a.wv, a.w,
-                    reinterpret_cast<const int*>(b->ws + b->o.scat_s), a.tickets + 3, stop, abort, s);
+                    reinterpret_cast<const int*>(b->ws + b->o.scat_s), a.tickets + 3, stop, abort, live,
+                    s);
   batch_launch_pass1(a, p, b->grid, s);
   batch_launch_reduce(a, 2, p, s);
   batch_launch_pass2(a, p, b->grid, s);
@@ -209,6 +215,10 @@ int batch_factor(cond_batch* b, std::vector<HostCsr>& as, std::vector<HostCsr>& 
     invert_panels(p, diag);
     return p;
   };
+  // CONDEST_PROGRESS=1: a line on stderr as each matrix is factored
+  const char* env = std::getenv("CONDEST_PROGRESS");
+  const bool progress = env && env[0] == '1';
+  std::atomic<int32_t> done(0);
   auto worker = [&]() {
     for (int32_t m; (m = next.fetch_add(1)) < count;) {
       try {
@@ -242,6 +252,8 @@ int batch_factor(cond_batch* b, std::vector<HostCsr>& as, std::vector<HostCsr>& 
         status[m] = COND_ENOMEM;
         why[m] = "host memory exhausted";
       }
+      const int32_t d = done.fetch_add(1) + 1;
+      if (progress) std::fprintf(stderr, "[condest] batch set-up: %d of %d matrices factored\n", d, count);
     }
   };
   std::vector<std::thread> pool;
@@ -267,12 +279,14 @@ int batch_factor(cond_batch* b, std::vector<HostCsr>& as, std::vector<HostCsr>& 
     const bool reversed = f == 1 || f == 3;
     std::vector<const PanelCsr*> ps;
     std::vector<int64_t> offs;
+    std::vector<int32_t> groups;
     for (int32_t k = 0; k < count; ++k) {
       const int32_t m = reversed ? count - 1 - k : k;
       ps.push_back(&parts[m].t[f]);
       offs.push_back(reversed ? n - b->row0[m + 1] : b->row0[m]);
+      groups.push_back(m);
     }
-    *out[f] = merge_panels(ps, offs);
+    *out[f] = merge_panels(ps, offs, groups);
     for (int32_t m = 0; m < count; ++m) parts[m].t[f] = PanelCsr();
   }
   b->rev.resize(n);
@@ -361,6 +375,7 @@ int cond_batch_create(const cond_csr_t* As, int32_t count, const cond_opts_t* o,
   b->o.mat_tile0 = take(off, (count + 1) * 4);
   b->o.live_mat = take(off, static_cast<size_t>(count) * 4);
   b->o.live_pref = take(off, (count + 1) * 4);
+  b->o.mat_live = take(off, static_cast<size_t>(count) * 4);
   for (int k = 0; k < 7; ++k) b->o.vec[k] = take(off, n * K * 8);
   for (int k = 0; k < 4; ++k) b->o.parts[k] = take(off, b->max_tiles * K * 8);
   b->o.pairs = take(off, static_cast<size_t>(count) * K * sizeof(BatchPair));
@@ -443,6 +458,7 @@ int cond_batch_bind(cond_batch_t* b, void* workspace, size_t bytes, void* stream
   a.mat_tile0 = reinterpret_cast<const int*>(b->ws + b->o.mat_tile0);
   a.live_mat = reinterpret_cast<int*>(b->ws + b->o.live_mat);
   a.live_pref = reinterpret_cast<int*>(b->ws + b->o.live_pref);
+  a.mat_live = reinterpret_cast<int*>(b->ws + b->o.mat_live);
   a.a_rowptr = reinterpret_cast<const int*>(b->ws + b->o.a_rp);
   a.a_col = reinterpret_cast<const int*>(b->ws + b->o.a_col);
   a.a_val = reinterpret_cast<const double*>(b->ws + b->o.a_val);
@@ -580,6 +596,14 @@ int batch_run(cond_batch_t* b, int route, const cond_opts_t* o, const double* x0
     if (e != hipSuccess) return fail(COND_EHIP, std::string("instantiate: ") + hipGetErrorString(e));
     key = k;
   }
+  if (route == 1 && b->rearm_slots) {
+    const PanelCsr* tris[4] = {&b->pL, &b->pU, &b->pUt, &b->pLt};
+    const DevTri* devs[4] = {&b->dL, &b->dU, &b->dUt, &b->dLt};
+    for (int f = 0; f < 4; ++f)
+      if (tris[f]->nslots > 0)
+        launch_fill(tris[f]->nslots * kPanelRows * kBatchK, devs[f]->partials, kPending, b->stream);
+    b->rearm_slots = false;
+  }
   // initial per-pair state
   for (int q = 0; q < npairs; ++q) {
     BatchPair& s = b->h_pairs[q];
@@ -608,14 +632,24 @@ int batch_run(cond_batch_t* b, int route, const cond_opts_t* o, const double* x0
     return COND_OK;
   };
   int st;
+  const char* env = std::getenv("CONDEST_PROGRESS");
+  const bool progress = env && env[0] == '1';
+  auto t_last = std::chrono::steady_clock::now();
   if ((st = launch_chunk(0))) return st;
   for (;;) {
     const bool more = launched < total;
     if (more && (st = launch_chunk(cur ^ 1))) return st;
     BCHK(hipEventSynchronize(ev[cur]));
     bool all = true;
-    for (int q = 0; q < npairs && all; ++q) all = slot[cur][q].stopped != 0;
+    int running = 0;
+    for (int q = 0; q < npairs; ++q) running += slot[cur][q].stopped == 0;
+    all = running == 0;
     if (all || !more) break;
+    if (progress && std::chrono::steady_clock::now() - t_last > std::chrono::seconds(30)) {
+      t_last = std::chrono::steady_clock::now();
+      std::fprintf(stderr, "[condest] batch %s run: %lld updates, %d of %d pairs running\n",
+                   route == 1 ? "sigma_min" : "sigma_max", launched - chunk, running, npairs);
+    }
     cur ^= 1;
   }
   BCHK(hipEventRecord(b->ev1, b->stream));
@@ -635,6 +669,7 @@ int batch_run(cond_batch_t* b, int route, const cond_opts_t* o, const double* x0
       if (pair_iters) pair_iters[m * kBatchK + kk] = s.iters;
       if (pair_status) pair_status[m * kBatchK + kk] = s.status;
       if (s.status && !status) status = s.status;
+      if (s.status == COND_ETIMEOUT) b->rearm_slots = true;
       if (s.status == COND_OK) best = std::max(best, s.best);
     }
     // every start is a lower bound of ||M||_2: keep the largest

@@ -43,6 +43,7 @@ struct BatchArgs {
   const int* mat_tile0 = nullptr;    // tiles of matrix m: [mat_tile0[m], mat_tile0[m+1])
   int* live_mat = nullptr;           // matrices with a running start, in order
   int* live_pref = nullptr;          // their tiles: live index u in [live_pref[j], live_pref[j+1])
+  int* mat_live = nullptr;           // per matrix: 1 while one of its starts runs
   const int* a_rowptr = nullptr;     // block-diagonal A (global row and column indices)
   const int* a_col = nullptr;
   const double* a_val = nullptr;

@@ -133,6 +133,8 @@ __global__ __launch_bounds__(kB) void b_live_k(BatchArgs a) {
     if (m < a.nmat && !a.pairs[static_cast<long long>(m) * K + threadIdx.x % K].stopped)
       run_sh[threadIdx.x / K] = 1;  // benign: every writer stores 1
     __syncthreads();
+    if (a.mat_live && threadIdx.x < kB / K && m0 + static_cast<int>(threadIdx.x) < a.nmat)
+      a.mat_live[m0 + threadIdx.x] = run_sh[threadIdx.x];
     if (threadIdx.x == 0) {
       int j = j_sh, u = u_sh;
       for (int q = 0; q < kB / K && m0 + q < a.nmat; ++q)
@@ -386,19 +388,27 @@ __global__ __launch_bounds__(kB) void b_pass2_k(BatchArgs a, AdamParams p) {
 // ------------------------------------------------------- sigma_min route
 // Re-arm the solves' vectors with the not-yet-solved pattern and reset their
 // ticket counters before the four solves of an update.
+// Only the rows of matrices with a running start: the solves skip the rest.
+// c and h are in pivot order (tile t's rows), z and wv reversed (its mirror).
 __global__ __launch_bounds__(kB) void b_rearm_k(BatchArgs a) {
-  if (a.g->stop_all) return;
-  const long long total = a.nrows * kBatchK;
-  unsigned long long* v[4] = {reinterpret_cast<unsigned long long*>(a.c),
-                              reinterpret_cast<unsigned long long*>(a.z),
-                              reinterpret_cast<unsigned long long*>(a.h),
-                              reinterpret_cast<unsigned long long*>(a.wv)};
-  for (long long i = blockIdx.x * static_cast<long long>(kB) + threadIdx.x; i < total;
-       i += static_cast<long long>(gridDim.x) * kB) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) v[k][i] = kPending;
-  }
   if (blockIdx.x == 0 && threadIdx.x < 4) a.tickets[threadIdx.x] = 0u;
+  if (a.g->stop_all) return;
+  unsigned long long* c = reinterpret_cast<unsigned long long*>(a.c);
+  unsigned long long* z = reinterpret_cast<unsigned long long*>(a.z);
+  unsigned long long* h = reinterpret_cast<unsigned long long*>(a.h);
+  unsigned long long* wv = reinterpret_cast<unsigned long long*>(a.wv);
+  LiveTiles lt;
+  lt.begin(a);
+  for (long long t = lt.tile(a); t >= 0; ++lt.u, t = lt.tile(a)) {
+    const long long r0 = a.tiles[t], r1 = a.tiles[t + 1];
+    const long long m0 = a.nrows - r1;  // the mirrored rows
+    for (long long e = threadIdx.x; e < (r1 - r0) * kBatchK; e += kB) {
+      c[r0 * kBatchK + e] = kPending;
+      h[r0 * kBatchK + e] = kPending;
+      z[m0 * kBatchK + e] = kPending;
+      wv[m0 * kBatchK + e] = kPending;
+    }
+  }
 }
 
 // ||A^-1 x||^2 per (tile, start): z is the U solve's output in reversed pivot

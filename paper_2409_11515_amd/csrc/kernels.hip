@@ -481,12 +481,19 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_k(TrsvArgs t, const double* _
     const int cnt = ra.w;
     const int S = rb.x;
     double* slots = t.partials + static_cast<long long>(rb.y) * kPanelRows;
+    const long long woff = static_cast<long long>(static_cast<unsigned>(rb.z)) |
+                           (static_cast<long long>(rb.w) << 32);
+    // the task's row pointers and split points, loaded by ticket alone (in
+    // flight together with the record, not after it)
+    const long long* trp = t.task_rp + static_cast<long long>(T) * (kPanelRows + 1);
+    const long long* tsp = t.task_sp + static_cast<long long>(T) * kPanelRows;
     long long q0[kSubPanels], q1[kSubPanels];  // the group's rows g + 64 j: off-panel ranges
 #pragma unroll
     for (int j = 0; j < kSubPanels; ++j) {
       const int r = g + kPanel * j;
-      q0[j] = r < cnt ? t.off_rp[lo + r] : 0;
-      q1[j] = r < cnt ? t.off_rp[lo + r + 1] : 0;
+      const long long a0 = trp[r], a1 = trp[r + 1];
+      q0[j] = r < cnt ? a0 : 0;
+      q1[j] = r < cnt ? a1 : 0;
     }
     if (kind >= 0 && kind < S) {
       // ---- slice task: partial off-panel sums over one slice of every row's
@@ -495,7 +502,7 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_k(TrsvArgs t, const double* _
 #pragma unroll
       for (int j = 0; j < kSubPanels; ++j) {
         const int r = g + kPanel * j;
-        if (r < cnt) q1[j] = t.off_split[lo + r];
+        if (r < cnt) q1[j] = tsp[r];
         const long long len = q1[j] - q0[j];
         q1[j] = q0[j] + len * (kind + 1) / S;
         q0[j] = q0[j] + len * kind / S;
@@ -521,11 +528,17 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_k(TrsvArgs t, const double* _
       lc[u] = 0;
       lv[u] = 0.0;
     }
+    // (into registers: their LDS copies are written once the sums are in, so
+    // that no wait for these loads stands between the task record and the
+    // first loads of the off-panel entries)
+    double bval[kSubPanels];
+    double wreg[kSubPanels][kLocalPerLane];
 #pragma unroll
     for (int j = 0; j < kSubPanels; ++j) {
       const int r = g + kPanel * j;
+      bval[j] = 0.0;
       if (r < cnt) {
-        if (sub == 0) b_sh[r] = rhs_perm ? rhs[rhs_perm[lo + r]] : rhs[lo + r];
+        if (sub == 0) bval[j] = rhs_perm ? rhs[rhs_perm[lo + r]] : rhs[lo + r];
         if (j > 0) {  // entries on the first sub-panel: at most 64, four per lane
           const long long e0 = t.in_rp[lo + r], em = t.in_split[lo + r];
 #pragma unroll
@@ -539,11 +552,11 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_k(TrsvArgs t, const double* _
       // row g of the sub-panel's inverse, columns sub + 16 u (zero above the
       // diagonal and past the sub-panel's last row)
       const int ck = cnt - kPanel * j < kPanel ? cnt - kPanel * j : kPanel;
-      const double* w = t.winv + t.woff[P] + static_cast<long long>(j) * kTriPacked;
+      const double* w = t.winv + woff + static_cast<long long>(j) * kTriPacked;
 #pragma unroll
       for (int u = 0; u < kLocalPerLane; ++u) {
         const int c = sub + u * kLanesPerRow;
-        w_sh[j][g * kLdW + c] = (g < ck && c <= g) ? w[g * (g + 1) / 2 + c] : 0.0;
+        wreg[j][u] = (g < ck && c <= g) ? w[g * (g + 1) / 2 + c] : 0.0;
       }
     }
     // ---- off-panel sums of every row (these wait for the panel's inputs)
@@ -588,15 +601,20 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_k(TrsvArgs t, const double* _
         for (int off = kLanesPerRow / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kLanesPerRow);
         // the row's newest entries (on the panels just before this one): the
         // finish step waits for them itself, one hop fewer on a chain
-        const double recent = r < cnt ? row_sum(t.off_split[lo + r], t.off_rp[lo + r + 1], sub,
-                                                t.off_col, t.off_val, out, st)
+        const double recent = r < cnt ? row_sum(tsp[r], trp[r + 1], sub, t.off_col, t.off_val, out, st)
                                       : 0.0;
         sums[j] = acc + recent;
       }
     }
 #pragma unroll
-    for (int j = 0; j < kSubPanels; ++j)
-      if (g + kPanel * j < cnt && sub == 0) t_sh[g + kPanel * j] = sums[j];
+    for (int j = 0; j < kSubPanels; ++j) {
+      if (g + kPanel * j < cnt && sub == 0) {
+        t_sh[g + kPanel * j] = sums[j];
+        b_sh[g + kPanel * j] = bval[j];
+      }
+#pragma unroll
+      for (int u = 0; u < kLocalPerLane; ++u) w_sh[j][g * kLdW + sub + u * kLanesPerRow] = wreg[j][u];
+    }
     __syncthreads();
     // ---- the sub-panels in order: x = W (b - sums), row g by its 16 lanes
 #pragma unroll
@@ -666,46 +684,62 @@ __device__ __noinline__ double wait_pending_flag(const double* p, int* abort) {
   return __longlong_as_double(static_cast<long long>(bits));
 }
 
-// Off-panel sum of one row for side kk over entries [p0, p1): entry lane es
-// takes entries es, es + EL, ...; every lane of the row's group that holds
-// side kk gets the sum.
+// Off-panel sums of one row over entries [p0, p1) for all K sides at once:
+// lane sub of the row's 16 takes entries sub, sub + 16, ... (the single-side
+// solve's order, so each side's sum is rounded exactly as there), reads the
+// entry's column and value once and the K solved values of that column as
+// K/2 16-byte loads, and keeps K sums; a 16-lane butterfly then gives every
+// lane all K sums, and the lane returns side kk's.
 template <int K>
-__device__ __forceinline__ double row_sum_multi(long long p0, long long p1, int es, int kk,
+__device__ __forceinline__ double row_sum_multi(long long p0, long long p1, int sub, int kk,
                                                 const int* __restrict__ col,
                                                 const double* __restrict__ val, const double* out,
                                                 int* abort) {
-  constexpr int EL = kLanesPerRow / K;
-  double acc = 0.0;
-  for (long long base = p0; base < p1; base += EL * kUnroll) {
-    int j[kUnroll];
-    double a[kUnroll];
-    unsigned long long bits[kUnroll];
+  constexpr int U = 2;  // entries in flight per lane
+  double acc[K];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const long long p = base + u * EL + es;
+  for (int k = 0; k < K; ++k) acc[k] = 0.0;
+  for (long long base = p0; base < p1; base += kLanesPerRow * U) {
+    int j[U];
+    double a[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long long p = base + u * kLanesPerRow + sub;
       const bool act = p < p1;
       j[u] = act ? col[p] : -1;
       a[u] = act ? val[p] : 0.0;
     }
+    double2 v[U][K / 2];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u)
-      bits[u] = j[u] >= 0 ? __hip_atomic_load(reinterpret_cast<const unsigned long long*>(
-                                                  out + static_cast<long long>(j[u]) * K + kk),
-                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)
-                          : 0ull;
+    for (int u = 0; u < U; ++u) {
+      const double2* src = reinterpret_cast<const double2*>(out + static_cast<long long>(j[u] < 0 ? 0 : j[u]) * K);
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      if (j[u] >= 0) {
-        const double xj = bits[u] != kPending
-                              ? __longlong_as_double(static_cast<long long>(bits[u]))
-                              : wait_pending_flag(out + static_cast<long long>(j[u]) * K + kk, abort);
-        acc += a[u] * xj;
+      for (int h = 0; h < K / 2; ++h) v[u][h] = j[u] >= 0 ? src[h] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (j[u] < 0) continue;
+      const double* q = out + static_cast<long long>(j[u]) * K;
+#pragma unroll
+      for (int h = 0; h < K / 2; ++h) {
+        double x0 = v[u][h].x, x1 = v[u][h].y;
+        if (static_cast<unsigned long long>(__double_as_longlong(x0)) == kPending)
+          x0 = wait_pending_flag(q + 2 * h, abort);
+        if (static_cast<unsigned long long>(__double_as_longlong(x1)) == kPending)
+          x1 = wait_pending_flag(q + 2 * h + 1, abort);
+        acc[2 * h] += a[u] * x0;
+        acc[2 * h + 1] += a[u] * x1;
       }
     }
   }
 #pragma unroll
-  for (int off = kLanesPerRow / 2; off >= K; off >>= 1) acc += __shfl_xor(acc, off, kLanesPerRow);
-  return acc;
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int off = kLanesPerRow / 2; off > 0; off >>= 1) acc[k] += __shfl_xor(acc[k], off, kLanesPerRow);
+  double r = acc[0];
+#pragma unroll
+  for (int k = 1; k < K; ++k) r = kk == k ? acc[k] : r;
+  return r;
 }
 
 template <int K>
@@ -714,7 +748,7 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_multi_k(TrsvArgs t, const dou
                                                            double* out, double* __restrict__ scatter,
                                                            const int* __restrict__ scatter_perm,
                                                            unsigned* ticket, const int* stop,
-                                                           int* abort) {
+                                                           int* abort, const int* group_live) {
   constexpr int EL = kLanesPerRow / K;
   static_assert(EL >= 1 && EL * K == kLanesPerRow, "K divides the 16 lanes of a row");
   __shared__ double w_sh[kPanel * kLdW];  // the sub-panel triangle's inverse, row-major
@@ -737,6 +771,11 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_multi_k(TrsvArgs t, const dou
     __syncthreads();
     const unsigned T = task_sh;
     if (T >= static_cast<unsigned>(t.ntasks)) break;
+    // a block (matrix) whose starts have all stopped: nothing reads its values
+    if (group_live && !group_live[t.task_group[T]]) {
+      __syncthreads();  // task_sh is reused
+      continue;
+    }
     const int4 ra = reinterpret_cast<const int4*>(t.task_rec)[2 * static_cast<long long>(T)];
     const int4 rb = reinterpret_cast<const int4*>(t.task_rec)[2 * static_cast<long long>(T) + 1];
     const int P = ra.x;
@@ -745,26 +784,32 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_multi_k(TrsvArgs t, const dou
     const int cnt = ra.w;
     const int S = rb.x;
     double* slots = t.partials + static_cast<long long>(rb.y) * kPanelRows * K;
+    const long long woff = static_cast<long long>(static_cast<unsigned>(rb.z)) |
+                           (static_cast<long long>(rb.w) << 32);
+    const long long* trp = t.task_rp + static_cast<long long>(T) * (kPanelRows + 1);
+    const long long* tsp = t.task_sp + static_cast<long long>(T) * kPanelRows;
     const bool row = g < cnt;
-    long long q0 = row ? t.off_rp[lo + g] : 0, q1 = row ? t.off_rp[lo + g + 1] : 0;
+    const long long a0 = trp[g], a1 = trp[g + 1], sp = tsp[g];
+    long long q0 = row ? a0 : 0, q1 = row ? a1 : 0;
     if (kind >= 0 && kind < S) {
       // slice task: partial sums over one slice of the row's older entries
-      if (row) q1 = t.off_split[lo + g];
+      if (row) q1 = sp;
       const long long len = q1 - q0;
       const long long s1 = q0 + len * (kind + 1) / S;
       const long long s0 = q0 + len * kind / S;
-      const double part = row_sum_multi<K>(s0, s1, es, kk, t.off_col, t.off_val, out, abort);
+      const double part = row_sum_multi<K>(s0, s1, sub, kk, t.off_col, t.off_val, out, abort);
       if (row && es == 0)
         publish(slots + (static_cast<long long>(kind) * kPanelRows + g) * K + kk, part);
       __syncthreads();  // task_sh is reused
       continue;
     }
-    // everything that needs no solved value: right-hand sides and the inverse
+    // everything that needs no solved value: right-hand sides and the
+    // inverse (into LDS: registers are what the K sums need)
     if (row && es == 0)
       b_sh[g * K + kk] = rhs_perm ? rhs[static_cast<long long>(rhs_perm[lo + g]) * K + kk]
                                   : rhs[(lo + g) * K + kk];
     {
-      const double* w = t.winv + t.woff[P];
+      const double* w = t.winv + woff;
 #pragma unroll
       for (int u = 0; u < kLocalPerLane; ++u) {
         const int c = sub + u * kLanesPerRow;
@@ -773,24 +818,24 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_multi_k(TrsvArgs t, const dou
     }
     double sum;
     if (kind < 0) {
-      sum = row_sum_multi<K>(q0, q1, es, kk, t.off_col, t.off_val, out, abort);
+      sum = row_sum_multi<K>(q0, q1, sub, kk, t.off_col, t.off_val, out, abort);
     } else {
       // finish: entry lane es adds slices es, es + EL, ... of side kk in that
-      // fixed order (8 loads in flight), re-arming each slot it read
+      // fixed order (4 loads in flight), re-arming each slot it read
       double acc = 0.0;
       if (row) {
         unsigned long long* sp = reinterpret_cast<unsigned long long*>(slots);
-        for (int k0 = es; k0 < S; k0 += EL * 8) {
-          unsigned long long bits[8];
+        for (int k0 = es; k0 < S; k0 += EL * 4) {
+          unsigned long long bits[4];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
+          for (int u = 0; u < 4; ++u) {
             const int k = k0 + u * EL;
             bits[u] = k < S ? __hip_atomic_load(sp + (static_cast<long long>(k) * kPanelRows + g) * K + kk,
                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                             : 0ull;
           }
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
+          for (int u = 0; u < 4; ++u) {
             const int k = k0 + u * EL;
             if (k < S) {
               const long long at = (static_cast<long long>(k) * kPanelRows + g) * K + kk;
@@ -803,8 +848,7 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_multi_k(TrsvArgs t, const dou
       }
 #pragma unroll
       for (int off = kLanesPerRow / 2; off >= K; off >>= 1) acc += __shfl_xor(acc, off, kLanesPerRow);
-      const double recent = row ? row_sum_multi<K>(t.off_split[lo + g], t.off_rp[lo + g + 1], es,
-                                                   kk, t.off_col, t.off_val, out, abort)
+      const double recent = row ? row_sum_multi<K>(sp, q1, sub, kk, t.off_col, t.off_val, out, abort)
                                 : 0.0;
       sum = acc + recent;
     }
@@ -1016,8 +1060,8 @@ __global__ __launch_bounds__(kBlock) void reduce3_k(const double* __restrict__ p
 // ---------------------------------------------------------------- triad
 // a = b + s c over n doubles: the streaming reference every HBM-bound kernel
 // is quoted against (24 bytes per element). Each thread moves two elements
-// per step as 16-byte loads and stores; consecutive threads take consecutive
-// 16-byte chunks.
+// per chunk as 16-byte loads and stores, four chunks in flight; consecutive
+// threads take consecutive 16-byte chunks.
 __global__ __launch_bounds__(kBlock) void triad_k(long long n, double* __restrict__ a,
                                                   const double* __restrict__ b,
                                                   const double* __restrict__ c, double s) {
@@ -1026,7 +1070,19 @@ __global__ __launch_bounds__(kBlock) void triad_k(long long n, double* __restric
   const double2* c2 = reinterpret_cast<const double2*>(c);
   double2* a2 = reinterpret_cast<double2*>(a);
   const long long stride = static_cast<long long>(gridDim.x) * kBlock;
-  for (long long i = blockIdx.x * static_cast<long long>(kBlock) + threadIdx.x; i < n2; i += stride) {
+  long long i = blockIdx.x * static_cast<long long>(kBlock) + threadIdx.x;
+  // four chunks in flight per thread, then the remainder one at a time
+  for (; i + 3 * stride < n2; i += 4 * stride) {
+    double2 x[4], y[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      x[u] = b2[i + u * stride];
+      y[u] = c2[i + u * stride];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a2[i + u * stride] = make_double2(x[u].x + s * y[u].x, x[u].y + s * y[u].y);
+  }
+  for (; i < n2; i += stride) {
     const double2 x = b2[i], y = c2[i];
     a2[i] = make_double2(x.x + s * y.x, x.y + s * y.y);
   }
@@ -1037,6 +1093,10 @@ __global__ void fill_k(long long n, unsigned long long* p, unsigned long long bi
   for (long long i = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<long long>(gridDim.x) * blockDim.x)
     p[i] = bits;
+}
+
+__global__ void set_int_k(int* p, int v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
 __global__ void zero_u32_k(unsigned* p, int count) {
@@ -1128,22 +1188,22 @@ void launch_trsv(const DevTri& t, const double* rhs, const int* rhs_perm, double
 
 void launch_trsv_multi(int K, const DevTri& t, const double* rhs, const int* rhs_perm, double* out,
                        double* scatter, const int* scatter_perm, unsigned* ticket, const int* stop,
-                       int* abort, hipStream_t s) {
+                       int* abort, const int* group_live, hipStream_t s) {
   long long blocks = t.ntasks < 512 ? t.ntasks : 512;
   if (blocks < 1) blocks = 1;
   const int g = static_cast<int>(blocks);
   switch (K) {
     case 2:
       trsv_multi_k<2><<<g, kTrsvBlock, 0, s>>>(t, rhs, rhs_perm, out, scatter, scatter_perm, ticket,
-                                               stop, abort);
+                                               stop, abort, group_live);
       break;
     case 4:
       trsv_multi_k<4><<<g, kTrsvBlock, 0, s>>>(t, rhs, rhs_perm, out, scatter, scatter_perm, ticket,
-                                               stop, abort);
+                                               stop, abort, group_live);
       break;
     default:
       trsv_multi_k<8><<<g, kTrsvBlock, 0, s>>>(t, rhs, rhs_perm, out, scatter, scatter_perm, ticket,
-                                               stop, abort);
+                                               stop, abort, group_live);
       break;
   }
 }
@@ -1184,6 +1244,8 @@ void launch_fill(int n, double* p, unsigned long long bits, hipStream_t s) {
   if (blocks < 1) blocks = 1;
   fill_k<<<blocks, kBlock, 0, s>>>(n, reinterpret_cast<unsigned long long*>(p), bits);
 }
+
+void launch_set_int(int* p, int v, hipStream_t s) { set_int_k<<<1, 64, 0, s>>>(p, v); }
 
 void launch_zero_u32(unsigned* p, int count, hipStream_t s) {
   zero_u32_k<<<(count + 63) / 64, 64, 0, s>>>(p, count);

@@ -19,6 +19,8 @@
 
 #include <cstdint>
 
+#include "solve_consts.hpp"
+
 namespace condest {
 
 constexpr int kBlock = 256;      // threads per block (4 waves of 64)
@@ -87,10 +89,6 @@ constexpr long long kTileEntriesHost = 2048;
 // task t works on panel task_panel[t]; task_kind[t] = -1 for the whole panel,
 // 0..S-1 for slice k of its off-panel entries, S for the step that adds the
 // slices and finishes the panel (S = panel_split[panel]).
-constexpr int kPanel = 64;       // rows of a sub-panel: one wave solves its triangle
-constexpr int kMaxSlicesDev = 64;  // most slices a heavy panel is cut into
-constexpr int kPanelRows = 64;   // rows of a panel: its sub-panels are solved in order by one block
-constexpr int kTriPacked = kPanel * (kPanel + 1) / 2;  // entries of a packed 64-row triangle
 struct DevTri {
   int n = 0;
   const long long* off_rp = nullptr;
@@ -111,8 +109,15 @@ struct DevTri {
   int ntasks = 0;
   // per task, in dependency-level order, 8 ints (two 16-byte loads): panel,
   // kind (-1 whole panel, 0..S-1 slice, S finish), first row, rows, slices
-  // S, first partial-sum slot, 0, 0
+  // S, first partial-sum slot, offset of the panel's inverse in winv (low
+  // and high 32 bits)
   const int* task_rec = nullptr;
+  // per task: off-panel row pointers of its rows (kPanelRows + 1 values,
+  // padded) and their split points (kPanelRows values), indexed by ticket
+  const long long* task_rp = nullptr;
+  const long long* task_sp = nullptr;
+  // joined schedules (a batch): the block (matrix) of each task, or null
+  const int* task_group = nullptr;
 };
 using TrsvArgs = DevTri;
 
@@ -143,10 +148,12 @@ void launch_trsv(const DevTri& t, const double* rhs, const int* rhs_perm, double
 // The same solve for K in {2, 4, 8} interleaved right-hand sides (row i,
 // side k at i * K + k; rhs, out and scatter in that layout, the permutations
 // over rows). t.partials must hold K values per slot row. Skipped when *stop
-// (may be null) is non-zero; a timed-out wait sets *abort.
+// (may be null) is non-zero; a timed-out wait sets *abort. With group_live
+// and t.task_group, the tasks of a block whose flag is 0 are skipped (the
+// blocks of a joined schedule never read each other's values).
 void launch_trsv_multi(int K, const DevTri& t, const double* rhs, const int* rhs_perm, double* out,
                        double* scatter, const int* scatter_perm, unsigned* ticket, const int* stop,
-                       int* abort, hipStream_t s);
+                       int* abort, const int* group_live, hipStream_t s);
 void launch_pass1(int n, const double* x, const double* w, double* m, double* v, double* d,
                   double* xbest, const double* parts_x, const double* parts_y, int grid,
                   double* parts_xd, RunState* st, double* trace, const AdamParams& p,
@@ -163,5 +170,6 @@ void launch_triad(long long n, double* a, const double* b, const double* c, doub
                   hipStream_t s);
 void launch_fill(int n, double* p, unsigned long long bits, hipStream_t s);
 void launch_zero_u32(unsigned* p, int count, hipStream_t s);
+void launch_set_int(int* p, int v, hipStream_t s);
 
 }  // namespace condest

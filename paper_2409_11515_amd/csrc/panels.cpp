@@ -1,7 +1,8 @@
 // Panel schedules of the sparse triangular solves: the planner (panel cuts
 // chosen by a measured cost model, dependency levels, slices of heavy panels,
-// task records), the inverses of the sub-panel triangles, and the device
-// layout and upload of one solve.
+// task records), the inverses of the sub-panel triangles, the schedule of
+// several independent blocks joined into one, the host replay of a solve,
+// and the device layout of one solve. Plain host C++.
 
 #include "panels.hpp"
 
@@ -116,6 +117,24 @@ double cut_cost(const HostCsr& t, const std::vector<int32_t>& pstart) {
   return kLevelUs * levels + kTaskUs * static_cast<double>(tasks);
 }
 
+// The parts of each task record that need the inverses' offsets, and the
+// per-task row pointers and split points.
+void finish_records(PanelCsr& s) {
+  const size_t ntasks = s.task_panel.size();
+  s.task_rp.assign(ntasks * (kPanelRows + 1), 0);
+  s.task_sp.assign(ntasks * kPanelRows, 0);
+  for (size_t k = 0; k < ntasks; ++k) {
+    const int32_t p = s.task_panel[k];
+    const int64_t w = s.woff.empty() ? 0 : s.woff[p];
+    s.task_rec[8 * k + 6] = static_cast<int32_t>(static_cast<uint32_t>(w & 0xffffffffLL));
+    s.task_rec[8 * k + 7] = static_cast<int32_t>(w >> 32);
+    const int32_t lo = s.pstart[p], cnt = s.pstart[p + 1] - lo;
+    for (int32_t r = 0; r <= kPanelRows; ++r)
+      s.task_rp[k * (kPanelRows + 1) + r] = s.off_rp[lo + std::min(r, cnt)];
+    for (int32_t r = 0; r < cnt; ++r) s.task_sp[k * kPanelRows + r] = s.off_split[lo + r];
+  }
+}
+
 }  // namespace
 
 PanelCsr split_panels(const HostCsr& t) {
@@ -198,7 +217,8 @@ PanelCsr split_panels(const HostCsr& t) {
   return s;
 }
 
-PanelCsr merge_panels(const std::vector<const PanelCsr*>& parts, const std::vector<int64_t>& offsets) {
+PanelCsr merge_panels(const std::vector<const PanelCsr*>& parts, const std::vector<int64_t>& offsets,
+                      const std::vector<int32_t>& groups) {
   PanelCsr m;
   m.off_rp.push_back(0);
   m.in_rp.push_back(0);
@@ -250,10 +270,12 @@ PanelCsr merge_panels(const std::vector<const PanelCsr*>& parts, const std::vect
     m.task_panel.push_back(P);
     m.task_kind.push_back(s.task_kind[r.task]);
     m.task_level.push_back(r.level);
+    m.task_group.push_back(groups[r.part]);
     const int32_t rec[8] = {P, s.task_kind[r.task], m.pstart[P], m.pstart[P + 1] - m.pstart[P],
                             m.panel_split[P], m.panel_slot[P], 0, 0};
     m.task_rec.insert(m.task_rec.end(), rec, rec + 8);
   }
+  finish_records(m);
   return m;
 }
 
@@ -298,6 +320,7 @@ void invert_panels(PanelCsr& s, const double* diag) {
         for (int32_t c = 0; c <= r; ++c) out[r * (r + 1) / 2 + c] = w[r * kPanel + c];
     }
   }
+  finish_records(s);
 }
 
 // Row i -> n-1-i and column j -> n-1-j: an upper factor becomes lower.
@@ -348,10 +371,14 @@ bool replay_solve(const PanelCsr& t, const int32_t* gather, const double* in, do
   const size_t ntasks = t.task_rec.size() / 8;
   for (size_t k = 0; k < ntasks && ok; ++k) {
     const int32_t* rec = &t.task_rec[8 * k];
-    const int32_t q = rec[0], kind = rec[1], lo = rec[2], cnt = rec[3], S = rec[4], slot = rec[5];
+    const int32_t kind = rec[1], lo = rec[2], cnt = rec[3], S = rec[4], slot = rec[5];
+    const int64_t woff = static_cast<int64_t>(static_cast<uint32_t>(rec[6])) |
+                         (static_cast<int64_t>(rec[7]) << 32);
+    const int64_t* trp = &t.task_rp[k * (kPanelRows + 1)];
+    const int64_t* tsp = &t.task_sp[k * kPanelRows];
     if (kind >= 0 && kind < S) {  // slice
       for (int32_t r = 0; r < cnt; ++r) {
-        const int64_t q0 = t.off_rp[lo + r], len = t.off_split[lo + r] - q0;
+        const int64_t q0 = trp[r], len = tsp[r] - q0;
         const size_t at = static_cast<size_t>(slot + kind) * kPanelRows + r;
         slots[at] = sum(q0 + len * kind / S, q0 + len * (kind + 1) / S);
         slot_set[at] = 1;
@@ -362,7 +389,7 @@ bool replay_solve(const PanelCsr& t, const int32_t* gather, const double* in, do
       const int32_t i = lo + r;
       double sums;
       if (kind < 0) {
-        sums = sum(t.off_rp[i], t.off_rp[i + 1]);
+        sums = sum(trp[r], trp[r + 1]);
       } else {  // finish
         sums = 0.0;
         for (int32_t m = 0; m < S; ++m) {
@@ -370,7 +397,7 @@ bool replay_solve(const PanelCsr& t, const int32_t* gather, const double* in, do
           ok = ok && slot_set[at];
           sums += slots[at];
         }
-        sums += sum(t.off_split[i], t.off_rp[i + 1]);
+        sums += sum(tsp[r], trp[r + 1]);
       }
       acc[r] = in[gather ? gather[i] : i] - sums;
     }
@@ -380,7 +407,7 @@ bool replay_solve(const PanelCsr& t, const int32_t* gather, const double* in, do
         const int32_t i = lo + k0 + r;
         for (int64_t e = t.in_rp[i]; e < t.in_split[i]; ++e) acc[k0 + r] -= t.in_val[e] * out[lo + t.in_col[e]];
       }
-      const double* w = t.winv.data() + t.woff[q] + static_cast<int64_t>(j) * kTriPacked;
+      const double* w = t.winv.data() + woff + static_cast<int64_t>(j) * kTriPacked;
       for (int32_t r = 0; r < ck; ++r) {
         double x = 0.0;
         for (int32_t c = 0; c <= r; ++c) x += w[r * (r + 1) / 2 + c] * acc[k0 + c];
@@ -409,44 +436,9 @@ void tri_layout(const PanelCsr& t, int K, Layout& L, size_t* o) {
   o[kWinv] = L.take(t.winv.size() * 8);
   o[kWoff] = L.take(t.woff.size() * 8);
   o[kTaskRec] = L.take(t.task_rec.size() * 4);
-}
-
-int tri_upload(char* ws, const size_t* off, const PanelCsr& t, int K, hipStream_t s, DevTri& out) {
-  auto up = [&](int slot, const void* src, size_t bytes) -> hipError_t {
-    return bytes ? hipMemcpyAsync(ws + off[slot], src, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
-  };
-  hipError_t e = up(kOffRp, t.off_rp.data(), (t.n + 1) * 8);
-  if (e == hipSuccess) e = up(kOffCol, t.off_col.data(), t.off_col.size() * 4);
-  if (e == hipSuccess) e = up(kOffVal, t.off_val.data(), t.off_val.size() * 8);
-  if (e == hipSuccess) e = up(kOffSplit, t.off_split.data(), static_cast<size_t>(t.n) * 8);
-  if (kPanelRows > kPanel) {
-    if (e == hipSuccess) e = up(kInRp, t.in_rp.data(), (t.n + 1) * 8);
-    if (e == hipSuccess) e = up(kInSplit, t.in_split.data(), static_cast<size_t>(t.n) * 8);
-    if (e == hipSuccess) e = up(kInCol, t.in_col.data(), t.in_col.size() * 4);
-    if (e == hipSuccess) e = up(kInVal, t.in_val.data(), t.in_val.size() * 8);
-  }
-  if (e == hipSuccess) e = up(kWinv, t.winv.data(), t.winv.size() * 8);
-  if (e == hipSuccess) e = up(kWoff, t.woff.data(), t.woff.size() * 8);
-  if (e == hipSuccess) e = up(kTaskRec, t.task_rec.data(), t.task_rec.size() * 4);
-  if (e != hipSuccess) return fail(COND_EHIP, std::string("solve upload: ") + hipGetErrorString(e));
-  auto at = [&](int slot) { return ws + off[slot]; };
-  if (t.nslots > 0)
-    launch_fill(t.nslots * kPanelRows * K, reinterpret_cast<double*>(at(kPartials)), kPending, s);
-  out.n = t.n;
-  out.off_rp = reinterpret_cast<const long long*>(at(kOffRp));
-  out.off_col = reinterpret_cast<const int*>(at(kOffCol));
-  out.off_val = reinterpret_cast<const double*>(at(kOffVal));
-  out.off_split = reinterpret_cast<const long long*>(at(kOffSplit));
-  out.in_rp = reinterpret_cast<const long long*>(at(kInRp));
-  out.in_split = reinterpret_cast<const long long*>(at(kInSplit));
-  out.in_col = reinterpret_cast<const int*>(at(kInCol));
-  out.in_val = reinterpret_cast<const double*>(at(kInVal));
-  out.winv = reinterpret_cast<const double*>(at(kWinv));
-  out.woff = reinterpret_cast<const long long*>(at(kWoff));
-  out.partials = reinterpret_cast<double*>(at(kPartials));
-  out.task_rec = reinterpret_cast<const int*>(at(kTaskRec));
-  out.ntasks = static_cast<int>(t.task_panel.size());
-  return COND_OK;
+  o[kTaskRp] = L.take(t.task_rp.size() * 8);
+  o[kTaskSp] = L.take(t.task_sp.size() * 8);
+  o[kTaskGroup] = L.take(t.task_group.size() * 4);
 }
 
 }  // namespace condest

@@ -1,17 +1,15 @@
 // Panel schedules of the sparse triangular solves (Algorithm 2's four
-// solves with the LU factors): host planning, the device layout of one
-// solve's arrays, and their upload. Shared by the single-matrix plan and the
-// batch.
+// solves with the LU factors): host planning and the device layout of one
+// solve's arrays (plain C++; the upload is in panels_upload.hpp). Shared by
+// the single-matrix plan and the batch.
 #pragma once
-
-#include <hip/hip_runtime.h>
 
 #include <cstddef>
 #include <cstdint>
 #include <vector>
 
 #include "internal.hpp"
-#include "kernels.hpp"
+#include "solve_consts.hpp"
 
 namespace condest {
 
@@ -29,7 +27,7 @@ struct Layout {
 // Device arrays of one solve's panel structure (offsets into the workspace).
 enum TriSlot {
   kOffRp, kOffCol, kOffVal, kOffSplit, kInRp, kInSplit, kInCol, kInVal,
-  kPartials, kWinv, kWoff, kTaskRec, kTriSlots
+  kPartials, kWinv, kWoff, kTaskRec, kTaskRp, kTaskSp, kTaskGroup, kTriSlots
 };
 
 // A strictly lower-triangular factor in solve order, cut into panels of at
@@ -46,7 +44,15 @@ struct PanelCsr {
   std::vector<int32_t> panel_split, panel_slot;  // slices per panel, first slot of a split panel
   std::vector<int32_t> task_panel, task_kind;    // tasks in dependency-level order
   std::vector<int32_t> task_level;               // dependency level of each task's panel
-  std::vector<int32_t> task_rec;  // per task: panel, kind, first row, rows, slices, slot, 0, 0
+  std::vector<int32_t> task_group;  // joined schedules: the id of the block each task belongs to
+  // per task: panel, kind, first row, rows, slices, first slot, and the
+  // offset of its panel's inverse in winv as two 32-bit halves (low, high)
+  std::vector<int32_t> task_rec;
+  // per task, indexed by ticket alone: the off-panel row pointers of its
+  // panel's rows (kPanelRows + 1 values, the last repeated past the panel's
+  // end) and their split points (kPanelRows values, 0 past the end), so a
+  // block loads them together with the record instead of after it
+  std::vector<int64_t> task_rp, task_sp;
   // inverse of each sub-panel's triangle, lower rows packed; panel p's
   // sub-panel j at winv[woff[p] + j * kTriPacked]
   std::vector<double> winv;
@@ -61,9 +67,12 @@ PanelCsr split_panels(const HostCsr& t);
 // schedule of the block whose first row (in solve order) is offsets[k], the
 // blocks in increasing offset order, contiguous. Panels, slots and inverses
 // are concatenated; the tasks of all blocks are merged by dependency level
-// (then block, then their own order), so the blocks' levels overlap.
-PanelCsr merge_panels(const std::vector<const PanelCsr*>& parts, const std::vector<int64_t>& offsets);
-// The inverse of every sub-panel's triangle with diagonal diag (nullptr: unit).
+// (then block, then their own order), so the blocks' levels overlap; each
+// task records groups[k] of its block.
+PanelCsr merge_panels(const std::vector<const PanelCsr*>& parts, const std::vector<int64_t>& offsets,
+                      const std::vector<int32_t>& groups);
+// The inverse of every sub-panel's triangle with diagonal diag (nullptr: unit);
+// completes the task records (inverse offsets, row pointers).
 void invert_panels(PanelCsr& s, const double* diag);
 // Row i -> n-1-i and column j -> n-1-j: an upper factor becomes lower.
 HostCsr reverse_order(const HostCsr& u);
@@ -76,7 +85,5 @@ bool replay_solve(const PanelCsr& t, const int32_t* gather, const double* in, do
 // Workspace offsets of one solve's arrays for K right-hand sides (the slice
 // partial slots hold K values per row).
 void tri_layout(const PanelCsr& t, int K, Layout& L, size_t* off);
-// Uploads them on `s` at ws + off[...], arms the partial slots, fills `out`.
-int tri_upload(char* ws, const size_t* off, const PanelCsr& t, int K, hipStream_t s, DevTri& out);
 
 }  // namespace condest

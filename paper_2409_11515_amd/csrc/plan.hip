@@ -18,6 +18,7 @@
 #include "bounds.hpp"
 #include "kernels.hpp"
 #include "panels.hpp"
+#include "panels_upload.hpp"
 
 using namespace condest;
 
@@ -95,6 +96,10 @@ struct cond_plan {
   double *dcol = nullptr, *dinv = nullptr, *dz = nullptr;
   bool has_zero_col = false;
   bool scale_ready = false;
+  // after a timed-out wait a slice may publish into a slot its finish step
+  // already re-armed: every slot is re-armed before the next solve
+  bool rearm_slots = false;
+  bool inject_timeout = false;  // test hook: the next solve starts timed out
   double *parts_x = nullptr, *parts_y = nullptr, *parts_xd = nullptr, *parts_xx = nullptr;
   RunState* st = nullptr;
   RunState* st_free = nullptr;
@@ -417,6 +422,17 @@ int ensure_scaling(cond_plan* p) {
   return COND_OK;
 }
 
+// Re-arms every slice partial slot of the four solves (kPending) when the
+// previous solve on this plan timed out.
+void rearm_after_timeout(cond_plan* p) {
+  if (!p->rearm_slots || !p->want_min) return;
+  const PanelCsr* tris[4] = {&p->pL, &p->pU, &p->pUt, &p->pLt};
+  const DevTri* devs[4] = {&p->dL, &p->dU, &p->dUt, &p->dLt};
+  for (int f = 0; f < 4; ++f)
+    if (tris[f]->nslots > 0) launch_fill(tris[f]->nslots * kPanelRows, devs[f]->partials, kPending, p->stream);
+  p->rearm_slots = false;
+}
+
 struct RouteResult {
   double sigma = 0.0;
   long long iters = 0;
@@ -430,12 +446,18 @@ int run_route(cond_plan* p, int route, const cond_opts_t& o, const double* x0, d
   AdamParams ap = params_of(o);
   ap.minimise = route == 2 ? 1 : 0;
   const bool scaled = o.scaling == COND_SCALE_COL;
+  const bool inject = route == 1 && p->inject_timeout;
+  if (route == 1) {
+    rearm_after_timeout(p);
+    p->inject_timeout = false;
+  }
   const long long total = o.max_iter + 1;  // the last pass only evaluates x_T
   if (o.profile) {
     // eager launches with an event pair around each kernel; poll every iteration
     CHK(hipEventRecord(p->ev_start, p->stream));
     launch_init(p->n, x0, p->x, p->m, p->v, p->parts_xx, p->grid, p->st, o.alpha, ap.minimise,
                 p->stream);
+    if (inject) launch_set_int(&p->st->abort_wait, 1, p->stream);
     CHK(hipGetLastError());
     p->profiling = true;
     int st = COND_OK;
@@ -460,6 +482,7 @@ int run_route(cond_plan* p, int route, const cond_opts_t& o, const double* x0, d
     CHK(hipEventRecord(p->ev_start, p->stream));
     launch_init(p->n, x0, p->x, p->m, p->v, p->parts_xx, p->grid, p->st, o.alpha, ap.minimise,
                 p->stream);
+    if (inject) launch_set_int(&p->st->abort_wait, 1, p->stream);
     CHK(hipGetLastError());
     if ((st = replay_until_stop(p, exec, chunk, total))) return st;
   }
@@ -473,6 +496,7 @@ int run_route(cond_plan* p, int route, const cond_opts_t& o, const double* x0, d
   rr.sigma = s.stop_req && s.done ? s.best : s.best_next;
   rr.iters = s.iters;
   rr.status = s.abort_wait ? COND_ETIMEOUT : s.status;
+  if (s.abort_wait) p->rearm_slots = true;
   rr.flags = s.flags;
   rr.ms = ms;
   return COND_OK;
@@ -785,7 +809,10 @@ int cond_plan_inverse_apply(cond_plan_t* p, const double* x, double* r, double* 
   int st0 = join_user_stream(p);
   if (st0) return st0;
   hipStream_t st = p->stream;
+  rearm_after_timeout(p);
   CHK(hipMemsetAsync(p->st_free, 0, sizeof(RunState), st));
+  if (p->inject_timeout) launch_set_int(&p->st_free->abort_wait, 1, st);
+  p->inject_timeout = false;
   launch_zero_u32(p->tickets, 4, st);
   launch_fill(p->n, p->c, kPending, st);
   launch_fill(p->n, p->z, kPending, st);
@@ -799,7 +826,17 @@ int cond_plan_inverse_apply(cond_plan_t* p, const double* x, double* r, double* 
   RunState hs;
   CHK(hipMemcpyAsync(&hs, p->st_free, sizeof(RunState), hipMemcpyDeviceToHost, st));
   CHK(hipStreamSynchronize(st));
-  if (hs.abort_wait) return fail(COND_ETIMEOUT, "triangular-solve wait timed out");
+  if (hs.abort_wait) {
+    p->rearm_slots = true;
+    return fail(COND_ETIMEOUT, "triangular-solve wait timed out");
+  }
+  return COND_OK;
+}
+
+int cond_plan_inject_timeout(cond_plan_t* p) {
+  if (!p) return fail(COND_EINVAL, "null plan");
+  if (!p->want_min) return fail(COND_EINVAL, "the plan has no sigma_min route");
+  p->inject_timeout = true;
   return COND_OK;
 }
 

@@ -274,3 +274,34 @@ def test_n_equals_one(torch_cuda):
     r = p.run(_dev(torch, np.array([2.0])), max_iter=5)
     p.close()
     assert r["sigma_max"] == 3.5 and r["sigma_min"] == 3.5 and r["kappa"] == 1.0
+
+
+def test_timeout_path_then_recovery(torch_cuda):
+    """A solve that starts timed out (forced from the host: every solve kernel
+    exits at once) reports COND_ETIMEOUT; the next run on the same plan
+    re-arms the solves' slots and gives exactly what a fresh plan gives."""
+    import paper_2409_11515_amd as pa
+
+    torch = torch_cuda
+    a = hydromech2d(40, seed=3)  # large enough for sliced panels
+    x0 = _dev(torch, start_vector(a.n, 8))
+    ref = _plan(a)
+    want = ref.run(x0, max_iter=300)
+    ref.close()
+    p = _plan(a)
+    p.inject_timeout()
+    with pytest.raises(pa.CondError) as e:
+        p.run(x0, max_iter=300)
+    assert e.value.status == pa._binding.COND_ETIMEOUT
+    got = p.run(x0, max_iter=300)
+    assert got["kappa"] == want["kappa"] and got["iters_min"] == want["iters_min"]
+    p.inject_timeout()
+    with pytest.raises(pa.CondError) as e:
+        p.inverse_apply(x0)
+    assert e.value.status == pa._binding.COND_ETIMEOUT
+    r1, s1 = p.inverse_apply(x0)
+    q = _plan(a)
+    r2, s2 = q.inverse_apply(x0)
+    q.close()
+    p.close()
+    assert torch.equal(r1, r2) and torch.equal(s1, s2)
