@@ -215,9 +215,29 @@ def bench_warm(w, args):
                      "unit": "TFLOP/s", "frac": flops / (fwd * 1e-3) / 1e12 / 2500.0,
                      "traffic": None, "kernel": "cnn forward (prep + 4 convs + output)"},
         "label_s": label_s, "train_s": train_s, "loss": [hist[0], hist[-1]],
+        "criterion": warm_criterion(rows, args.ref_iters),
         "tests": rows,
     }
     print(json.dumps(out), flush=True)
+
+
+def warm_criterion(rows, ref_iters):
+    """The warm-start criterion fixed before the evaluation: (1) the median
+    over systems of the ratio of updates to 1e-3 of the best value found
+    (predicted start / random start) and the share of systems where the
+    predicted start is ahead; (2) the mean sigma_min time of the whole
+    warm-started estimate over the plain run's; it pays iff (2) <= 1 with
+    both estimates within 1e-3 of the best value found."""
+    def upd(r, k):
+        v = r[f"updates_to_1e3_{k}"]
+        return v if v is not None else ref_iters + 1
+
+    ratios = np.array([upd(r, "warm") / upd(r, "plain") for r in rows])
+    t_ratio = float(np.mean([r["warm_ms"] for r in rows]) / np.mean([r["cold_ms"] for r in rows]))
+    accurate = all(r["err_plain"] <= 1e-3 and r["err_warm"] <= 1e-3 for r in rows)
+    return {"systems": len(rows), "median_update_ratio": float(np.median(ratios)),
+            "share_ahead": float(np.mean(ratios < 1.0)), "time_ratio_warm_over_plain": t_ratio,
+            "both_within_1e-3": accurate, "pays": bool(t_ratio <= 1.0 and accurate)}
 
 
 def bench_batch(w, args):
@@ -388,9 +408,9 @@ def make_matrix(w):
 
 def _source_hash(kind):
     """SHA-256 of the code a kernel family's counters in profiles/pmc_traffic.json
-    were taken on: for "trsv" the triangular-solve section of kernels.hip and
-    the panel schedule in plan.hip, for "spmv" the streaming SpMV section of
-    kernels.hip and the row tiles in plan.hip."""
+    were taken on: for "trsv" the single-side triangular-solve section of
+    kernels.hip and the panel schedule in panels.cpp, for "spmv" the streaming
+    SpMV section of kernels.hip and the row tiles in plan.hip."""
     import hashlib
 
     csrc = os.path.join(ROOT, "paper_2409_11515_amd", "csrc")

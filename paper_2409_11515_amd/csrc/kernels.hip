@@ -771,8 +771,12 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_multi_k(TrsvArgs t, const dou
     __syncthreads();
     const unsigned T = task_sh;
     if (T >= static_cast<unsigned>(t.ntasks)) break;
-    // a block (matrix) whose starts have all stopped: nothing reads its values
+    // a block (matrix) whose starts have all stopped: nothing reads its
+    // values, so the rest of its run of tasks at this level is skipped at
+    // once (the counter jumps past it; tickets already handed out inside the
+    // run are skipped by their holders the same way)
     if (group_live && !group_live[t.task_group[T]]) {
+      if (threadIdx.x == 0) atomicMax(ticket, static_cast<unsigned>(t.task_seg_end[T]));
       __syncthreads();  // task_sh is reused
       continue;
     }

@@ -116,8 +116,10 @@ struct DevTri {
   // padded) and their split points (kPanelRows values), indexed by ticket
   const long long* task_rp = nullptr;
   const long long* task_sp = nullptr;
-  // joined schedules (a batch): the block (matrix) of each task, or null
+  // joined schedules (a batch): the block (matrix) of each task, and one
+  // past the last task of its run of same-block same-level tasks; or null
   const int* task_group = nullptr;
+  const int* task_seg_end = nullptr;
 };
 using TrsvArgs = DevTri;
 

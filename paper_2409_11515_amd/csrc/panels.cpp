@@ -275,6 +275,12 @@ PanelCsr merge_panels(const std::vector<const PanelCsr*>& parts, const std::vect
                             m.panel_split[P], m.panel_slot[P], 0, 0};
     m.task_rec.insert(m.task_rec.end(), rec, rec + 8);
   }
+  m.task_seg_end.assign(refs.size(), 0);
+  for (size_t q = refs.size(); q-- > 0;) {
+    const bool last = q + 1 == refs.size() || refs[q + 1].level != refs[q].level ||
+                      refs[q + 1].part != refs[q].part;
+    m.task_seg_end[q] = last ? static_cast<int32_t>(q + 1) : m.task_seg_end[q + 1];
+  }
   finish_records(m);
   return m;
 }
@@ -439,6 +445,7 @@ void tri_layout(const PanelCsr& t, int K, Layout& L, size_t* o) {
   o[kTaskRp] = L.take(t.task_rp.size() * 8);
   o[kTaskSp] = L.take(t.task_sp.size() * 8);
   o[kTaskGroup] = L.take(t.task_group.size() * 4);
+  o[kTaskSegEnd] = L.take(t.task_seg_end.size() * 4);
 }
 
 }  // namespace condest

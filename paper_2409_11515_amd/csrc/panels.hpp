@@ -27,7 +27,7 @@ struct Layout {
 // Device arrays of one solve's panel structure (offsets into the workspace).
 enum TriSlot {
   kOffRp, kOffCol, kOffVal, kOffSplit, kInRp, kInSplit, kInCol, kInVal,
-  kPartials, kWinv, kWoff, kTaskRec, kTaskRp, kTaskSp, kTaskGroup, kTriSlots
+  kPartials, kWinv, kWoff, kTaskRec, kTaskRp, kTaskSp, kTaskGroup, kTaskSegEnd, kTriSlots
 };
 
 // A strictly lower-triangular factor in solve order, cut into panels of at
@@ -45,6 +45,9 @@ struct PanelCsr {
   std::vector<int32_t> task_panel, task_kind;    // tasks in dependency-level order
   std::vector<int32_t> task_level;               // dependency level of each task's panel
   std::vector<int32_t> task_group;  // joined schedules: the id of the block each task belongs to
+  // joined schedules: one past the last task of the run of consecutive tasks
+  // of the same block and level (all of a dead block's run is skipped at once)
+  std::vector<int32_t> task_seg_end;
   // per task: panel, kind, first row, rows, slices, first slot, and the
   // offset of its panel's inverse in winv as two 32-bit halves (low, high)
   std::vector<int32_t> task_rec;

@@ -198,6 +198,12 @@ int main() {
       const int64_t lo = reversed ? total - row0[g + 1] : row0[g];
       const int64_t hi = reversed ? total - row0[g] : row0[g + 1];
       EXPECT(row >= lo && row < hi, "task group");
+      // the run of same-block same-level tasks ends at task_seg_end
+      const int32_t e = joined.t[f].task_seg_end[q];
+      EXPECT(e > static_cast<int32_t>(q) && e <= static_cast<int32_t>(joined.t[f].task_panel.size()), "seg end range");
+      for (int32_t u = static_cast<int32_t>(q); u < e; ++u)
+        EXPECT(joined.t[f].task_group[u] == g && joined.t[f].task_level[u] == joined.t[f].task_level[q],
+               "seg end run");
     }
   }
   joined.row_perm.resize(total);

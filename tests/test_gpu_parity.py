@@ -305,3 +305,21 @@ def test_timeout_path_then_recovery(torch_cuda):
     q.close()
     p.close()
     assert torch.equal(r1, r2) and torch.equal(s1, s2)
+
+
+def test_one_shot_estimate_matches_plan_and_oracle(torch_cuda):
+    """cond_estimate (create + bind with library memory + run + destroy)
+    gives exactly what a plan on torch memory gives, and the oracle's kappa."""
+    import paper_2409_11515_amd as pa
+
+    torch = torch_cuda
+    a = hydromech2d(19, seed=7)
+    x0 = _dev(torch, start_vector(a.n, 5))
+    kw = dict(max_iter=3000, stop_rtol=1e-9, stop_window=50)
+    one = pa.estimate_cond(a.n, a.rowptr, a.col, a.val, x0, **kw)
+    p = _plan(a)
+    ref = p.run(x0, **kw)
+    p.close()
+    assert one["kappa"] == ref["kappa"] and one["iters_min"] == ref["iters_min"]
+    o = oracle_estimate(a.n, a.rowptr, a.col, a.val, start_vector(a.n, 5), opts=PAOptions(**kw))
+    assert one["kappa"] == pytest.approx(o["kappa"], rel=1e-3)
