@@ -122,11 +122,12 @@ def bench_warm(w, args):
     rows = []
     fwd_ms = []
     with ThreadPoolExecutor(max_workers=min(8, args.test_count)) as ex:
-        futs = [ex.submit(build, s, side) for s in range(20000, 20000 + args.test_count)]
+        first = 20000 + args.test_first
+        futs = [ex.submit(build, s, side) for s in range(first, first + args.test_count)]
         for i, fu in enumerate(futs):
             a, f, plan = fu.result()
             plan.bind()
-            seed = 20000 + i
+            seed = first + i
             xr = torch.as_tensor(start_vector(a.n, seed + 7), device="cuda")
             ft = torch.as_tensor(f[None], device="cuda").contiguous()
             ws.predict(ft)  # first call warms the kernels
@@ -191,7 +192,8 @@ def bench_warm(w, args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f64 (network bf16/f32)",
         "data": "synthetic",
         "config": {"workload": f"c5warm: held-out {side}x{side} hydro-mechanical systems "
-                               f"(seeds 20000+), network trained on {train_desc} systems",
+                               f"(seeds {first}-{first + args.test_count - 1}), network trained "
+                               f"on {train_desc} systems",
                    "epochs": args.epochs, "stop_rtol": args.stop_rtol,
                    "stop_window": args.stop_window, "parallelism": "single GPU"},
         "plain_s": float(np.mean(smax_ms + cold_ms)) / 1e3,
@@ -551,6 +553,8 @@ def main():
     ap.add_argument("--train-scale", type=float, default=1.0,
                     help="c5warm: multiplies the training-set sizes")
     ap.add_argument("--test-count", type=int, default=8, help="c5warm: held-out matrices")
+    ap.add_argument("--test-first", type=int, default=0,
+                    help="c5warm: index of the first held-out matrix (seed 20000 + index)")
     ap.add_argument("--epochs", type=int, default=60, help="c5warm: training epochs")
     ap.add_argument("--params-in", default=None, help="c5warm: trained parameters (.npy), no training")
     ap.add_argument("--params-out", default=None, help="c5warm: save the trained parameters (.npy)")
