@@ -158,15 +158,16 @@ void enqueue_batch_min_iteration(cond_batch* b, const BatchArgs& a, const AdamPa
   // L^T wv = h, w = P^T wv
   const int* live = a.mat_live;
   launch_trsv_multi(K, b->dL, a.x, reinterpret_cast<const int*>(b->ws + b->o.row_perm), a.c,
-                    nullptr, nullptr, a.tickets + 0, stop, abort, live, s);
+                    nullptr, nullptr, a.tickets, stop, abort, live, s);
   const int* rev = reinterpret_cast<const int*>(b->ws + b->o.rev);
-  launch_trsv_multi(K, b->dU, a.c, rev, a.z, nullptr, nullptr, a.tickets + 1, stop, abort, live, s);
+  launch_trsv_multi(K, b->dU, a.c, rev, a.z, nullptr, nullptr, tix(a.tickets, 1), stop, abort, live,
+                    s);
   batch_launch_sumsq_rev(a, b->grid, s);
   batch_launch_reduce(a, 1, p, s);
-  launch_trsv_multi(K, b->dUt, a.z, rev, a.h, nullptr, nullptr, a.tickets + 2, stop, abort, live, s);
-  launch_trsv_multi(K, b->dLt, a.h, rev, a.wv, a.w,
-                    reinterpret_cast<const int*>(b->ws + b->o.scat_s), a.tickets + 3, stop, abort, live,
+  launch_trsv_multi(K, b->dUt, a.z, rev, a.h, nullptr, nullptr, tix(a.tickets, 2), stop, abort, live,
                     s);
+  launch_trsv_multi(K, b->dLt, a.h, rev, a.wv, a.w, reinterpret_cast<const int*>(b->ws + b->o.scat_s),
+                    tix(a.tickets, 3), stop, abort, live, s);
   batch_launch_pass1(a, p, b->grid, s);
   batch_launch_reduce(a, 2, p, s);
   batch_launch_pass2(a, p, b->grid, s);
@@ -389,7 +390,7 @@ int cond_batch_create(const cond_csr_t* As, int32_t count, const cond_opts_t* o,
     b->o.rev = L.take(n * 4);
     b->o.scat_s = L.take(n * 4);
     for (int k = 0; k < 4; ++k) b->o.svec[k] = L.take(n * K * 8);
-    b->o.tickets = L.take(64);
+    b->o.tickets = L.take(4 * kSolveTickets * sizeof(unsigned));  // four solves' counters
     off = L.off;
   }
   b->need = off;
@@ -485,7 +486,7 @@ int cond_batch_bind(cond_batch_t* b, void* workspace, size_t bytes, void* stream
     double** sv[4] = {&a.c, &a.z, &a.h, &a.wv};
     for (int k = 0; k < 4; ++k) *sv[k] = reinterpret_cast<double*>(b->ws + b->o.svec[k]);
     a.tickets = reinterpret_cast<unsigned*>(b->ws + b->o.tickets);
-    BCHK(hipMemsetAsync(a.tickets, 0, 64, b->stream));
+    BCHK(hipMemsetAsync(a.tickets, 0, 4 * kSolveTickets * sizeof(unsigned), b->stream));
   }
   BCHK(hipMemsetAsync(b->ws + b->o.vec[0], 0, b->nrows * kBatchK * 8, b->stream));
   // every pair running: the autotuner's products cover every tile

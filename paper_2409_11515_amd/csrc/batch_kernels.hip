@@ -23,6 +23,7 @@ namespace condest {
 namespace {
 
 constexpr int kB = 256;
+constexpr int kElemBatch = 4;  // elements per thread in flight in the element kernels
 
 __device__ __forceinline__ double wsum(double v) {
 #pragma unroll
@@ -75,16 +76,22 @@ struct LiveTiles {
 };
 
 // Per-tile partial sums of K values, lane k of each 8-lane group owning start
-// k (K == 8). Reduces the block's per-start accumulators into slot rows.
+// k (K == 8). The lanes of one start inside a wave are added by a fixed
+// butterfly, then the block's waves in wave order: the same order on every
+// run.
 template <int K>
 __device__ __forceinline__ void tile_partials(double acc, int tile, double* parts) {
-  // lanes with the same (lane % K) hold the same start: add them up
-  __shared__ double red[kB];
-  red[threadIdx.x] = acc;
+  static_assert(K == 8, "one start per lane of an 8-lane group");
+  __shared__ double red[(kB / 64) * K];
+#pragma unroll
+  for (int off = K; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
+  const int lane = threadIdx.x & 63;
+  if (lane < K) red[(threadIdx.x >> 6) * K + lane] = acc;
   __syncthreads();
   if (threadIdx.x < K) {
-    double s = 0.0;
-    for (int t = threadIdx.x; t < kB; t += K) s += red[t];
+    double s = red[threadIdx.x];
+#pragma unroll
+    for (int w = 1; w < kB / 64; ++w) s += red[w * K + threadIdx.x];
     parts[static_cast<long long>(tile) * K + threadIdx.x] = s;
   }
   __syncthreads();
@@ -256,10 +263,23 @@ __global__ __launch_bounds__(kB) void b_normalise_k(BatchArgs a) {
     double acc = 0.0;
     if (!q.stopped) {
       const double nrm = q.nrm;
-      for (long long e = r0 * K + threadIdx.x; e < r1 * K; e += kB) {
-        const double xi = a.x[e] / nrm;
-        a.x[e] = xi;
-        acc += xi * xi;
+      const long long e1 = r1 * K;
+      for (long long e0 = r0 * K + threadIdx.x; e0 < e1; e0 += kElemBatch * kB) {
+        double xs[kElemBatch];
+#pragma unroll
+        for (int u = 0; u < kElemBatch; ++u) {
+          const long long e = e0 + u * kB;
+          xs[u] = e < e1 ? a.x[e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kElemBatch; ++u) {
+          const long long e = e0 + u * kB;
+          if (e < e1) {
+            const double xi = xs[u] / nrm;
+            a.x[e] = xi;
+            acc += xi * xi;
+          }
+        }
       }
     }
     tile_partials<K>(acc, static_cast<int>(t), a.parts_x);
@@ -271,10 +291,14 @@ __global__ __launch_bounds__(kB) void b_normalise_k(BatchArgs a) {
 // 32-row chunk and start t % K and walks that row: the K threads of a row
 // read the same column index and value (one transaction for all of them)
 // and K contiguous entries of X (64 bytes), so one read of the matrix serves
-// all starts, with no staging and no barrier inside a tile. Starts that have
-// stopped are skipped, and a tile whose matrix has no running start is
-// skipped entirely.
+// all starts, with no staging and no barrier inside a tile. A row's entries
+// are taken kRowBatch at a time, all of their loads issued before the first
+// product (a row of the stencil matrices fits in one or two such batches),
+// and the next row's pointers are loaded while this row is summed. Starts
+// that have stopped are skipped, and a tile whose matrix has no running
+// start is skipped entirely.
 constexpr int kChunkRowsB = kB / 8;  // 32 rows x 8 starts
+constexpr int kRowBatch = 8;
 
 template <int K>
 __global__ __launch_bounds__(kB) void b_spmm_k(BatchArgs a, const int* __restrict__ rowptr,
@@ -293,25 +317,32 @@ __global__ __launch_bounds__(kB) void b_spmm_k(BatchArgs a, const int* __restric
     const long long r0 = a.tiles[t], r1 = a.tiles[t + 1];
     double sq = 0.0;
     if (mine) {
-      for (long long r = r0 + rl; r < r1; r += kChunkRowsB) {
-        const int p0 = rowptr[r], p1 = rowptr[r + 1];
+      long long r = r0 + rl;
+      int p0 = r < r1 ? rowptr[r] : 0, p1 = r < r1 ? rowptr[r + 1] : 0;
+      for (; r < r1; r += kChunkRowsB) {
+        const long long rn = r + kChunkRowsB;
+        const int n0 = rn < r1 ? rowptr[rn] : 0, n1 = rn < r1 ? rowptr[rn + 1] : 0;
         double acc = 0.0;
-        int q = p0;
-        for (; q + 4 <= p1; q += 4) {
-          const int c0 = col[q], c1 = col[q + 1], c2 = col[q + 2], c3 = col[q + 3];
-          const double v0 = val[q], v1 = val[q + 1], v2 = val[q + 2], v3 = val[q + 3];
-          const double x0 = x[static_cast<long long>(c0) * K + k];
-          const double x1 = x[static_cast<long long>(c1) * K + k];
-          const double x2 = x[static_cast<long long>(c2) * K + k];
-          const double x3 = x[static_cast<long long>(c3) * K + k];
-          acc += v0 * x0;
-          acc += v1 * x1;
-          acc += v2 * x2;
-          acc += v3 * x3;
+        for (int b = p0; b < p1; b += kRowBatch) {
+          int c[kRowBatch];
+          double v[kRowBatch], xv[kRowBatch];
+#pragma unroll
+          for (int u = 0; u < kRowBatch; ++u) {
+            const int q = b + u;
+            c[u] = q < p1 ? col[q] : -1;
+            v[u] = q < p1 ? val[q] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < kRowBatch; ++u)
+            xv[u] = c[u] >= 0 ? x[static_cast<long long>(c[u]) * K + k] : 0.0;
+#pragma unroll
+          for (int u = 0; u < kRowBatch; ++u)
+            if (c[u] >= 0) acc += v[u] * xv[u];
         }
-        for (; q < p1; ++q) acc += val[q] * x[static_cast<long long>(col[q]) * K + k];
         y[r * K + k] = acc;
         sq += acc * acc;
+        p0 = n0;
+        p1 = n1;
       }
     }
     if (parts) tile_partials<K>(sq, static_cast<int>(t), parts);
@@ -335,19 +366,37 @@ __global__ __launch_bounds__(kB) void b_pass1_k(BatchArgs a, AdamParams p) {
     if (q.improved && a.xbest)
       for (long long e = r0 * K + threadIdx.x; e < r1 * K; e += kB) a.xbest[e] = a.x[e];
     if (!q.stopped) {
-      const double nx2 = q.nx2, ny2 = q.ny2;
-      for (long long e = r0 * K + threadIdx.x; e < r1 * K; e += kB) {
-        const double xi = a.x[e];
-        const double g = xi / nx2 - a.w[e] / ny2;
-        const double mi = b1 * a.m[e] + (1.0 - b1) * g;
-        const double vi = b2 * a.v[e] + (1.0 - b2) * (g * g);
-        const double mh = mi / (1.0 - b1t);
-        const double vh = vi / (1.0 - b2t);
-        const double di = q.alpha * mh / (sqrt(vh) + p.eps);
-        a.m[e] = mi;
-        a.v[e] = vi;
-        a.d[e] = di;
-        acc += xi * di;
+      const double nx2 = q.nx2, ny2 = q.ny2, alpha = q.alpha;
+      const long long e1 = r1 * K;
+      // kElemBatch elements per thread in flight, each computed as alone and
+      // added in the thread's element order
+      for (long long e0 = r0 * K + threadIdx.x; e0 < e1; e0 += kElemBatch * kB) {
+        double xs[kElemBatch], ws[kElemBatch], ms[kElemBatch], vs[kElemBatch];
+#pragma unroll
+        for (int u = 0; u < kElemBatch; ++u) {
+          const long long e = e0 + u * kB;
+          xs[u] = e < e1 ? a.x[e] : 0.0;
+          ws[u] = e < e1 ? a.w[e] : 0.0;
+          ms[u] = e < e1 ? a.m[e] : 0.0;
+          vs[u] = e < e1 ? a.v[e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kElemBatch; ++u) {
+          const long long e = e0 + u * kB;
+          if (e < e1) {
+            const double xi = xs[u];
+            const double g = xi / nx2 - ws[u] / ny2;
+            const double mi = b1 * ms[u] + (1.0 - b1) * g;
+            const double vi = b2 * vs[u] + (1.0 - b2) * (g * g);
+            const double mh = mi / (1.0 - b1t);
+            const double vh = vi / (1.0 - b2t);
+            const double di = alpha * mh / (sqrt(vh) + p.eps);
+            a.m[e] = mi;
+            a.v[e] = vi;
+            a.d[e] = di;
+            acc += xi * di;
+          }
+        }
       }
     }
     tile_partials<K>(acc, static_cast<int>(t), a.parts_xd);
@@ -368,12 +417,26 @@ __global__ __launch_bounds__(kB) void b_pass2_k(BatchArgs a, AdamParams p) {
     double acc = 0.0;
     if (!q.stopped) {
       const double xd = q.xd;
-      for (long long e = r0 * K + threadIdx.x; e < r1 * K; e += kB) {
-        const double xi = a.x[e];
-        const double dd = a.d[e] - xd * xi;
-        const double xn = xi - dd;
-        a.x[e] = xn;
-        acc += xn * xn;
+      const long long e1 = r1 * K;
+      for (long long e0 = r0 * K + threadIdx.x; e0 < e1; e0 += kElemBatch * kB) {
+        double xs[kElemBatch], ds[kElemBatch];
+#pragma unroll
+        for (int u = 0; u < kElemBatch; ++u) {
+          const long long e = e0 + u * kB;
+          xs[u] = e < e1 ? a.x[e] : 0.0;
+          ds[u] = e < e1 ? a.d[e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kElemBatch; ++u) {
+          const long long e = e0 + u * kB;
+          if (e < e1) {
+            const double xi = xs[u];
+            const double dd = ds[u] - xd * xi;
+            const double xn = xi - dd;
+            a.x[e] = xn;
+            acc += xn * xn;
+          }
+        }
       }
     }
     tile_partials<K>(acc, static_cast<int>(t), a.parts_xx);
@@ -391,7 +454,8 @@ __global__ __launch_bounds__(kB) void b_pass2_k(BatchArgs a, AdamParams p) {
 // Only the rows of matrices with a running start: the solves skip the rest.
 // c and h are in pivot order (tile t's rows), z and wv reversed (its mirror).
 __global__ __launch_bounds__(kB) void b_rearm_k(BatchArgs a) {
-  if (blockIdx.x == 0 && threadIdx.x < 4) a.tickets[threadIdx.x] = 0u;
+  if (blockIdx.x == 0)
+    for (int c = threadIdx.x; c < 4 * kTaskLists; c += kB) a.tickets[c * kTicketStride] = 0u;
   if (a.g->stop_all) return;
   unsigned long long* c = reinterpret_cast<unsigned long long*>(a.c);
   unsigned long long* z = reinterpret_cast<unsigned long long*>(a.z);

@@ -121,7 +121,9 @@ __global__ __launch_bounds__(kBlock) void normalise_k(int n, double* __restrict_
   }
   const double s = block_sum(acc);
   if (threadIdx.x == 0) parts_x[lb] = s;
-  if (blockIdx.x == 0 && threadIdx.x < ntickets) tickets[threadIdx.x] = 0u;
+  // the solves' ticket counters: kTaskLists per solve, kTicketStride apart
+  if (blockIdx.x == 0)
+    for (int c = threadIdx.x; c < ntickets * kTaskLists; c += kBlock) tickets[c * kTicketStride] = 0u;
 }
 
 // ---------------------------------------------------------- spmv (stream)
@@ -274,14 +276,23 @@ __global__ __launch_bounds__(kBlock) void sumsq_k(int n, const double* __restric
 
 // ----------------------------------------------------------------- trsv
 // Sparse lower-triangular solve in solve order (upper factors arrive
-// reversed). Work items ("tasks") are handed out by a ticket counter in the
-// order the host prepared: by dependency level of their panel (at most 64
-// consecutive rows). A task is a whole panel, or -- for a panel with many
-// entries left of it -- one slice of those entries, or the finish step of
-// such a panel. Every task a block waits on was handed out earlier: panels
-// of lower level, or the slices of its own panel; those are finished, or
-// held by resident blocks that only wait on lower levels, so every wait
-// ends.
+// reversed). Work items ("tasks") come in the order the host prepared, by
+// dependency level of their panel (at most 64 consecutive rows). A task is a
+// whole panel, or -- for a panel with many entries left of it -- one slice
+// of those entries, or the finish step of such a panel; it only waits on
+// tasks earlier in that order (panels of lower level, or the slices of its
+// own panel).
+//
+// The tasks are dealt round-robin into kTaskLists lists, each keeping that
+// order, and each list has its own ticket counter: one counter taking every
+// block's atomic would hand out a ticket only every ~12 ns, which for
+// 10^4 tasks is a large part of the whole solve. Every wait ends: of the
+// tasks held by blocks, the earliest in the order waits only on earlier
+// tasks, and each of those is finished or still untaken in its list -- and
+// an untaken one is next in line for that list's blocks, which hold nothing
+// earlier, so they are free to take it (each list has a resident block:
+// the grid is a multiple of kTaskLists and the lowest block ids start
+// first).
 //
 // Off-panel sums: each wave takes 4 rows at once, 16 lanes per row, loads
 // unrolled for memory-level parallelism. A slice task stores its partial
@@ -303,34 +314,50 @@ constexpr int kLanesPerRow = 16;
 
 constexpr unsigned kMaxBackoff = 4u;        // sleep units between polls, at most
 
-__device__ __noinline__ double wait_pending(const double* p, RunState* st) {
-  const unsigned long long* q = reinterpret_cast<const unsigned long long*>(p);
+// Resolves the still-pending values among the U x S gathered slots of one
+// lane (value u * S + k at out[j[u] * S + k], for j[u] >= 0; S > 1 for
+// interleaved sides) together: every pass re-reads all of the
+// pending ones at the coherent level at once, so values that were published
+// at about the same time (the rows of one panel) cost one round trip, not
+// one each. Between passes the lane sleeps, backing off exponentially; after
+// kSleepLimit sleep units it gives up and sets *abort, and a wait that finds
+// *abort set gives up too: its still-pending values read as NaN.
+template <int U, int S = 1>
+__device__ __forceinline__ void resolve_pending(const double* out, const int (&j)[U],
+                                                unsigned long long (&bits)[U * S], int* abort) {
   unsigned slept = 0, backoff = 1, polls = 0;
-  unsigned long long bits;
   for (;;) {
-    bits = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (bits != kPending) break;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int k = 0; k < S; ++k)
+        if (j[u] >= 0 && bits[u * S + k] == kPending)
+          bits[u * S + k] = __hip_atomic_load(
+              reinterpret_cast<const unsigned long long*>(out + static_cast<long long>(j[u]) * S + k),
+              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    bool pend = false;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int k = 0; k < S; ++k) pend = pend || (j[u] >= 0 && bits[u * S + k] == kPending);
+    if (!pend) return;
     if ((++polls & 63u) == 0u) {
-      if (__hip_atomic_load(&st->abort_wait, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-        return __longlong_as_double(0x7FF8000000000000ll);
-      if (slept >= kSleepLimit) {
-        __hip_atomic_store(&st->abort_wait, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        return __longlong_as_double(0x7FF8000000000000ll);
+      bool give_up = __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+      if (!give_up && slept >= kSleepLimit) {
+        __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        give_up = true;
+      }
+      if (give_up) {
+#pragma unroll
+        for (int e = 0; e < U * S; ++e)
+          if (j[e / S] >= 0 && bits[e] == kPending) bits[e] = 0x7FF8000000000000ull;
+        return;
       }
     }
     for (unsigned k = 0; k < backoff; ++k) __builtin_amdgcn_s_sleep(1);
     slept += backoff;
     if (backoff < kMaxBackoff) backoff <<= 1;
   }
-  return __longlong_as_double(static_cast<long long>(bits));
-}
-
-// Cached read of a published slot; a still-pending one is re-read at the
-// coherent level until it is published.
-__device__ __forceinline__ double ready_value(const double* p, RunState* st) {
-  const unsigned long long bits = __hip_atomic_load(
-      reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-  return bits != kPending ? __longlong_as_double(static_cast<long long>(bits)) : wait_pending(p, st);
 }
 
 __device__ __forceinline__ void publish(double* p, double v) {
@@ -362,15 +389,13 @@ __device__ __forceinline__ double row_sum(long long p0, long long p1, int sub,
       bits[u] = j[u] >= 0 ? __hip_atomic_load(reinterpret_cast<const unsigned long long*>(out + j[u]),
                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)
                           : 0ull;
+    bool pend = false;
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      if (j[u] >= 0) {
-        const double xj = bits[u] != kPending
-                              ? __longlong_as_double(static_cast<long long>(bits[u]))
-                              : wait_pending(out + j[u], st);
-        acc += a[u] * xj;
-      }
-    }
+    for (int u = 0; u < kUnroll; ++u) pend = pend || (j[u] >= 0 && bits[u] == kPending);
+    if (pend) resolve_pending<kUnroll>(out, j, bits, &st->abort_wait);
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+      if (j[u] >= 0) acc += a[u] * __longlong_as_double(static_cast<long long>(bits[u]));
   }
 #pragma unroll
   for (int off = kLanesPerRow / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kLanesPerRow);
@@ -415,15 +440,17 @@ __device__ __forceinline__ void row_sums(const long long* p0, const long long* p
                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)
                          : 0ull;
 #pragma unroll
+    for (int j = 0; j < NR; ++j) {
+      bool pend = false;
+#pragma unroll
+      for (int u = 0; u < U; ++u) pend = pend || (jc[j][u] >= 0 && bits[j][u] == kPending);
+      if (pend) resolve_pending<U>(out, jc[j], bits[j], &st->abort_wait);
+    }
+#pragma unroll
     for (int j = 0; j < NR; ++j)
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if (jc[j][u] >= 0) {
-          const double xj = bits[j][u] != kPending
-                                ? __longlong_as_double(static_cast<long long>(bits[j][u]))
-                                : wait_pending(out + jc[j][u], st);
-          acc[j] += a[j][u] * xj;
-        }
+        if (jc[j][u] >= 0) acc[j] += a[j][u] * __longlong_as_double(static_cast<long long>(bits[j][u]));
   }
 #pragma unroll
   for (int j = 0; j < NR; ++j)
@@ -466,15 +493,21 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_k(TrsvArgs t, const double* _
   const int wave = threadIdx.x >> 6;
   const int sub = lane & (kLanesPerRow - 1);
   const int g = wave * (64 / kLanesPerRow) + lane / kLanesPerRow;  // this group's row, 0..63
+  // this block's task list (block b serves list b mod kTaskLists: on the
+  // usual round-robin dispatch, one list per XCD) and its ticket counter
+  const int lst = static_cast<int>(blockIdx.x % kTaskLists);
+  const int l0 = t.list_off[lst];
+  const unsigned lcount = static_cast<unsigned>(t.list_off[lst + 1] - l0);
+  unsigned* const ctr = ticket + lst * kTicketStride;
   for (;;) {
-    if (threadIdx.x == 0) task_sh = atomicAdd(ticket, 1u);
+    if (threadIdx.x == 0) task_sh = atomicAdd(ctr, 1u);
     __syncthreads();
-    const unsigned T = task_sh;
-    if (T >= static_cast<unsigned>(t.ntasks)) break;
+    if (task_sh >= lcount) break;
+    const long long T = l0 + static_cast<long long>(task_sh);  // the task's slot
     // the task's record: one round trip instead of the task list and then
     // the panel's own arrays
-    const int4 ra = reinterpret_cast<const int4*>(t.task_rec)[2 * static_cast<long long>(T)];
-    const int4 rb = reinterpret_cast<const int4*>(t.task_rec)[2 * static_cast<long long>(T) + 1];
+    const int4 ra = reinterpret_cast<const int4*>(t.task_rec)[2 * T];
+    const int4 rb = reinterpret_cast<const int4*>(t.task_rec)[2 * T + 1];
     const int P = ra.x;
     const int kind = ra.y;  // -1 whole panel, 0..S-1 slice, S finish
     const long long lo = ra.z;
@@ -485,8 +518,8 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_k(TrsvArgs t, const double* _
                            (static_cast<long long>(rb.w) << 32);
     // the task's row pointers and split points, loaded by ticket alone (in
     // flight together with the record, not after it)
-    const long long* trp = t.task_rp + static_cast<long long>(T) * (kPanelRows + 1);
-    const long long* tsp = t.task_sp + static_cast<long long>(T) * kPanelRows;
+    const long long* trp = t.task_rp + T * (kPanelRows + 1);
+    const long long* tsp = t.task_sp + T * kPanelRows;
     long long q0[kSubPanels], q1[kSubPanels];  // the group's rows g + 64 j: off-panel ranges
 #pragma unroll
     for (int j = 0; j < kSubPanels; ++j) {
@@ -577,25 +610,22 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_k(TrsvArgs t, const double* _
         if (r < cnt) {
           constexpr int kSlotsPerLane = kMaxSlicesDev / kLanesPerRow;
           unsigned long long bits[kSlotsPerLane];
+          int so[kSlotsPerLane];  // slot offsets from the row's first slot
           unsigned long long* sp = reinterpret_cast<unsigned long long*>(slots) + r;
 #pragma unroll
           for (int u = 0; u < kSlotsPerLane; ++u) {
             const int k = sub + u * kLanesPerRow;
-            bits[u] = k < S ? __hip_atomic_load(sp + static_cast<long long>(k) * kPanelRows,
-                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+            so[u] = k < S ? k * kPanelRows : -1;
+            bits[u] = k < S ? __hip_atomic_load(sp + so[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                             : 0ull;
           }
+          resolve_pending<kSlotsPerLane>(slots + r, so, bits, &st->abort_wait);
 #pragma unroll
-          for (int u = 0; u < kSlotsPerLane; ++u) {
-            const int k = sub + u * kLanesPerRow;
-            if (k < S) {
-              const double* q = slots + static_cast<long long>(k) * kPanelRows + r;
-              acc += bits[u] != kPending ? __longlong_as_double(static_cast<long long>(bits[u]))
-                                         : wait_pending(q, st);
-              __hip_atomic_store(sp + static_cast<long long>(k) * kPanelRows, kPending,
-                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          for (int u = 0; u < kSlotsPerLane; ++u)
+            if (so[u] >= 0) {
+              acc += __longlong_as_double(static_cast<long long>(bits[u]));
+              __hip_atomic_store(sp + so[u], kPending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-          }
         }
 #pragma unroll
         for (int off = kLanesPerRow / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kLanesPerRow);
@@ -662,28 +692,6 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_k(TrsvArgs t, const double* _
 // (every start of the run has stopped); a wait that times out sets *abort.
 static_assert(kPanelRows == kPanel, "the several-sides solve takes one sub-panel per panel");
 
-__device__ __noinline__ double wait_pending_flag(const double* p, int* abort) {
-  const unsigned long long* q = reinterpret_cast<const unsigned long long*>(p);
-  unsigned slept = 0, backoff = 1, polls = 0;
-  unsigned long long bits;
-  for (;;) {
-    bits = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (bits != kPending) break;
-    if ((++polls & 63u) == 0u) {
-      if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-        return __longlong_as_double(0x7FF8000000000000ll);
-      if (slept >= kSleepLimit) {
-        __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        return __longlong_as_double(0x7FF8000000000000ll);
-      }
-    }
-    for (unsigned k = 0; k < backoff; ++k) __builtin_amdgcn_s_sleep(1);
-    slept += backoff;
-    if (backoff < kMaxBackoff) backoff <<= 1;
-  }
-  return __longlong_as_double(static_cast<long long>(bits));
-}
-
 // Off-panel sums of one row over entries [p0, p1) for all K sides at once:
 // lane sub of the row's 16 takes entries sub, sub + 16, ... (the single-side
 // solve's order, so each side's sum is rounded exactly as there), reads the
@@ -716,20 +724,25 @@ __device__ __forceinline__ double row_sum_multi(long long p0, long long p1, int 
 #pragma unroll
       for (int h = 0; h < K / 2; ++h) v[u][h] = j[u] >= 0 ? src[h] : make_double2(0.0, 0.0);
     }
+    // the values still pending, re-read together (see resolve_pending)
+    unsigned long long bits[U * K];
+    bool pend = false;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int h = 0; h < K / 2; ++h) {
+        bits[u * K + 2 * h] = static_cast<unsigned long long>(__double_as_longlong(v[u][h].x));
+        bits[u * K + 2 * h + 1] = static_cast<unsigned long long>(__double_as_longlong(v[u][h].y));
+      }
+#pragma unroll
+    for (int e = 0; e < U * K; ++e) pend = pend || (j[e / K] >= 0 && bits[e] == kPending);
+    if (pend) resolve_pending<U, K>(out, j, bits, abort);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (j[u] < 0) continue;
-      const double* q = out + static_cast<long long>(j[u]) * K;
 #pragma unroll
-      for (int h = 0; h < K / 2; ++h) {
-        double x0 = v[u][h].x, x1 = v[u][h].y;
-        if (static_cast<unsigned long long>(__double_as_longlong(x0)) == kPending)
-          x0 = wait_pending_flag(q + 2 * h, abort);
-        if (static_cast<unsigned long long>(__double_as_longlong(x1)) == kPending)
-          x1 = wait_pending_flag(q + 2 * h + 1, abort);
-        acc[2 * h] += a[u] * x0;
-        acc[2 * h + 1] += a[u] * x1;
-      }
+      for (int k = 0; k < K; ++k)
+        acc[k] += a[u] * __longlong_as_double(static_cast<long long>(bits[u * K + k]));
     }
   }
 #pragma unroll
@@ -766,22 +779,26 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_multi_k(TrsvArgs t, const dou
   const int sub = lane & (kLanesPerRow - 1);
   const int es = sub / K, kk = sub % K;
   const int g = wave * (64 / kLanesPerRow) + lane / kLanesPerRow;  // this group's row, 0..63
+  const int lst = static_cast<int>(blockIdx.x % kTaskLists);  // as in trsv_k
+  const int l0 = t.list_off[lst];
+  const unsigned lcount = static_cast<unsigned>(t.list_off[lst + 1] - l0);
+  unsigned* const ctr = ticket + lst * kTicketStride;
   for (;;) {
-    if (threadIdx.x == 0) task_sh = atomicAdd(ticket, 1u);
+    if (threadIdx.x == 0) task_sh = atomicAdd(ctr, 1u);
     __syncthreads();
-    const unsigned T = task_sh;
-    if (T >= static_cast<unsigned>(t.ntasks)) break;
+    if (task_sh >= lcount) break;
+    const long long T = l0 + static_cast<long long>(task_sh);  // the task's slot
     // a block (matrix) whose starts have all stopped: nothing reads its
-    // values, so the rest of its run of tasks at this level is skipped at
-    // once (the counter jumps past it; tickets already handed out inside the
-    // run are skipped by their holders the same way)
-    if (group_live && !group_live[t.task_group[T]]) {
-      if (threadIdx.x == 0) atomicMax(ticket, static_cast<unsigned>(t.task_seg_end[T]));
+    // values, so the rest of its list's run of tasks at this level is
+    // skipped at once (the counter jumps past it; tickets already handed out
+    // inside the run are skipped by their holders the same way)
+    if (group_live && !group_live[t.slot_group[T]]) {
+      if (threadIdx.x == 0) atomicMax(ctr, static_cast<unsigned>(t.slot_seg_end[T]));
       __syncthreads();  // task_sh is reused
       continue;
     }
-    const int4 ra = reinterpret_cast<const int4*>(t.task_rec)[2 * static_cast<long long>(T)];
-    const int4 rb = reinterpret_cast<const int4*>(t.task_rec)[2 * static_cast<long long>(T) + 1];
+    const int4 ra = reinterpret_cast<const int4*>(t.task_rec)[2 * T];
+    const int4 rb = reinterpret_cast<const int4*>(t.task_rec)[2 * T + 1];
     const int P = ra.x;
     const int kind = ra.y;  // -1 whole panel, 0..S-1 slice, S finish
     const long long lo = ra.z;
@@ -790,8 +807,8 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_multi_k(TrsvArgs t, const dou
     double* slots = t.partials + static_cast<long long>(rb.y) * kPanelRows * K;
     const long long woff = static_cast<long long>(static_cast<unsigned>(rb.z)) |
                            (static_cast<long long>(rb.w) << 32);
-    const long long* trp = t.task_rp + static_cast<long long>(T) * (kPanelRows + 1);
-    const long long* tsp = t.task_sp + static_cast<long long>(T) * kPanelRows;
+    const long long* trp = t.task_rp + T * (kPanelRows + 1);
+    const long long* tsp = t.task_sp + T * kPanelRows;
     const bool row = g < cnt;
     const long long a0 = trp[g], a1 = trp[g + 1], sp = tsp[g];
     long long q0 = row ? a0 : 0, q1 = row ? a1 : 0;
@@ -831,23 +848,21 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_multi_k(TrsvArgs t, const dou
         unsigned long long* sp = reinterpret_cast<unsigned long long*>(slots);
         for (int k0 = es; k0 < S; k0 += EL * 4) {
           unsigned long long bits[4];
+          int so[4];  // slot offsets
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const int k = k0 + u * EL;
-            bits[u] = k < S ? __hip_atomic_load(sp + (static_cast<long long>(k) * kPanelRows + g) * K + kk,
-                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+            so[u] = k < S ? (k * kPanelRows + g) * K + kk : -1;
+            bits[u] = k < S ? __hip_atomic_load(sp + so[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                             : 0ull;
           }
+          resolve_pending<4>(slots, so, bits, abort);
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int k = k0 + u * EL;
-            if (k < S) {
-              const long long at = (static_cast<long long>(k) * kPanelRows + g) * K + kk;
-              acc += bits[u] != kPending ? __longlong_as_double(static_cast<long long>(bits[u]))
-                                         : wait_pending_flag(slots + at, abort);
-              __hip_atomic_store(sp + at, kPending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          for (int u = 0; u < 4; ++u)
+            if (so[u] >= 0) {
+              acc += __longlong_as_double(static_cast<long long>(bits[u]));
+              __hip_atomic_store(sp + so[u], kPending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-          }
         }
       }
 #pragma unroll
@@ -1181,21 +1196,25 @@ void launch_sumsq(int n, const double* z, double* parts, int grid, const RunStat
   sumsq_k<<<grid, kBlock, 0, s>>>(n, z, parts, st);
 }
 
+// Blocks of a solve: a multiple of kTaskLists, so every list has its blocks
+// (block b serves list b mod kTaskLists), at most 512.
+static int trsv_grid(int ntasks) {
+  long long blocks = ntasks < 512 ? ntasks : 512;
+  blocks = (blocks + kTaskLists - 1) / kTaskLists * kTaskLists;
+  return static_cast<int>(blocks < kTaskLists ? kTaskLists : blocks);
+}
+
 void launch_trsv(const DevTri& t, const double* rhs, const int* rhs_perm, double* out,
                  double* scatter, const int* scatter_perm, unsigned* ticket, RunState* st,
                  hipStream_t s) {
-  long long blocks = t.ntasks < 512 ? t.ntasks : 512;
-  if (blocks < 1) blocks = 1;
-  const int g = static_cast<int>(blocks);
+  const int g = trsv_grid(t.ntasks);
   trsv_k<<<g, kTrsvBlock, 0, s>>>(t, rhs, rhs_perm, out, scatter, scatter_perm, ticket, st);
 }
 
 void launch_trsv_multi(int K, const DevTri& t, const double* rhs, const int* rhs_perm, double* out,
                        double* scatter, const int* scatter_perm, unsigned* ticket, const int* stop,
                        int* abort, const int* group_live, hipStream_t s) {
-  long long blocks = t.ntasks < 512 ? t.ntasks : 512;
-  if (blocks < 1) blocks = 1;
-  const int g = static_cast<int>(blocks);
+  const int g = trsv_grid(t.ntasks);
   switch (K) {
     case 2:
       trsv_multi_k<2><<<g, kTrsvBlock, 0, s>>>(t, rhs, rhs_perm, out, scatter, scatter_perm, ticket,

@@ -107,19 +107,23 @@ struct DevTri {
   const long long* woff = nullptr;
   double* partials = nullptr;  // slice partial sums, kPanelRows doubles per slot; kPending when idle
   int ntasks = 0;
-  // per task, in dependency-level order, 8 ints (two 16-byte loads): panel,
-  // kind (-1 whole panel, 0..S-1 slice, S finish), first row, rows, slices
-  // S, first partial-sum slot, offset of the panel's inverse in winv (low
-  // and high 32 bits)
+  // the tasks in kTaskLists lists, each in dependency order and handed out
+  // by its own ticket counter: list l is the slots [list_off[l],
+  // list_off[l+1]); the per-task arrays below are indexed by slot
+  int list_off[kTaskLists + 1] = {};
+  // per slot, 8 ints (two 16-byte loads): panel, kind (-1 whole panel,
+  // 0..S-1 slice, S finish), first row, rows, slices S, first partial-sum
+  // slot, offset of the panel's inverse in winv (low and high 32 bits)
   const int* task_rec = nullptr;
-  // per task: off-panel row pointers of its rows (kPanelRows + 1 values,
-  // padded) and their split points (kPanelRows values), indexed by ticket
+  // per slot: off-panel row pointers of its rows (kPanelRows + 1 values,
+  // padded) and their split points (kPanelRows values)
   const long long* task_rp = nullptr;
   const long long* task_sp = nullptr;
-  // joined schedules (a batch): the block (matrix) of each task, and one
-  // past the last task of its run of same-block same-level tasks; or null
-  const int* task_group = nullptr;
-  const int* task_seg_end = nullptr;
+  // joined schedules (a batch), per slot: the block (matrix), and one past
+  // the end of its list's run of same-block same-level slots, counted from
+  // the list's first slot; or null
+  const int* slot_group = nullptr;
+  const int* slot_seg_end = nullptr;
 };
 using TrsvArgs = DevTri;
 
@@ -127,6 +131,10 @@ int grid_for(int n);  // fixed grid size of the reduction kernels for length n
 
 void launch_init(int n, const double* x0, double* x, double* m, double* v, double* parts_xx,
                  int grid, RunState* st, double alpha0, int minimise, hipStream_t s);
+// The ticket counters of solve k in an area of kSolveTickets per solve.
+inline unsigned* tix(unsigned* base, int k) { return base + k * kSolveTickets; }
+// x <- x / ||x||, partials of x.x; re-arms the `nresets` solve vectors and
+// the ticket counters of `ntickets` solves (an area as above).
 void launch_normalise(int n, double* x, const double* parts_xx, int grid, double* parts_x,
                       RunState* st, double* const* resets, int nresets, unsigned* tickets,
                       int ntickets, hipStream_t s);

@@ -117,21 +117,52 @@ double cut_cost(const HostCsr& t, const std::vector<int32_t>& pstart) {
   return kLevelUs * levels + kTaskUs * static_cast<double>(tasks);
 }
 
-// The parts of each task record that need the inverses' offsets, and the
-// per-task row pointers and split points.
+// The device order of the tasks and everything indexed by it: the tasks are
+// dealt round-robin to kTaskLists lists in dependency order (so each list is
+// in dependency order, and each holds about 1/kTaskLists of every level),
+// then the records, row pointers and split points (and, for joined
+// schedules, the blocks and runs) are laid out list after list. Built from
+// the tasks, panels and inverse offsets alone.
 void finish_records(PanelCsr& s) {
   const size_t ntasks = s.task_panel.size();
+  s.list_off.assign(kTaskLists + 1, 0);
+  for (size_t k = 0; k < ntasks; ++k) ++s.list_off[k % kTaskLists + 1];
+  for (int l = 0; l < kTaskLists; ++l) s.list_off[l + 1] += s.list_off[l];
+  s.task_slot.assign(ntasks, 0);
+  std::vector<int32_t> next(s.list_off.begin(), s.list_off.end() - 1);
+  for (size_t k = 0; k < ntasks; ++k) s.task_slot[k] = next[k % kTaskLists]++;
+  s.task_rec.assign(8 * ntasks, 0);
   s.task_rp.assign(ntasks * (kPanelRows + 1), 0);
   s.task_sp.assign(ntasks * kPanelRows, 0);
   for (size_t k = 0; k < ntasks; ++k) {
+    const size_t q = static_cast<size_t>(s.task_slot[k]);
     const int32_t p = s.task_panel[k];
     const int64_t w = s.woff.empty() ? 0 : s.woff[p];
-    s.task_rec[8 * k + 6] = static_cast<int32_t>(static_cast<uint32_t>(w & 0xffffffffLL));
-    s.task_rec[8 * k + 7] = static_cast<int32_t>(w >> 32);
     const int32_t lo = s.pstart[p], cnt = s.pstart[p + 1] - lo;
+    const int32_t rec[8] = {p, s.task_kind[k], lo, cnt, s.panel_split[p], s.panel_slot[p],
+                            static_cast<int32_t>(static_cast<uint32_t>(w & 0xffffffffLL)),
+                            static_cast<int32_t>(w >> 32)};
+    std::copy(rec, rec + 8, s.task_rec.begin() + 8 * q);
     for (int32_t r = 0; r <= kPanelRows; ++r)
-      s.task_rp[k * (kPanelRows + 1) + r] = s.off_rp[lo + std::min(r, cnt)];
-    for (int32_t r = 0; r < cnt; ++r) s.task_sp[k * kPanelRows + r] = s.off_split[lo + r];
+      s.task_rp[q * (kPanelRows + 1) + r] = s.off_rp[lo + std::min(r, cnt)];
+    for (int32_t r = 0; r < cnt; ++r) s.task_sp[q * kPanelRows + r] = s.off_split[lo + r];
+  }
+  s.slot_group.clear();
+  s.slot_seg_end.clear();
+  if (s.task_group.empty()) return;
+  s.slot_group.assign(ntasks, 0);
+  std::vector<int32_t> level(ntasks, 0);
+  for (size_t k = 0; k < ntasks; ++k) {
+    s.slot_group[s.task_slot[k]] = s.task_group[k];
+    level[s.task_slot[k]] = s.task_level[k];
+  }
+  s.slot_seg_end.assign(ntasks, 0);
+  for (int l = 0; l < kTaskLists; ++l) {
+    const int32_t q0 = s.list_off[l], q1 = s.list_off[l + 1];
+    for (int32_t q = q1; q-- > q0;) {
+      const bool last = q + 1 == q1 || s.slot_group[q + 1] != s.slot_group[q] || level[q + 1] != level[q];
+      s.slot_seg_end[q] = last ? q + 1 - q0 : s.slot_seg_end[q + 1];
+    }
   }
 }
 
@@ -207,13 +238,6 @@ PanelCsr split_panels(const HostCsr& t) {
       s.task_level.push_back(level[p]);
     }
   }
-  s.task_rec.reserve(8 * s.task_panel.size());
-  for (size_t k = 0; k < s.task_panel.size(); ++k) {
-    const int32_t p = s.task_panel[k];
-    const int32_t rec[8] = {p, s.task_kind[k], s.pstart[p], s.pstart[p + 1] - s.pstart[p],
-                            s.panel_split[p], s.panel_slot[p], 0, 0};
-    s.task_rec.insert(s.task_rec.end(), rec, rec + 8);
-  }
   return s;
 }
 
@@ -263,23 +287,12 @@ PanelCsr merge_panels(const std::vector<const PanelCsr*>& parts, const std::vect
     for (size_t t = 0; t < parts[k]->task_panel.size(); ++t)
       refs.push_back({parts[k]->task_level[t], static_cast<int32_t>(k), static_cast<int32_t>(t)});
   std::stable_sort(refs.begin(), refs.end(), [](const Ref& a, const Ref& b) { return a.level < b.level; });
-  m.task_rec.reserve(8 * refs.size());
   for (const Ref& r : refs) {
     const PanelCsr& s = *parts[r.part];
-    const int32_t P = panel0[r.part] + s.task_panel[r.task];
-    m.task_panel.push_back(P);
+    m.task_panel.push_back(panel0[r.part] + s.task_panel[r.task]);
     m.task_kind.push_back(s.task_kind[r.task]);
     m.task_level.push_back(r.level);
     m.task_group.push_back(groups[r.part]);
-    const int32_t rec[8] = {P, s.task_kind[r.task], m.pstart[P], m.pstart[P + 1] - m.pstart[P],
-                            m.panel_split[P], m.panel_slot[P], 0, 0};
-    m.task_rec.insert(m.task_rec.end(), rec, rec + 8);
-  }
-  m.task_seg_end.assign(refs.size(), 0);
-  for (size_t q = refs.size(); q-- > 0;) {
-    const bool last = q + 1 == refs.size() || refs[q + 1].level != refs[q].level ||
-                      refs[q + 1].part != refs[q].part;
-    m.task_seg_end[q] = last ? static_cast<int32_t>(q + 1) : m.task_seg_end[q + 1];
   }
   finish_records(m);
   return m;
@@ -374,14 +387,15 @@ bool replay_solve(const PanelCsr& t, const int32_t* gather, const double* in, do
     }
     return a;
   };
-  const size_t ntasks = t.task_rec.size() / 8;
+  const size_t ntasks = t.task_panel.size();
   for (size_t k = 0; k < ntasks && ok; ++k) {
-    const int32_t* rec = &t.task_rec[8 * k];
+    const size_t q = static_cast<size_t>(t.task_slot[k]);
+    const int32_t* rec = &t.task_rec[8 * q];
     const int32_t kind = rec[1], lo = rec[2], cnt = rec[3], S = rec[4], slot = rec[5];
     const int64_t woff = static_cast<int64_t>(static_cast<uint32_t>(rec[6])) |
                          (static_cast<int64_t>(rec[7]) << 32);
-    const int64_t* trp = &t.task_rp[k * (kPanelRows + 1)];
-    const int64_t* tsp = &t.task_sp[k * kPanelRows];
+    const int64_t* trp = &t.task_rp[q * (kPanelRows + 1)];
+    const int64_t* tsp = &t.task_sp[q * kPanelRows];
     if (kind >= 0 && kind < S) {  // slice
       for (int32_t r = 0; r < cnt; ++r) {
         const int64_t q0 = trp[r], len = tsp[r] - q0;
@@ -444,8 +458,8 @@ void tri_layout(const PanelCsr& t, int K, Layout& L, size_t* o) {
   o[kTaskRec] = L.take(t.task_rec.size() * 4);
   o[kTaskRp] = L.take(t.task_rp.size() * 8);
   o[kTaskSp] = L.take(t.task_sp.size() * 8);
-  o[kTaskGroup] = L.take(t.task_group.size() * 4);
-  o[kTaskSegEnd] = L.take(t.task_seg_end.size() * 4);
+  o[kSlotGroup] = L.take(t.slot_group.size() * 4);
+  o[kSlotSegEnd] = L.take(t.slot_seg_end.size() * 4);
 }
 
 }  // namespace condest

@@ -27,7 +27,7 @@ struct Layout {
 // Device arrays of one solve's panel structure (offsets into the workspace).
 enum TriSlot {
   kOffRp, kOffCol, kOffVal, kOffSplit, kInRp, kInSplit, kInCol, kInVal,
-  kPartials, kWinv, kWoff, kTaskRec, kTaskRp, kTaskSp, kTaskGroup, kTaskSegEnd, kTriSlots
+  kPartials, kWinv, kWoff, kTaskRec, kTaskRp, kTaskSp, kSlotGroup, kSlotSegEnd, kTriSlots
 };
 
 // A strictly lower-triangular factor in solve order, cut into panels of at
@@ -45,17 +45,23 @@ struct PanelCsr {
   std::vector<int32_t> task_panel, task_kind;    // tasks in dependency-level order
   std::vector<int32_t> task_level;               // dependency level of each task's panel
   std::vector<int32_t> task_group;  // joined schedules: the id of the block each task belongs to
-  // joined schedules: one past the last task of the run of consecutive tasks
-  // of the same block and level (all of a dead block's run is skipped at once)
-  std::vector<int32_t> task_seg_end;
-  // per task: panel, kind, first row, rows, slices, first slot, and the
+  // Device order. Task k (in the order above) is dealt to list k mod
+  // kTaskLists; list l is the slots [list_off[l], list_off[l+1]), its tasks
+  // in dependency order, and task k sits at slot task_slot[k]. The arrays
+  // below are indexed by slot.
+  std::vector<int32_t> list_off, task_slot;
+  // per slot: panel, kind, first row, rows, slices, first slot, and the
   // offset of its panel's inverse in winv as two 32-bit halves (low, high)
   std::vector<int32_t> task_rec;
-  // per task, indexed by ticket alone: the off-panel row pointers of its
-  // panel's rows (kPanelRows + 1 values, the last repeated past the panel's
-  // end) and their split points (kPanelRows values, 0 past the end), so a
-  // block loads them together with the record instead of after it
+  // per slot: the off-panel row pointers of its panel's rows (kPanelRows + 1
+  // values, the last repeated past the panel's end) and their split points
+  // (kPanelRows values, 0 past the end), so a block loads them together
+  // with the record instead of after it
   std::vector<int64_t> task_rp, task_sp;
+  // joined schedules, per slot: the block, and one past the end of the run
+  // of consecutive slots of its list with the same block and level, counted
+  // from the list's first slot (a dead block's run is skipped at once)
+  std::vector<int32_t> slot_group, slot_seg_end;
   // inverse of each sub-panel's triangle, lower rows packed; panel p's
   // sub-panel j at winv[woff[p] + j * kTriPacked]
   std::vector<double> winv;
@@ -80,9 +86,9 @@ void invert_panels(PanelCsr& s, const double* diag);
 // Row i -> n-1-i and column j -> n-1-j: an upper factor becomes lower.
 HostCsr reverse_order(const HostCsr& u);
 
-// One solve on the host from the device-ready data, tasks in ticket order
-// (in: right-hand side, gathered through `gather` when given); false when a
-// task would read a value or slot that only a later ticket writes.
+// One solve on the host from the device-ready data, tasks in dependency
+// order (in: right-hand side, gathered through `gather` when given); false
+// when a task would read a value or slot that only a later task writes.
 bool replay_solve(const PanelCsr& t, const int32_t* gather, const double* in, double* out);
 
 // Workspace offsets of one solve's arrays for K right-hand sides (the slice

@@ -163,7 +163,7 @@ void plan_layout(cond_plan* p) {
   for (int k = 0; k < 4; ++k) p->o.parts[k] = L.take(kMaxParts * 8);
   p->o.st = L.take(sizeof(RunState));
   p->o.st_free = L.take(sizeof(RunState));
-  p->o.tickets = L.take(64);
+  p->o.tickets = L.take(4 * kSolveTickets * sizeof(unsigned));  // four solves' counters
   p->need_bytes = L.off;
 }
 
@@ -300,9 +300,9 @@ void enqueue_iteration(cond_plan* p, int route, bool scaled, double* trace, doub
       launch_normalise(n, p->x, p->parts_xx, g, p->parts_x, p->st, resets, 4, p->tickets, 4, s); }
     // r = A^-1 x: L c = P x, U z = c (r = Q z; ||r|| = ||z||); z is kept reversed
     { Prof pr(p, COND_K_TRSV_L, 12.0 * nl + rp + 28.0 * dn);
-      launch_trsv(p->dL, p->x, p->d_row_perm, p->c, nullptr, nullptr, p->tickets + 0, p->st, s); }
+      launch_trsv(p->dL, p->x, p->d_row_perm, p->c, nullptr, nullptr, p->tickets, p->st, s); }
     { Prof pr(p, COND_K_TRSV_U, 12.0 * nu + rp + 36.0 * dn);
-      launch_trsv(p->dU, p->c, p->d_rev, p->z, nullptr, nullptr, p->tickets + 1, p->st, s); }
+      launch_trsv(p->dU, p->c, p->d_rev, p->z, nullptr, nullptr, tix(p->tickets, 1), p->st, s); }
     // scaled: z <- D z (= D r) and c <- D z (the transposed solves' input;
     // c, the L solve's output, is free once the U solve has run)
     { Prof pr(p, COND_K_SUMSQ, scaled ? 32.0 * dn : 8.0 * dn);
@@ -312,10 +312,10 @@ void enqueue_iteration(cond_plan* p, int route, bool scaled, double* trace, doub
         launch_sumsq(n, p->z, p->parts_y, g, p->st, s); }
     // s = A^-T r: U^T h = Q^T r = z, L^T wv = h, s = P^T wv (wv kept reversed)
     { Prof pr(p, COND_K_TRSV_UT, 12.0 * nu + rp + 36.0 * dn);
-      launch_trsv(p->dUt, scaled ? p->c : p->z, p->d_rev, p->h, nullptr, nullptr, p->tickets + 2,
-                  p->st, s); }
+      launch_trsv(p->dUt, scaled ? p->c : p->z, p->d_rev, p->h, nullptr, nullptr,
+                  tix(p->tickets, 2), p->st, s); }
     { Prof pr(p, COND_K_TRSV_LT, 12.0 * nl + rp + 40.0 * dn);
-      launch_trsv(p->dLt, p->h, p->d_rev, p->wv, p->w, p->d_scat_s, p->tickets + 3, p->st, s); }
+      launch_trsv(p->dLt, p->h, p->d_rev, p->wv, p->w, p->d_scat_s, tix(p->tickets, 3), p->st, s); }
   }
   { Prof pr(p, COND_K_ADAM1, 56.0 * dn);
     launch_pass1(n, p->x, p->w, p->m, p->v, p->d, xbest, p->parts_x, p->parts_y, g, p->parts_xd,
@@ -647,7 +647,7 @@ int cond_plan_bind(cond_plan_t* p, void* workspace, size_t bytes, void* stream) 
   p->tickets = at_off<unsigned>(p, p->o.tickets);
   CHK(hipMemsetAsync(p->st, 0, sizeof(RunState), p->stream));
   CHK(hipMemsetAsync(p->st_free, 0, sizeof(RunState), p->stream));
-  CHK(hipMemsetAsync(p->tickets, 0, 64, p->stream));
+  CHK(hipMemsetAsync(p->tickets, 0, 4 * kSolveTickets * sizeof(unsigned), p->stream));
   CHK(hipStreamSynchronize(p->stream));
   p->bound = true;
   return COND_OK;
@@ -813,15 +813,15 @@ int cond_plan_inverse_apply(cond_plan_t* p, const double* x, double* r, double* 
   CHK(hipMemsetAsync(p->st_free, 0, sizeof(RunState), st));
   if (p->inject_timeout) launch_set_int(&p->st_free->abort_wait, 1, st);
   p->inject_timeout = false;
-  launch_zero_u32(p->tickets, 4, st);
+  launch_zero_u32(p->tickets, 4 * kSolveTickets, st);
   launch_fill(p->n, p->c, kPending, st);
   launch_fill(p->n, p->z, kPending, st);
   launch_fill(p->n, p->h, kPending, st);
   launch_fill(p->n, p->wv, kPending, st);
-  launch_trsv(p->dL, x, p->d_row_perm, p->c, nullptr, nullptr, p->tickets + 0, p->st_free, st);
-  launch_trsv(p->dU, p->c, p->d_rev, p->z, r, p->d_scat_r, p->tickets + 1, p->st_free, st);
-  launch_trsv(p->dUt, p->z, p->d_rev, p->h, nullptr, nullptr, p->tickets + 2, p->st_free, st);
-  launch_trsv(p->dLt, p->h, p->d_rev, p->wv, s, p->d_scat_s, p->tickets + 3, p->st_free, st);
+  launch_trsv(p->dL, x, p->d_row_perm, p->c, nullptr, nullptr, p->tickets, p->st_free, st);
+  launch_trsv(p->dU, p->c, p->d_rev, p->z, r, p->d_scat_r, tix(p->tickets, 1), p->st_free, st);
+  launch_trsv(p->dUt, p->z, p->d_rev, p->h, nullptr, nullptr, tix(p->tickets, 2), p->st_free, st);
+  launch_trsv(p->dLt, p->h, p->d_rev, p->wv, s, p->d_scat_s, tix(p->tickets, 3), p->st_free, st);
   CHK(hipGetLastError());
   RunState hs;
   CHK(hipMemcpyAsync(&hs, p->st_free, sizeof(RunState), hipMemcpyDeviceToHost, st));

@@ -88,6 +88,28 @@ double backward_error(const HostCsr& a, bool transpose, const std::vector<double
   return worst;
 }
 
+// The device order: the slots are a permutation of the tasks, the lists
+// partition them, and each list keeps the dependency order (its slots hold
+// increasing task indices), which is what makes every wait of the solve end.
+void check_lists(const PanelCsr& t) {
+  const int32_t ntasks = static_cast<int32_t>(t.task_panel.size());
+  EXPECT(static_cast<int>(t.list_off.size()) == kTaskLists + 1, "list count");
+  EXPECT(t.list_off[0] == 0 && t.list_off[kTaskLists] == ntasks, "lists cover the tasks");
+  std::vector<int32_t> seen(ntasks, 0);
+  std::vector<int32_t> last(kTaskLists, -1);
+  for (int32_t k = 0; k < ntasks; ++k) {
+    const int32_t q = t.task_slot[k];
+    EXPECT(q >= 0 && q < ntasks && !seen[q], "slot permutation");
+    if (q < 0 || q >= ntasks) continue;
+    seen[q] = 1;
+    int l = 0;
+    while (l < kTaskLists && q >= t.list_off[l + 1]) ++l;
+    EXPECT(l < kTaskLists && q > last[l], "list keeps the dependency order");
+    if (l < kTaskLists) last[l] = q;
+    EXPECT(t.task_rec[8 * q] == t.task_panel[k] && t.task_rec[8 * q + 1] == t.task_kind[k], "record at slot");
+  }
+}
+
 struct Schedules {
   PanelCsr t[4];
   std::vector<int32_t> row_perm, col_perm, rev;
@@ -101,12 +123,16 @@ Schedules schedule(const cond_lu& f) {
   for (int32_t k = 0; k < n; ++k) udiag_rev[k] = f.u_diag[n - 1 - k];
   s.t[0] = split_panels(f.l_rows);
   invert_panels(s.t[0], nullptr);
+  check_lists(s.t[0]);
   s.t[1] = split_panels(reverse_order(f.u_rows));
   invert_panels(s.t[1], udiag_rev.data());
+  check_lists(s.t[1]);
   s.t[2] = split_panels(f.u_cols);
   invert_panels(s.t[2], f.u_diag.data());
+  check_lists(s.t[2]);
   s.t[3] = split_panels(reverse_order(f.l_cols));
   invert_panels(s.t[3], nullptr);
+  check_lists(s.t[3]);
   s.row_perm = f.row_perm;
   s.col_perm = f.col_perm;
   s.rev.resize(n);
@@ -191,19 +217,34 @@ int main() {
       groups.push_back(m);
     }
     joined.t[f] = merge_panels(ps, offs, groups);
+    const PanelCsr& J = joined.t[f];
+    check_lists(J);
     // every task carries its block's id
-    for (size_t q = 0; q < joined.t[f].task_panel.size(); ++q) {
-      const int32_t row = joined.t[f].pstart[joined.t[f].task_panel[q]];
-      const int32_t g = joined.t[f].task_group[q];
+    for (size_t q = 0; q < J.task_panel.size(); ++q) {
+      const int32_t row = J.pstart[J.task_panel[q]];
+      const int32_t g = J.task_group[q];
       const int64_t lo = reversed ? total - row0[g + 1] : row0[g];
       const int64_t hi = reversed ? total - row0[g] : row0[g + 1];
       EXPECT(row >= lo && row < hi, "task group");
-      // the run of same-block same-level tasks ends at task_seg_end
-      const int32_t e = joined.t[f].task_seg_end[q];
-      EXPECT(e > static_cast<int32_t>(q) && e <= static_cast<int32_t>(joined.t[f].task_panel.size()), "seg end range");
-      for (int32_t u = static_cast<int32_t>(q); u < e; ++u)
-        EXPECT(joined.t[f].task_group[u] == g && joined.t[f].task_level[u] == joined.t[f].task_level[q],
-               "seg end run");
+      EXPECT(J.slot_group[J.task_slot[q]] == g, "slot group");
+    }
+    // in each list, the run of same-block same-level slots ends at
+    // slot_seg_end (counted from the list's first slot)
+    std::vector<int32_t> slot_task(J.task_panel.size());
+    for (size_t q = 0; q < J.task_panel.size(); ++q) slot_task[J.task_slot[q]] = static_cast<int32_t>(q);
+    for (int l = 0; l < kTaskLists; ++l) {
+      const int32_t q0 = J.list_off[l], q1 = J.list_off[l + 1];
+      for (int32_t q = q0; q < q1; ++q) {
+        const int32_t e = J.slot_seg_end[q];
+        EXPECT(e > q - q0 && e <= q1 - q0, "seg end range");
+        for (int32_t u = q; u < q0 + e; ++u)
+          EXPECT(J.slot_group[u] == J.slot_group[q] &&
+                     J.task_level[slot_task[u]] == J.task_level[slot_task[q]],
+                 "seg end run");
+        EXPECT(q0 + e == q1 || J.slot_group[q0 + e] != J.slot_group[q] ||
+                   J.task_level[slot_task[q0 + e]] != J.task_level[slot_task[q]],
+               "seg end is the run's end");
+      }
     }
   }
   joined.row_perm.resize(total);
