@@ -212,7 +212,7 @@ int batch_factor(cond_batch* b, std::vector<HostCsr>& as, std::vector<HostCsr>& 
   unsigned hw = std::thread::hardware_concurrency();
   const int32_t nthreads = std::max<int32_t>(1, std::min<int32_t>(count, hw ? static_cast<int32_t>(hw) : 4));
   auto sched = [](const HostCsr& t, const double* diag) {
-    PanelCsr p = split_panels(t);
+    PanelCsr p = split_panels(t, kPanel);  // the several-sides solves take 64-row panels
     invert_panels(p, diag);
     return p;
   };
@@ -602,7 +602,7 @@ int batch_run(cond_batch_t* b, int route, const cond_opts_t* o, const double* x0
     const DevTri* devs[4] = {&b->dL, &b->dU, &b->dUt, &b->dLt};
     for (int f = 0; f < 4; ++f)
       if (tris[f]->nslots > 0)
-        launch_fill(tris[f]->nslots * kPanelRows * kBatchK, devs[f]->partials, kPending, b->stream);
+        launch_fill(static_cast<long long>(tris[f]->nslots) * tris[f]->prows * kBatchK, devs[f]->partials, kPending, b->stream);
     b->rearm_slots = false;
   }
   // initial per-pair state

@@ -458,29 +458,42 @@ __device__ __forceinline__ void row_sums(const long long* p0, const long long* p
     for (int off = kLanesPerRow / 2; off > 0; off >>= 1) acc[j] += __shfl_xor(acc[j], off, kLanesPerRow);
 }
 
-// A panel of up to kPanelRows rows is solved by one block as kSubPanels
-// sub-panels of 64 rows. Everything that does not depend on solved values --
-// the right-hand side, the inverse of each sub-panel's triangle (into LDS)
-// and the entries of the second sub-panel on the first (into registers) --
-// is loaded before the first wait, so that once the panel's inputs are
-// published only the off-panel sums and the short products with the
-// inverses remain.
-constexpr int kSubPanels = kPanelRows / kPanel;
-static_assert(kSubPanels == 1 || kSubPanels == 2, "one or two sub-panels per panel");
-constexpr int kLocalPerLane = kPanel / kLanesPerRow;  // entries of a row on the first sub-panel
+// 16 bytes from src (16-byte aligned) into LDS at dst + 16 * (lane in its
+// wave) bytes, without passing through registers (dst: the same for every
+// lane of the wave).
+__device__ __forceinline__ void copy16_to_lds(const double* src, double* dst) {
+  __builtin_amdgcn_global_load_lds(src, dst, 16, 0, 0);
+}
 
-constexpr int kLdW = kPanel + 1;  // LDS row stride of a staged inverse (padded against bank conflicts)
+// Waits until every memory access this wave issued has completed (the
+// copies into LDS among them).
+__device__ __forceinline__ void wait_all_memory() { __builtin_amdgcn_s_waitcnt(0); }
 
+// A panel of up to R rows (R = kPanel or kMaxPanelRows) is solved by one
+// block: row group g (16 lanes) takes rows g + 64 j, j < R / 64.
+// Everything that does not depend on solved values -- the right-hand side
+// (into registers) and the panel's triangle's inverse (copied from memory
+// straight into LDS, 16 bytes per lane, without passing through registers)
+// -- is requested before the first wait, so that once the panel's inputs
+// are published only the off-panel sums and one product with the inverse
+// remain.
+constexpr int kLocalPerLane = kPanel / kLanesPerRow;  // inverse columns per lane of a 64-row panel
+constexpr int kLdW = kPanel + 1;  // LDS row stride of a staged 64-row inverse (padded against bank conflicts)
+
+template <int R>
 __global__ __launch_bounds__(kTrsvBlock) void trsv_k(TrsvArgs t, const double* __restrict__ rhs,
                                                      const int* __restrict__ rhs_perm, double* out,
                                                      double* __restrict__ scatter,
                                                      const int* __restrict__ scatter_perm,
                                                      unsigned* ticket, RunState* st) {
-  // inverse of sub-panel k's triangle, row-major: (r, c) at [k][r * kLdW + c]
-  __shared__ double w_sh[kSubPanels][kPanel * kLdW];
-  __shared__ double t_sh[kPanelRows];  // off-panel sums (then minus the first sub-panel)
-  __shared__ double b_sh[kPanelRows];  // right-hand side of the panel's rows
-  __shared__ double x_sh[kPanel];      // solved values of the first sub-panel
+  constexpr int NR = R / kPanel;        // rows per row group
+  constexpr int CPL = R / kLanesPerRow;  // inverse columns per lane
+  constexpr int kW = R * (R + 1) / 2;    // values of a packed R-row triangle (even)
+  static_assert(NR == 1 || NR == 2, "64- or 128-row panels");
+  static_assert(kW % 2 == 0, "whole 16-byte chunks");
+  __shared__ double w_sh[kW];  // the panel's inverse, rows packed: (r, c) at r (r + 1) / 2 + c
+  __shared__ double t_sh[R];        // off-panel sums
+  __shared__ double b_sh[R];        // right-hand side of the panel's rows
   __shared__ unsigned task_sh;
   __shared__ int quit_sh;
   // one read for the whole block: abort_wait may change while blocks start
@@ -492,7 +505,7 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_k(TrsvArgs t, const double* _
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int sub = lane & (kLanesPerRow - 1);
-  const int g = wave * (64 / kLanesPerRow) + lane / kLanesPerRow;  // this group's row, 0..63
+  const int g = wave * (64 / kLanesPerRow) + lane / kLanesPerRow;  // this group's first row, 0..63
   // this block's task list (block b serves list b mod kTaskLists: on the
   // usual round-robin dispatch, one list per XCD) and its ticket counter
   const int lst = static_cast<int>(blockIdx.x % kTaskLists);
@@ -508,21 +521,20 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_k(TrsvArgs t, const double* _
     // the panel's own arrays
     const int4 ra = reinterpret_cast<const int4*>(t.task_rec)[2 * T];
     const int4 rb = reinterpret_cast<const int4*>(t.task_rec)[2 * T + 1];
-    const int P = ra.x;
     const int kind = ra.y;  // -1 whole panel, 0..S-1 slice, S finish
     const long long lo = ra.z;
     const int cnt = ra.w;
     const int S = rb.x;
-    double* slots = t.partials + static_cast<long long>(rb.y) * kPanelRows;
+    double* slots = t.partials + static_cast<long long>(rb.y) * R;
     const long long woff = static_cast<long long>(static_cast<unsigned>(rb.z)) |
                            (static_cast<long long>(rb.w) << 32);
-    // the task's row pointers and split points, loaded by ticket alone (in
+    // the task's row pointers and split points, loaded by slot alone (in
     // flight together with the record, not after it)
-    const long long* trp = t.task_rp + T * (kPanelRows + 1);
-    const long long* tsp = t.task_sp + T * kPanelRows;
-    long long q0[kSubPanels], q1[kSubPanels];  // the group's rows g + 64 j: off-panel ranges
+    const long long* trp = t.task_rp + T * (R + 1);
+    const long long* tsp = t.task_sp + T * R;
+    long long q0[NR], q1[NR];  // the group's rows g + 64 j: off-panel ranges
 #pragma unroll
-    for (int j = 0; j < kSubPanels; ++j) {
+    for (int j = 0; j < NR; ++j) {
       const int r = g + kPanel * j;
       const long long a0 = trp[r], a1 = trp[r + 1];
       q0[j] = r < cnt ? a0 : 0;
@@ -533,78 +545,60 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_k(TrsvArgs t, const double* _
       // older entries (the ones on rows before off_split; the finish step
       // adds the newest ones itself)
 #pragma unroll
-      for (int j = 0; j < kSubPanels; ++j) {
+      for (int j = 0; j < NR; ++j) {
         const int r = g + kPanel * j;
         if (r < cnt) q1[j] = tsp[r];
         const long long len = q1[j] - q0[j];
         q1[j] = q0[j] + len * (kind + 1) / S;
         q0[j] = q0[j] + len * kind / S;
       }
-      double part[kSubPanels];
-      if (kSubPanels == 1 || cnt <= kPanel)
+      double part[NR];
+      if (NR == 1 || cnt <= kPanel)
         part[0] = row_sum(q0[0], q1[0], sub, t.off_col, t.off_val, out, st);
       else
-        row_sums<kSubPanels>(q0, q1, sub, t.off_col, t.off_val, out, st, part);
+        row_sums<NR>(q0, q1, sub, t.off_col, t.off_val, out, st, part);
 #pragma unroll
-      for (int j = 0; j < kSubPanels; ++j) {
+      for (int j = 0; j < NR; ++j) {
         const int r = g + kPanel * j;
-        if (r < cnt && sub == 0) publish(slots + static_cast<long long>(kind) * kPanelRows + r, part[j]);
+        if (r < cnt && sub == 0) publish(slots + static_cast<long long>(kind) * R + r, part[j]);
       }
       __syncthreads();  // task_sh is reused
       continue;
     }
-    // ---- everything that needs no solved value
-    int lc[kLocalPerLane];
-    double lv[kLocalPerLane];
-#pragma unroll
-    for (int u = 0; u < kLocalPerLane; ++u) {
-      lc[u] = 0;
-      lv[u] = 0.0;
+    // ---- everything that needs no solved value: the inverse, 16-byte chunk
+    // ch of the packed triangle by thread ch mod kTrsvBlock into the same
+    // place in LDS (the triangle starts 16-byte aligned; the last chunk may
+    // take one value past its end, still inside winv), and the right-hand
+    // side into registers
+    {
+      const double* w = t.winv + woff;
+      const int nch = (cnt * (cnt + 1) / 2 + 1) / 2;
+      for (int c0 = 0; c0 < nch; c0 += kTrsvBlock)
+        if (c0 + static_cast<int>(threadIdx.x) < nch)
+          copy16_to_lds(w + 2 * (c0 + threadIdx.x), w_sh + 2 * (c0 + wave * 64));
     }
-    // (into registers: their LDS copies are written once the sums are in, so
-    // that no wait for these loads stands between the task record and the
-    // first loads of the off-panel entries)
-    double bval[kSubPanels];
-    double wreg[kSubPanels][kLocalPerLane];
+    double bval[NR];
 #pragma unroll
-    for (int j = 0; j < kSubPanels; ++j) {
+    for (int j = 0; j < NR; ++j) {
       const int r = g + kPanel * j;
-      bval[j] = 0.0;
-      if (r < cnt) {
-        if (sub == 0) bval[j] = rhs_perm ? rhs[rhs_perm[lo + r]] : rhs[lo + r];
-        if (j > 0) {  // entries on the first sub-panel: at most 64, four per lane
-          const long long e0 = t.in_rp[lo + r], em = t.in_split[lo + r];
-#pragma unroll
-          for (int u = 0; u < kLocalPerLane; ++u) {
-            const long long e = e0 + u * kLanesPerRow + sub;
-            lc[u] = e < em ? t.in_col[e] : 0;
-            lv[u] = e < em ? t.in_val[e] : 0.0;
-          }
-        }
-      }
-      // row g of the sub-panel's inverse, columns sub + 16 u (zero above the
-      // diagonal and past the sub-panel's last row)
-      const int ck = cnt - kPanel * j < kPanel ? cnt - kPanel * j : kPanel;
-      const double* w = t.winv + woff + static_cast<long long>(j) * kTriPacked;
-#pragma unroll
-      for (int u = 0; u < kLocalPerLane; ++u) {
-        const int c = sub + u * kLanesPerRow;
-        wreg[j][u] = (g < ck && c <= g) ? w[g * (g + 1) / 2 + c] : 0.0;
-      }
+      bval[j] = (r < cnt && sub == 0) ? (rhs_perm ? rhs[rhs_perm[lo + r]] : rhs[lo + r]) : 0.0;
     }
     // ---- off-panel sums of every row (these wait for the panel's inputs)
-    double sums[kSubPanels];
+    double sums[NR];
     if (kind < 0) {
-      if (kSubPanels == 1 || cnt <= kPanel)
+      if (NR == 1 || cnt <= kPanel) {
         sums[0] = row_sum(q0[0], q1[0], sub, t.off_col, t.off_val, out, st);
-      else
-        row_sums<kSubPanels>(q0, q1, sub, t.off_col, t.off_val, out, st, sums);
+#pragma unroll
+        for (int j = 1; j < NR; ++j) sums[j] = 0.0;
+      } else {
+        row_sums<NR>(q0, q1, sub, t.off_col, t.off_val, out, st, sums);
+      }
     } else {
       // finish: the 16 lanes of a row read its slice partials together (lane
       // sub takes slices sub, sub + 16, ...), add them in that fixed order,
       // then re-arm the slots they read for the next solve
 #pragma unroll
-      for (int j = 0; j < kSubPanels; ++j) {
+      for (int j = 0; j < NR; ++j) {
         const int r = g + kPanel * j;
         double acc = 0.0;
         if (r < cnt) {
@@ -615,7 +609,7 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_k(TrsvArgs t, const double* _
 #pragma unroll
           for (int u = 0; u < kSlotsPerLane; ++u) {
             const int k = sub + u * kLanesPerRow;
-            so[u] = k < S ? k * kPanelRows : -1;
+            so[u] = k < S ? k * R : -1;
             bits[u] = k < S ? __hip_atomic_load(sp + so[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                             : 0ull;
           }
@@ -629,7 +623,7 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_k(TrsvArgs t, const double* _
         }
 #pragma unroll
         for (int off = kLanesPerRow / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kLanesPerRow);
-        // the row's newest entries (on the panels just before this one): the
+        // the row's newest entries (on the panel just before this one): the
         // finish step waits for them itself, one hop fewer on a chain
         const double recent = r < cnt ? row_sum(tsp[r], trp[r + 1], sub, t.off_col, t.off_val, out, st)
                                       : 0.0;
@@ -637,47 +631,34 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_k(TrsvArgs t, const double* _
       }
     }
 #pragma unroll
-    for (int j = 0; j < kSubPanels; ++j) {
-      if (g + kPanel * j < cnt && sub == 0) {
-        t_sh[g + kPanel * j] = sums[j];
-        b_sh[g + kPanel * j] = bval[j];
+    for (int j = 0; j < NR; ++j) {
+      const int r = g + kPanel * j;
+      if (r < cnt && sub == 0) {
+        t_sh[r] = sums[j];
+        b_sh[r] = bval[j];
       }
-#pragma unroll
-      for (int u = 0; u < kLocalPerLane; ++u) w_sh[j][g * kLdW + sub + u * kLanesPerRow] = wreg[j][u];
     }
+    wait_all_memory();  // the inverse's copies into LDS have landed
     __syncthreads();
-    // ---- the sub-panels in order: x = W (b - sums), row g by its 16 lanes
+    // ---- x = W (b - sums), row r by its 16 lanes
 #pragma unroll
-    for (int j = 0; j < kSubPanels; ++j) {
-      const int k0 = kPanel * j;
-      if (k0 >= cnt) break;
-      const int ck = cnt - k0 < kPanel ? cnt - k0 : kPanel;
-      if (j > 0) {
-        // minus the entries on the first sub-panel, now solved
-        double acc = 0.0;
-#pragma unroll
-        for (int u = 0; u < kLocalPerLane; ++u) acc += lv[u] * x_sh[lc[u]];
-#pragma unroll
-        for (int off = kLanesPerRow / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kLanesPerRow);
-        if (g < ck && sub == 0) t_sh[k0 + g] += acc;
-        __syncthreads();
-      }
+    for (int j = 0; j < NR; ++j) {
+      const int r = g + kPanel * j;
       double acc = 0.0;
 #pragma unroll
-      for (int u = 0; u < kLocalPerLane; ++u) {
+      for (int u = 0; u < CPL; ++u) {
         const int c = sub + u * kLanesPerRow;
-        if (c <= g && c < ck) acc += w_sh[j][g * kLdW + c] * (b_sh[k0 + c] - t_sh[k0 + c]);
+        if (c <= r && c < cnt) acc += w_sh[r * (r + 1) / 2 + c] * (b_sh[c] - t_sh[c]);
       }
 #pragma unroll
       for (int off = kLanesPerRow / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kLanesPerRow);
-      if (g < ck && sub == 0) {
-        const long long i = lo + k0 + g;
-        if (j == 0) x_sh[g] = acc;
+      if (r < cnt && sub == 0) {
+        const long long i = lo + r;
         publish(out + i, acc);
         if (scatter) scatter[scatter_perm[i]] = acc;
       }
-      __syncthreads();  // x_sh feeds the next sub-panel; LDS and task_sh are reused
     }
+    __syncthreads();  // LDS and task_sh are reused
   }
 }
 
@@ -690,7 +671,7 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_k(TrsvArgs t, const double* _
 // one pass over the factor, and one wait per dependency, serve all K sides.
 // Slice partials are K per row. The run is skipped when *stop is non-zero
 // (every start of the run has stopped); a wait that times out sets *abort.
-static_assert(kPanelRows == kPanel, "the several-sides solve takes one sub-panel per panel");
+// (Panels of kPanel rows: the host plans these schedules with that height.)
 
 // Off-panel sums of one row over entries [p0, p1) for all K sides at once:
 // lane sub of the row's 16 takes entries sub, sub + 16, ... (the single-side
@@ -804,11 +785,11 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_multi_k(TrsvArgs t, const dou
     const long long lo = ra.z;
     const int cnt = ra.w;
     const int S = rb.x;
-    double* slots = t.partials + static_cast<long long>(rb.y) * kPanelRows * K;
+    double* slots = t.partials + static_cast<long long>(rb.y) * kPanel * K;
     const long long woff = static_cast<long long>(static_cast<unsigned>(rb.z)) |
                            (static_cast<long long>(rb.w) << 32);
-    const long long* trp = t.task_rp + T * (kPanelRows + 1);
-    const long long* tsp = t.task_sp + T * kPanelRows;
+    const long long* trp = t.task_rp + T * (kPanel + 1);
+    const long long* tsp = t.task_sp + T * kPanel;
     const bool row = g < cnt;
     const long long a0 = trp[g], a1 = trp[g + 1], sp = tsp[g];
     long long q0 = row ? a0 : 0, q1 = row ? a1 : 0;
@@ -820,7 +801,7 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_multi_k(TrsvArgs t, const dou
       const long long s0 = q0 + len * kind / S;
       const double part = row_sum_multi<K>(s0, s1, sub, kk, t.off_col, t.off_val, out, abort);
       if (row && es == 0)
-        publish(slots + (static_cast<long long>(kind) * kPanelRows + g) * K + kk, part);
+        publish(slots + (static_cast<long long>(kind) * kPanel + g) * K + kk, part);
       __syncthreads();  // task_sh is reused
       continue;
     }
@@ -852,7 +833,7 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_multi_k(TrsvArgs t, const dou
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const int k = k0 + u * EL;
-            so[u] = k < S ? (k * kPanelRows + g) * K + kk : -1;
+            so[u] = k < S ? (k * kPanel + g) * K + kk : -1;
             bits[u] = k < S ? __hip_atomic_load(sp + so[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                             : 0ull;
           }
@@ -1208,7 +1189,10 @@ void launch_trsv(const DevTri& t, const double* rhs, const int* rhs_perm, double
                  double* scatter, const int* scatter_perm, unsigned* ticket, RunState* st,
                  hipStream_t s) {
   const int g = trsv_grid(t.ntasks);
-  trsv_k<<<g, kTrsvBlock, 0, s>>>(t, rhs, rhs_perm, out, scatter, scatter_perm, ticket, st);
+  if (t.prows == kMaxPanelRows)
+    trsv_k<kMaxPanelRows><<<g, kTrsvBlock, 0, s>>>(t, rhs, rhs_perm, out, scatter, scatter_perm, ticket, st);
+  else
+    trsv_k<kPanel><<<g, kTrsvBlock, 0, s>>>(t, rhs, rhs_perm, out, scatter, scatter_perm, ticket, st);
 }
 
 void launch_trsv_multi(int K, const DevTri& t, const double* rhs, const int* rhs_perm, double* out,
@@ -1261,11 +1245,11 @@ void launch_triad(long long n, double* a, const double* b, const double* c, doub
   triad_k<<<grid, kBlock, 0, s>>>(n, a, b, c, scale);
 }
 
-void launch_fill(int n, double* p, unsigned long long bits, hipStream_t s) {
-  int blocks = (n + kBlock - 1) / kBlock;
+void launch_fill(long long n, double* p, unsigned long long bits, hipStream_t s) {
+  long long blocks = (n + kBlock - 1) / kBlock;
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
-  fill_k<<<blocks, kBlock, 0, s>>>(n, reinterpret_cast<unsigned long long*>(p), bits);
+  fill_k<<<static_cast<int>(blocks), kBlock, 0, s>>>(n, reinterpret_cast<unsigned long long*>(p), bits);
 }
 
 void launch_set_int(int* p, int v, hipStream_t s) { set_int_k<<<1, 64, 0, s>>>(p, v); }

@@ -83,7 +83,7 @@ constexpr long long kTileEntriesHost = 2048;
 
 // A lower-triangular factor in solve order (upper factors are reversed on the
 // host, row i -> n-1-i, so every solve is a forward substitution), cut into
-// panels of at most 64 consecutive rows. Per row, the entries with a column
+// panels of at most prows consecutive rows. Per row, the entries with a column
 // before the row's panel ("off") and inside it ("in", column relative to the
 // panel start). The solve is a list of tasks in dependency-level order:
 // task t works on panel task_panel[t]; task_kind[t] = -1 for the whole panel,
@@ -95,17 +95,13 @@ struct DevTri {
   const int* off_col = nullptr;
   const double* off_val = nullptr;
   const long long* off_split = nullptr;  // per row of a sliced panel: first entry the finish adds
-  // in-panel entries (read only for a second sub-panel's entries on the first)
-  const long long* in_rp = nullptr;
-  const long long* in_split = nullptr;  // per row: first in-panel entry inside its own sub-panel
-  const int* in_col = nullptr;          // in-panel columns, relative to the panel's first row
-  const double* in_val = nullptr;
-  // inverse of each sub-panel's triangle (its own in-panel entries and the
+  // inverse of each panel's triangle (its in-panel entries and the
   // diagonal, unit for L), lower rows packed: (r, c) at r (r + 1) / 2 + c;
-  // sub-panel j of panel p at winv + woff[p] + j * kTriPacked
+  // panel p's at winv + woff[p]
   const double* winv = nullptr;
   const long long* woff = nullptr;
-  double* partials = nullptr;  // slice partial sums, kPanelRows doubles per slot; kPending when idle
+  double* partials = nullptr;  // slice partial sums, prows doubles per slot (times the sides); kPending when idle
+  int prows = kPanel;          // most rows of a panel
   int ntasks = 0;
   // the tasks in kTaskLists lists, each in dependency order and handed out
   // by its own ticket counter: list l is the slots [list_off[l],
@@ -178,7 +174,7 @@ void launch_residual(int n, const void* rowptr, int idx64, const int* col, const
 // a = b + scale c (n doubles; a, b, c 16-byte aligned): the streaming ceiling.
 void launch_triad(long long n, double* a, const double* b, const double* c, double scale, int grid,
                   hipStream_t s);
-void launch_fill(int n, double* p, unsigned long long bits, hipStream_t s);
+void launch_fill(long long n, double* p, unsigned long long bits, hipStream_t s);
 void launch_zero_u32(unsigned* p, int count, hipStream_t s);
 void launch_set_int(int* p, int v, hipStream_t s);
 

@@ -15,14 +15,14 @@ namespace {
 
 // A panel whose rows hold more off-panel entries than this is cut into
 // slices (at most kMaxSlices) that separate blocks sum in parallel. The
-// slices take a row's entries on rows more than kRecentRows before the
-// panel; the finish step takes the newer ones, so a chain of panels (a dense
-// separator block) waits for its predecessor in one step, not two.
+// slices take a row's entries on rows more than one panel height (prows)
+// before the panel; the finish step takes the newer ones, so a chain of
+// panels (a dense separator block) waits for its predecessor in one step,
+// not two.
 constexpr int64_t kSliceEntries = 4096;
-constexpr int32_t kRecentRows = 64;
 constexpr int32_t kMaxSlices = kMaxSlicesDev;
 
-// Panel boundaries: a panel closes when it holds kPanelRows rows, or -- once
+// Panel boundaries: a panel closes when it holds prows rows, or -- once
 // it holds at least kMinPanelRows -- before a row that needs nothing inside
 // it. Such a row usually opens an independent subtree of the elimination
 // order (a new leaf of the nested dissection); cutting there keeps independent
@@ -31,14 +31,14 @@ constexpr int32_t kMaxSlices = kMaxSlicesDev;
 // panels exactly as deep as the open panel does: it would run in the same
 // dependency level anyway, and one task fewer is cheaper than the parallelism
 // (the leaves of a nested dissection are thousands of panels of a few rows).
-// A panel also closes at a 64-row boundary when the next row reads a panel
-// that is deeper in the dependency order than anything the open panel reads:
-// the panel's later sub-panels then never hold back its first one. What
-// remains inside a panel are chains (a dense separator block, mostly), which
-// one block solves sub-panel after sub-panel without waiting on others.
+// A panel also closes at a kPanel-row boundary when the next row reads a
+// panel that is deeper in the dependency order than anything the open panel
+// reads, so that the rows before do not wait for it. What remains inside a
+// panel are chains (a dense separator block, mostly), which one block solves
+// at once with the inverse of the panel's triangle.
 constexpr int32_t kMinPanelRows = 4;
 
-std::vector<int32_t> cut_panels(const HostCsr& t, bool merge) {
+std::vector<int32_t> cut_panels(const HostCsr& t, bool merge, int32_t prows) {
   std::vector<int32_t> ps{0};
   std::vector<int32_t> pid(t.n, 0), plevel;  // panel of each closed row, level of each panel
   int32_t s = 0;
@@ -56,7 +56,7 @@ std::vector<int32_t> cut_panels(const HostCsr& t, bool merge) {
       needs_panel = t.col[p] >= s;
     const int32_t rows = e - s;
     const int32_t lv = ext_level(e);
-    if (rows >= kPanelRows || (!needs_panel && rows >= kMinPanelRows && (!merge || lv != cur)) ||
+    if (rows >= prows || (!needs_panel && rows >= kMinPanelRows && (!merge || lv != cur)) ||
         (rows % kPanel == 0 && lv > cur)) {
       const int32_t q = static_cast<int32_t>(plevel.size());
       for (int32_t i = s; i < e; ++i) pid[i] = q;
@@ -132,8 +132,9 @@ void finish_records(PanelCsr& s) {
   std::vector<int32_t> next(s.list_off.begin(), s.list_off.end() - 1);
   for (size_t k = 0; k < ntasks; ++k) s.task_slot[k] = next[k % kTaskLists]++;
   s.task_rec.assign(8 * ntasks, 0);
-  s.task_rp.assign(ntasks * (kPanelRows + 1), 0);
-  s.task_sp.assign(ntasks * kPanelRows, 0);
+  const int32_t R = s.prows;
+  s.task_rp.assign(ntasks * (R + 1), 0);
+  s.task_sp.assign(ntasks * R, 0);
   for (size_t k = 0; k < ntasks; ++k) {
     const size_t q = static_cast<size_t>(s.task_slot[k]);
     const int32_t p = s.task_panel[k];
@@ -143,9 +144,8 @@ void finish_records(PanelCsr& s) {
                             static_cast<int32_t>(static_cast<uint32_t>(w & 0xffffffffLL)),
                             static_cast<int32_t>(w >> 32)};
     std::copy(rec, rec + 8, s.task_rec.begin() + 8 * q);
-    for (int32_t r = 0; r <= kPanelRows; ++r)
-      s.task_rp[q * (kPanelRows + 1) + r] = s.off_rp[lo + std::min(r, cnt)];
-    for (int32_t r = 0; r < cnt; ++r) s.task_sp[q * kPanelRows + r] = s.off_split[lo + r];
+    for (int32_t r = 0; r <= R; ++r) s.task_rp[q * (R + 1) + r] = s.off_rp[lo + std::min(r, cnt)];
+    for (int32_t r = 0; r < cnt; ++r) s.task_sp[q * R + r] = s.off_split[lo + r];
   }
   s.slot_group.clear();
   s.slot_seg_end.clear();
@@ -168,12 +168,13 @@ void finish_records(PanelCsr& s) {
 
 }  // namespace
 
-PanelCsr split_panels(const HostCsr& t) {
+PanelCsr split_panels(const HostCsr& t, int32_t prows) {
   PanelCsr s;
   s.n = t.n;
+  s.prows = prows;
   // the cheaper of the two cuts by the cost model (merging the leaves pays
   // where they are many small panels, splitting where they are few)
-  std::vector<int32_t> split = cut_panels(t, false), merged = cut_panels(t, true);
+  std::vector<int32_t> split = cut_panels(t, false, prows), merged = cut_panels(t, true, prows);
   s.pstart = cut_cost(t, merged) < cut_cost(t, split) ? std::move(merged) : std::move(split);
   const int32_t np = static_cast<int32_t>(s.pstart.size()) - 1;
   std::vector<int32_t> pid;
@@ -185,25 +186,15 @@ PanelCsr split_panels(const HostCsr& t) {
   s.levels = np ? 1 + *std::max_element(level.begin(), level.end()) : 0;
   s.off_rp.assign(t.n + 1, 0);
   s.in_rp.assign(t.n + 1, 0);
-  s.in_split.assign(t.n, 0);
   s.off_split.assign(t.n, 0);
   for (int32_t i = 0; i < t.n; ++i) {
     const int32_t lo = s.pstart[pid[i]];
-    const int32_t sub0 = lo + (i - lo) / kPanel * kPanel;  // first row of i's sub-panel
     for (int64_t p = t.rowptr[i]; p < t.rowptr[i + 1]; ++p) {
       const int32_t j = t.col[p];
       if (j < lo) {
         s.off_col.push_back(j);
         s.off_val.push_back(t.val[p]);
-      } else if (j < sub0) {
-        s.in_col.push_back(j - lo);
-        s.in_val.push_back(t.val[p]);
-      }
-    }
-    s.in_split[i] = static_cast<int64_t>(s.in_col.size());
-    for (int64_t p = t.rowptr[i]; p < t.rowptr[i + 1]; ++p) {
-      const int32_t j = t.col[p];
-      if (j >= sub0) {
+      } else {
         s.in_col.push_back(j - lo);
         s.in_val.push_back(t.val[p]);
       }
@@ -226,7 +217,7 @@ PanelCsr split_panels(const HostCsr& t) {
     s.panel_split[p] = S;
     s.panel_slot[p] = s.nslots;
     s.nslots += S;
-    const int32_t c0 = s.pstart[p] - kRecentRows;  // older entries: columns below c0
+    const int32_t c0 = s.pstart[p] - prows;  // older entries: columns below c0
     for (int32_t i = s.pstart[p]; i < s.pstart[p + 1]; ++i) {
       int64_t e = s.off_rp[i];
       while (e < s.off_rp[i + 1] && s.off_col[e] < c0) ++e;  // columns are sorted in a row
@@ -244,6 +235,7 @@ PanelCsr split_panels(const HostCsr& t) {
 PanelCsr merge_panels(const std::vector<const PanelCsr*>& parts, const std::vector<int64_t>& offsets,
                       const std::vector<int32_t>& groups) {
   PanelCsr m;
+  m.prows = parts.empty() ? kPanel : parts[0]->prows;  // the parts share one panel height
   m.off_rp.push_back(0);
   m.in_rp.push_back(0);
   m.pstart.push_back(0);
@@ -260,7 +252,6 @@ PanelCsr merge_panels(const std::vector<const PanelCsr*>& parts, const std::vect
       m.off_rp.push_back(e_off + s.off_rp[i + 1]);
       m.in_rp.push_back(e_in + s.in_rp[i + 1]);
       m.off_split.push_back(e_off + s.off_split[i]);
-      m.in_split.push_back(e_in + s.in_split[i]);
     }
     for (int32_t c : s.off_col) m.off_col.push_back(c + r0);
     m.off_val.insert(m.off_val.end(), s.off_val.begin(), s.off_val.end());
@@ -298,46 +289,44 @@ PanelCsr merge_panels(const std::vector<const PanelCsr*>& parts, const std::vect
   return m;
 }
 
-// The inverse of every sub-panel's triangle: its own in-panel entries below
-// the diagonal and diag (nullptr: a unit diagonal) on it, inverted column by
-// column by substitution in float64. The kernel then forms a sub-panel's
-// values as one product with it instead of 64 dependent steps.
+// The inverse of every panel's triangle: its in-panel entries below the
+// diagonal and diag (nullptr: a unit diagonal) on it, inverted column by
+// column by substitution in float64 and stored packed by rows. The kernel
+// then forms a panel's values as one product with it instead of up to prows
+// dependent steps.
 void invert_panels(PanelCsr& s, const double* diag) {
   const int32_t np = static_cast<int32_t>(s.pstart.size()) - 1;
+  const int32_t R = s.prows;
   s.woff.assign(np, 0);
   int64_t total = 0;
+  // each triangle starts on a 16-byte boundary (an even offset): the kernel
+  // copies it into LDS 16 bytes per lane, up to one value past its end
   for (int32_t p = 0; p < np; ++p) {
     s.woff[p] = total;
-    const int32_t cnt = s.pstart[p + 1] - s.pstart[p];
-    for (int32_t k0 = 0; k0 < cnt; k0 += kPanel) {
-      const int64_t ck = std::min(kPanel, cnt - k0);
-      total += ck * (ck + 1) / 2;
-    }
+    const int64_t cnt = s.pstart[p + 1] - s.pstart[p];
+    total += (cnt * (cnt + 1) / 2 + 1) / 2 * 2;
   }
   s.winv.assign(total, 0.0);
-  std::vector<double> t(kPanel * kPanel), w(kPanel * kPanel);
+  std::vector<double> t(static_cast<size_t>(R) * R), w(static_cast<size_t>(R) * R);
   for (int32_t p = 0; p < np; ++p) {
     const int32_t lo = s.pstart[p], cnt = s.pstart[p + 1] - lo;
-    for (int32_t k0 = 0, j = 0; k0 < cnt; k0 += kPanel, ++j) {
-      const int32_t ck = std::min(kPanel, cnt - k0);
-      // the sub-panel's triangle, dense: strictly lower entries, then the diagonal
-      std::fill(t.begin(), t.end(), 0.0);
-      for (int32_t r = 0; r < ck; ++r) {
-        const int32_t i = lo + k0 + r;
-        for (int64_t e = s.in_split[i]; e < s.in_rp[i + 1]; ++e) t[r * kPanel + (s.in_col[e] - k0)] = s.in_val[e];
-        t[r * kPanel + r] = diag ? diag[i] : 1.0;
-      }
-      std::fill(w.begin(), w.end(), 0.0);
-      for (int32_t c = 0; c < ck; ++c)
-        for (int32_t r = c; r < ck; ++r) {
-          double a = r == c ? 1.0 : 0.0;
-          for (int32_t k = c; k < r; ++k) a -= t[r * kPanel + k] * w[k * kPanel + c];
-          w[r * kPanel + c] = a / t[r * kPanel + r];
-        }
-      double* out = s.winv.data() + s.woff[p] + static_cast<int64_t>(j) * kTriPacked;
-      for (int32_t r = 0; r < ck; ++r)
-        for (int32_t c = 0; c <= r; ++c) out[r * (r + 1) / 2 + c] = w[r * kPanel + c];
+    // the triangle, dense: strictly lower entries, then the diagonal
+    std::fill(t.begin(), t.end(), 0.0);
+    for (int32_t r = 0; r < cnt; ++r) {
+      const int32_t i = lo + r;
+      for (int64_t e = s.in_rp[i]; e < s.in_rp[i + 1]; ++e) t[r * R + s.in_col[e]] = s.in_val[e];
+      t[r * R + r] = diag ? diag[i] : 1.0;
     }
+    std::fill(w.begin(), w.end(), 0.0);
+    for (int32_t c = 0; c < cnt; ++c)
+      for (int32_t r = c; r < cnt; ++r) {
+        double a = r == c ? 1.0 : 0.0;
+        for (int32_t k = c; k < r; ++k) a -= t[r * R + k] * w[k * R + c];
+        w[r * R + c] = a / t[r * R + r];
+      }
+    double* out = s.winv.data() + s.woff[p];
+    for (int32_t r = 0; r < cnt; ++r)
+      for (int32_t c = 0; c <= r; ++c) out[r * (r + 1) / 2 + c] = w[r * R + c];
   }
   finish_records(s);
 }
@@ -375,9 +364,10 @@ HostCsr reverse_order(const HostCsr& u) {
 bool replay_solve(const PanelCsr& t, const int32_t* gather, const double* in, double* out) {
   const int32_t n = t.n;
   std::vector<char> ready(n, 0);
-  std::vector<double> slots(static_cast<size_t>(t.nslots) * kPanelRows, 0.0);
-  std::vector<char> slot_set(static_cast<size_t>(t.nslots) * kPanelRows, 0);
-  std::vector<double> acc(kPanelRows);
+  const int32_t R = t.prows;
+  std::vector<double> slots(static_cast<size_t>(t.nslots) * R, 0.0);
+  std::vector<char> slot_set(static_cast<size_t>(t.nslots) * R, 0);
+  std::vector<double> acc(R);
   bool ok = true;
   auto sum = [&](int64_t e0, int64_t e1) {
     double a = 0.0;
@@ -394,12 +384,12 @@ bool replay_solve(const PanelCsr& t, const int32_t* gather, const double* in, do
     const int32_t kind = rec[1], lo = rec[2], cnt = rec[3], S = rec[4], slot = rec[5];
     const int64_t woff = static_cast<int64_t>(static_cast<uint32_t>(rec[6])) |
                          (static_cast<int64_t>(rec[7]) << 32);
-    const int64_t* trp = &t.task_rp[q * (kPanelRows + 1)];
-    const int64_t* tsp = &t.task_sp[q * kPanelRows];
+    const int64_t* trp = &t.task_rp[q * (R + 1)];
+    const int64_t* tsp = &t.task_sp[q * R];
     if (kind >= 0 && kind < S) {  // slice
       for (int32_t r = 0; r < cnt; ++r) {
         const int64_t q0 = trp[r], len = tsp[r] - q0;
-        const size_t at = static_cast<size_t>(slot + kind) * kPanelRows + r;
+        const size_t at = static_cast<size_t>(slot + kind) * R + r;
         slots[at] = sum(q0 + len * kind / S, q0 + len * (kind + 1) / S);
         slot_set[at] = 1;
       }
@@ -413,7 +403,7 @@ bool replay_solve(const PanelCsr& t, const int32_t* gather, const double* in, do
       } else {  // finish
         sums = 0.0;
         for (int32_t m = 0; m < S; ++m) {
-          const size_t at = static_cast<size_t>(slot + m) * kPanelRows + r;
+          const size_t at = static_cast<size_t>(slot + m) * R + r;
           ok = ok && slot_set[at];
           sums += slots[at];
         }
@@ -421,19 +411,12 @@ bool replay_solve(const PanelCsr& t, const int32_t* gather, const double* in, do
       }
       acc[r] = in[gather ? gather[i] : i] - sums;
     }
-    for (int32_t k0 = 0, j = 0; k0 < cnt; k0 += kPanel, ++j) {
-      const int32_t ck = std::min(kPanel, cnt - k0);
-      for (int32_t r = 0; r < ck && j > 0; ++r) {
-        const int32_t i = lo + k0 + r;
-        for (int64_t e = t.in_rp[i]; e < t.in_split[i]; ++e) acc[k0 + r] -= t.in_val[e] * out[lo + t.in_col[e]];
-      }
-      const double* w = t.winv.data() + woff + static_cast<int64_t>(j) * kTriPacked;
-      for (int32_t r = 0; r < ck; ++r) {
-        double x = 0.0;
-        for (int32_t c = 0; c <= r; ++c) x += w[r * (r + 1) / 2 + c] * acc[k0 + c];
-        out[lo + k0 + r] = x;
-        ready[lo + k0 + r] = 1;
-      }
+    const double* w = t.winv.data() + woff;
+    for (int32_t r = 0; r < cnt; ++r) {
+      double x = 0.0;
+      for (int32_t c = 0; c <= r; ++c) x += w[r * (r + 1) / 2 + c] * acc[c];
+      out[lo + r] = x;
+      ready[lo + r] = 1;
     }
   }
   for (int32_t i = 0; i < n && ok; ++i) ok = ready[i];
@@ -446,13 +429,7 @@ void tri_layout(const PanelCsr& t, int K, Layout& L, size_t* o) {
   o[kOffCol] = L.take(t.off_col.size() * 4);
   o[kOffVal] = L.take(t.off_val.size() * 8);
   o[kOffSplit] = L.take(n * 8);
-  // in-panel entries: read only for a second sub-panel's entries on the first
-  const bool in_entries = kPanelRows > kPanel;
-  o[kInRp] = L.take(in_entries ? (n + 1) * 8 : 0);
-  o[kInSplit] = L.take(in_entries ? n * 8 : 0);
-  o[kInCol] = L.take(in_entries ? t.in_col.size() * 4 : 0);
-  o[kInVal] = L.take(in_entries ? t.in_val.size() * 8 : 0);
-  o[kPartials] = L.take(static_cast<size_t>(t.nslots) * kPanelRows * K * 8);
+  o[kPartials] = L.take(static_cast<size_t>(t.nslots) * t.prows * K * 8);
   o[kWinv] = L.take(t.winv.size() * 8);
   o[kWoff] = L.take(t.woff.size() * 8);
   o[kTaskRec] = L.take(t.task_rec.size() * 4);

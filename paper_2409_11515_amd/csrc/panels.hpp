@@ -26,18 +26,17 @@ struct Layout {
 
 // Device arrays of one solve's panel structure (offsets into the workspace).
 enum TriSlot {
-  kOffRp, kOffCol, kOffVal, kOffSplit, kInRp, kInSplit, kInCol, kInVal,
-  kPartials, kWinv, kWoff, kTaskRec, kTaskRp, kTaskSp, kSlotGroup, kSlotSegEnd, kTriSlots
+  kOffRp, kOffCol, kOffVal, kOffSplit, kPartials, kWinv, kWoff, kTaskRec, kTaskRp, kTaskSp,
+  kSlotGroup, kSlotSegEnd, kTriSlots
 };
 
 // A strictly lower-triangular factor in solve order, cut into panels of at
-// most kPanelRows consecutive rows, each split into the entries left of the
-// panel and the entries inside it, plus the order in which panels are handed
-// out. A row's in-panel entries list those on earlier 64-row sub-panels of
-// its panel first; in_split marks where the entries of its own sub-panel start.
+// most prows consecutive rows, each split into the entries left of the panel
+// and the entries inside it, plus the order in which panels are handed out.
 struct PanelCsr {
   int32_t n = 0;
-  std::vector<int64_t> off_rp, in_rp, in_split, off_split;
+  int32_t prows = kPanel;  // most rows of a panel: 64 or 128 (kMaxPanelRows)
+  std::vector<int64_t> off_rp, in_rp, off_split;
   std::vector<int32_t> off_col, in_col;
   std::vector<double> off_val, in_val;
   std::vector<int32_t> pstart;  // panel p holds rows [pstart[p], pstart[p+1])
@@ -53,17 +52,17 @@ struct PanelCsr {
   // per slot: panel, kind, first row, rows, slices, first slot, and the
   // offset of its panel's inverse in winv as two 32-bit halves (low, high)
   std::vector<int32_t> task_rec;
-  // per slot: the off-panel row pointers of its panel's rows (kPanelRows + 1
+  // per slot: the off-panel row pointers of its panel's rows (prows + 1
   // values, the last repeated past the panel's end) and their split points
-  // (kPanelRows values, 0 past the end), so a block loads them together
+  // (prows values, 0 past the end), so a block loads them together
   // with the record instead of after it
   std::vector<int64_t> task_rp, task_sp;
   // joined schedules, per slot: the block, and one past the end of the run
   // of consecutive slots of its list with the same block and level, counted
   // from the list's first slot (a dead block's run is skipped at once)
   std::vector<int32_t> slot_group, slot_seg_end;
-  // inverse of each sub-panel's triangle, lower rows packed; panel p's
-  // sub-panel j at winv[woff[p] + j * kTriPacked]
+  // inverse of each panel's triangle, lower rows packed ((r, c) at
+  // r (r + 1) / 2 + c); panel p's at winv[woff[p]]
   std::vector<double> winv;
   std::vector<int64_t> woff;
   int32_t levels = 0;
@@ -71,7 +70,7 @@ struct PanelCsr {
 };
 
 // Panels, slices and tasks of a strictly lower factor t (rows in solve order).
-PanelCsr split_panels(const HostCsr& t);
+PanelCsr split_panels(const HostCsr& t, int32_t prows);
 // Schedules of independent diagonal blocks joined into one: parts[k] is the
 // schedule of the block whose first row (in solve order) is offsets[k], the
 // blocks in increasing offset order, contiguous. Panels, slots and inverses
@@ -80,7 +79,7 @@ PanelCsr split_panels(const HostCsr& t);
 // task records groups[k] of its block.
 PanelCsr merge_panels(const std::vector<const PanelCsr*>& parts, const std::vector<int64_t>& offsets,
                       const std::vector<int32_t>& groups);
-// The inverse of every sub-panel's triangle with diagonal diag (nullptr: unit);
+// The inverse of every panel's triangle with diagonal diag (nullptr: unit);
 // completes the task records (inverse offsets, row pointers).
 void invert_panels(PanelCsr& s, const double* diag);
 // Row i -> n-1-i and column j -> n-1-j: an upper factor becomes lower.

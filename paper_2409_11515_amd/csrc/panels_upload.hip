@@ -14,12 +14,6 @@ int tri_upload(char* ws, const size_t* off, const PanelCsr& t, int K, hipStream_
   if (e == hipSuccess) e = up(kOffCol, t.off_col.data(), t.off_col.size() * 4);
   if (e == hipSuccess) e = up(kOffVal, t.off_val.data(), t.off_val.size() * 8);
   if (e == hipSuccess) e = up(kOffSplit, t.off_split.data(), static_cast<size_t>(t.n) * 8);
-  if (kPanelRows > kPanel) {
-    if (e == hipSuccess) e = up(kInRp, t.in_rp.data(), (t.n + 1) * 8);
-    if (e == hipSuccess) e = up(kInSplit, t.in_split.data(), static_cast<size_t>(t.n) * 8);
-    if (e == hipSuccess) e = up(kInCol, t.in_col.data(), t.in_col.size() * 4);
-    if (e == hipSuccess) e = up(kInVal, t.in_val.data(), t.in_val.size() * 8);
-  }
   if (e == hipSuccess) e = up(kWinv, t.winv.data(), t.winv.size() * 8);
   if (e == hipSuccess) e = up(kWoff, t.woff.data(), t.woff.size() * 8);
   if (e == hipSuccess) e = up(kTaskRec, t.task_rec.data(), t.task_rec.size() * 4);
@@ -30,16 +24,13 @@ int tri_upload(char* ws, const size_t* off, const PanelCsr& t, int K, hipStream_
   if (e != hipSuccess) return fail(COND_EHIP, std::string("solve upload: ") + hipGetErrorString(e));
   auto at = [&](int slot) { return ws + off[slot]; };
   if (t.nslots > 0)
-    launch_fill(t.nslots * kPanelRows * K, reinterpret_cast<double*>(at(kPartials)), kPending, s);
+    launch_fill(static_cast<long long>(t.nslots) * t.prows * K, reinterpret_cast<double*>(at(kPartials)), kPending, s);
   out.n = t.n;
+  out.prows = t.prows;
   out.off_rp = reinterpret_cast<const long long*>(at(kOffRp));
   out.off_col = reinterpret_cast<const int*>(at(kOffCol));
   out.off_val = reinterpret_cast<const double*>(at(kOffVal));
   out.off_split = reinterpret_cast<const long long*>(at(kOffSplit));
-  out.in_rp = reinterpret_cast<const long long*>(at(kInRp));
-  out.in_split = reinterpret_cast<const long long*>(at(kInSplit));
-  out.in_col = reinterpret_cast<const int*>(at(kInCol));
-  out.in_val = reinterpret_cast<const double*>(at(kInVal));
   out.winv = reinterpret_cast<const double*>(at(kWinv));
   out.woff = reinterpret_cast<const long long*>(at(kWoff));
   out.partials = reinterpret_cast<double*>(at(kPartials));

@@ -429,7 +429,7 @@ void rearm_after_timeout(cond_plan* p) {
   const PanelCsr* tris[4] = {&p->pL, &p->pU, &p->pUt, &p->pLt};
   const DevTri* devs[4] = {&p->dL, &p->dU, &p->dUt, &p->dLt};
   for (int f = 0; f < 4; ++f)
-    if (tris[f]->nslots > 0) launch_fill(tris[f]->nslots * kPanelRows, devs[f]->partials, kPending, p->stream);
+    if (tris[f]->nslots > 0) launch_fill(static_cast<long long>(tris[f]->nslots) * tris[f]->prows, devs[f]->partials, kPending, p->stream);
   p->rearm_slots = false;
 }
 
@@ -547,7 +547,7 @@ int cond_plan_create(const cond_csr_t* A, const cond_opts_t* o, cond_plan_t** ou
       // the four schedules are independent host work, one thread each; each
       // is the same computation as on one thread
       auto sched = [](const HostCsr& t, const double* diag) {
-        PanelCsr s = split_panels(t);
+        PanelCsr s = split_panels(t, kPanel);
         invert_panels(s, diag);
         return s;
       };

@@ -4,10 +4,13 @@
 
 namespace condest {
 
-constexpr int kPanel = 64;         // rows of a sub-panel: one wave solves its triangle
+// A block solves a panel with 64 row groups of 16 lanes: a panel of kPanel
+// rows has one row per group, one of kMaxPanelRows two. The single-side
+// solves use kMaxPanelRows-row panels, the several-sides solves kPanel-row
+// ones.
+constexpr int kPanel = 64;
+constexpr int kMaxPanelRows = 128;
 constexpr int kMaxSlicesDev = 64;  // most slices a heavy panel is cut into
-constexpr int kPanelRows = 64;     // rows of a panel: its sub-panels are solved in order by one block
-constexpr int kTriPacked = kPanel * (kPanel + 1) / 2;  // entries of a packed 64-row triangle
 // The tasks of a solve are dealt to kTaskLists lists, each handed out by its
 // own ticket counter; the counters sit kTicketStride unsigned apart (one
 // 128-byte line each), kSolveTickets unsigned per solve.

@@ -115,22 +115,23 @@ struct Schedules {
   std::vector<int32_t> row_perm, col_perm, rev;
 };
 
-// The four solves of Algorithm 2 as the device plan schedules them.
-Schedules schedule(const cond_lu& f) {
+// The four solves of Algorithm 2 as the device plan (prows = kMaxPanelRows)
+// or the batch (prows = kPanel) schedules them.
+Schedules schedule(const cond_lu& f, int32_t prows) {
   Schedules s;
   const int32_t n = f.n;
   std::vector<double> udiag_rev(n);
   for (int32_t k = 0; k < n; ++k) udiag_rev[k] = f.u_diag[n - 1 - k];
-  s.t[0] = split_panels(f.l_rows);
+  s.t[0] = split_panels(f.l_rows, prows);
   invert_panels(s.t[0], nullptr);
   check_lists(s.t[0]);
-  s.t[1] = split_panels(reverse_order(f.u_rows));
+  s.t[1] = split_panels(reverse_order(f.u_rows), prows);
   invert_panels(s.t[1], udiag_rev.data());
   check_lists(s.t[1]);
-  s.t[2] = split_panels(f.u_cols);
+  s.t[2] = split_panels(f.u_cols, prows);
   invert_panels(s.t[2], f.u_diag.data());
   check_lists(s.t[2]);
-  s.t[3] = split_panels(reverse_order(f.l_cols));
+  s.t[3] = split_panels(reverse_order(f.l_cols), prows);
   invert_panels(s.t[3], nullptr);
   check_lists(s.t[3]);
   s.row_perm = f.row_perm;
@@ -164,15 +165,17 @@ void check_system(const HostCsr& a, unsigned long long seed, double bound) {
   EXPECT(at.nnz() == a.nnz(), "transpose size");
   cond_lu f;
   EXPECT(lu_factor(a, at, nullptr, 1e-6, f) == COND_OK, "lu_factor");
-  Schedules s = schedule(f);
-  Lcg g{seed};
-  std::vector<double> x(a.n), r, t;
-  for (double& v : x) v = g.next() - 0.5;
-  EXPECT(solve(s, x, r, t), "replay");
-  const double be_r = backward_error(a, false, r, x), be_t = backward_error(a, true, t, r);
-  std::printf("n=%d fill=%lld+%lld backward errors %.2e %.2e\n", a.n,
-              static_cast<long long>(f.l_rows.nnz()), static_cast<long long>(f.u_rows.nnz()), be_r, be_t);
-  EXPECT(be_r < bound && be_t < bound, "backward error");
+  for (int32_t prows : {kMaxPanelRows, kPanel}) {
+    Schedules s = schedule(f, prows);
+    Lcg g{seed};
+    std::vector<double> x(a.n), r, t;
+    for (double& v : x) v = g.next() - 0.5;
+    EXPECT(solve(s, x, r, t), "replay");
+    const double be_r = backward_error(a, false, r, x), be_t = backward_error(a, true, t, r);
+    std::printf("n=%d prows=%d fill=%lld+%lld backward errors %.2e %.2e\n", a.n, prows,
+                static_cast<long long>(f.l_rows.nnz()), static_cast<long long>(f.u_rows.nnz()), be_r, be_t);
+    EXPECT(be_r < bound && be_t < bound, "backward error");
+  }
 }
 
 }  // namespace
@@ -199,7 +202,7 @@ int main() {
     transpose(blocks[k], at);
     cond_lu f;
     EXPECT(lu_factor(blocks[k], at, nullptr, 1e-6, f) == COND_OK, "block lu");
-    parts.push_back(schedule(f));
+    parts.push_back(schedule(f, kPanel));
     total += blocks[k].n;
   }
   Schedules joined;
