@@ -367,19 +367,21 @@ __device__ __forceinline__ void publish(double* p, double v) {
 }
 
 // Sum of off-panel entries [p0, p1) of one row against the solved values,
-// by the 16 lanes of a row group (sub = 0..15); every lane of the group gets it.
+// by the LPR lanes of a row group (sub = 0..LPR-1); every lane of the group
+// gets it.
+template <int LPR = kLanesPerRow>
 __device__ __forceinline__ double row_sum(long long p0, long long p1, int sub,
                                           const int* __restrict__ col,
                                           const double* __restrict__ val, const double* out,
                                           RunState* st) {
   double acc = 0.0;
-  for (long long base = p0; base < p1; base += kLanesPerRow * kUnroll) {
+  for (long long base = p0; base < p1; base += LPR * kUnroll) {
     int j[kUnroll];
     double a[kUnroll];
     unsigned long long bits[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      const long long p = base + u * kLanesPerRow + sub;
+      const long long p = base + u * LPR + sub;
       const bool act = p < p1;
       j[u] = act ? col[p] : -1;
       a[u] = act ? val[p] : 0.0;
@@ -398,64 +400,8 @@ __device__ __forceinline__ double row_sum(long long p0, long long p1, int sub,
       if (j[u] >= 0) acc += a[u] * __longlong_as_double(static_cast<long long>(bits[u]));
   }
 #pragma unroll
-  for (int off = kLanesPerRow / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kLanesPerRow);
+  for (int off = LPR / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, LPR);
   return acc;
-}
-
-// Sums of up to NR rows of a row group at once (ranges [p0[j], p1[j]), empty
-// for absent rows), with the loads of all NR rows in flight together
-// (kUnroll / (2 NR) entries of each row per lane, within the register budget
-// of 1024-thread blocks).
-template <int NR>
-__device__ __forceinline__ void row_sums(const long long* p0, const long long* p1, int sub,
-                                         const int* __restrict__ col,
-                                         const double* __restrict__ val, const double* out,
-                                         RunState* st, double* acc) {
-  constexpr int U = kUnroll / NR / 2 > 0 ? kUnroll / NR / 2 : 1;
-  long long len = 0;
-#pragma unroll
-  for (int j = 0; j < NR; ++j) {
-    acc[j] = 0.0;
-    len = p1[j] - p0[j] > len ? p1[j] - p0[j] : len;
-  }
-  for (long long b = 0; b < len; b += kLanesPerRow * U) {
-    int jc[NR][U];
-    double a[NR][U];
-    unsigned long long bits[NR][U];
-#pragma unroll
-    for (int j = 0; j < NR; ++j)
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const long long p = p0[j] + b + u * kLanesPerRow + sub;
-        const bool act = p < p1[j];
-        jc[j][u] = act ? col[p] : -1;
-        a[j][u] = act ? val[p] : 0.0;
-      }
-#pragma unroll
-    for (int j = 0; j < NR; ++j)
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        bits[j][u] = jc[j][u] >= 0
-                         ? __hip_atomic_load(reinterpret_cast<const unsigned long long*>(out + jc[j][u]),
-                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)
-                         : 0ull;
-#pragma unroll
-    for (int j = 0; j < NR; ++j) {
-      bool pend = false;
-#pragma unroll
-      for (int u = 0; u < U; ++u) pend = pend || (jc[j][u] >= 0 && bits[j][u] == kPending);
-      if (pend) resolve_pending<U>(out, jc[j], bits[j], &st->abort_wait);
-    }
-#pragma unroll
-    for (int j = 0; j < NR; ++j)
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (jc[j][u] >= 0) acc[j] += a[j][u] * __longlong_as_double(static_cast<long long>(bits[j][u]));
-  }
-#pragma unroll
-  for (int j = 0; j < NR; ++j)
-#pragma unroll
-    for (int off = kLanesPerRow / 2; off > 0; off >>= 1) acc[j] += __shfl_xor(acc[j], off, kLanesPerRow);
 }
 
 // 16 bytes from src (16-byte aligned) into LDS at dst + 16 * (lane in its
@@ -470,13 +416,13 @@ __device__ __forceinline__ void copy16_to_lds(const double* src, double* dst) {
 __device__ __forceinline__ void wait_all_memory() { __builtin_amdgcn_s_waitcnt(0); }
 
 // A panel of up to R rows (R = kPanel or kMaxPanelRows) is solved by one
-// block: row group g (16 lanes) takes rows g + 64 j, j < R / 64.
-// Everything that does not depend on solved values -- the right-hand side
-// (into registers) and the panel's triangle's inverse (copied from memory
-// straight into LDS, 16 bytes per lane, without passing through registers)
-// -- is requested before the first wait, so that once the panel's inputs
-// are published only the off-panel sums and one product with the inverse
-// remain.
+// block: row r by the LPR = 1024 / R lanes of row group r (16 lanes for
+// 64-row panels, 8 for 128-row ones). Everything that does not depend on
+// solved values -- the right-hand side (into registers) and the panel's
+// triangle's inverse (copied from memory straight into LDS, 16 bytes per
+// lane, without passing through registers) -- is requested before the first
+// wait, so that once the panel's inputs are published only the off-panel
+// sums and one product with the inverse remain.
 constexpr int kLocalPerLane = kPanel / kLanesPerRow;  // inverse columns per lane of a 64-row panel
 constexpr int kLdW = kPanel + 1;  // LDS row stride of a staged 64-row inverse (padded against bank conflicts)
 
@@ -486,14 +432,14 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_k(TrsvArgs t, const double* _
                                                      double* __restrict__ scatter,
                                                      const int* __restrict__ scatter_perm,
                                                      unsigned* ticket, RunState* st) {
-  constexpr int NR = R / kPanel;        // rows per row group
-  constexpr int CPL = R / kLanesPerRow;  // inverse columns per lane
-  constexpr int kW = R * (R + 1) / 2;    // values of a packed R-row triangle (even)
-  static_assert(NR == 1 || NR == 2, "64- or 128-row panels");
+  constexpr int LPR = kTrsvBlock / R;  // lanes per row
+  constexpr int CPL = R / LPR;         // inverse columns per lane
+  constexpr int kW = R * (R + 1) / 2;  // values of a packed R-row triangle (even)
+  static_assert(LPR == 8 || LPR == 16, "64- or 128-row panels");
   static_assert(kW % 2 == 0, "whole 16-byte chunks");
   __shared__ double w_sh[kW];  // the panel's inverse, rows packed: (r, c) at r (r + 1) / 2 + c
-  __shared__ double t_sh[R];        // off-panel sums
-  __shared__ double b_sh[R];        // right-hand side of the panel's rows
+  __shared__ double t_sh[R];   // off-panel sums
+  __shared__ double b_sh[R];   // right-hand side of the panel's rows
   __shared__ unsigned task_sh;
   __shared__ int quit_sh;
   // one read for the whole block: abort_wait may change while blocks start
@@ -502,10 +448,9 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_k(TrsvArgs t, const double* _
               __hip_atomic_load(&st->abort_wait, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
   if (quit_sh) return;
-  const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int sub = lane & (kLanesPerRow - 1);
-  const int g = wave * (64 / kLanesPerRow) + lane / kLanesPerRow;  // this group's first row, 0..63
+  const int sub = threadIdx.x & (LPR - 1);
+  const int r = threadIdx.x / LPR;  // this group's row, 0..R-1
   // this block's task list (block b serves list b mod kTaskLists: on the
   // usual round-robin dispatch, one list per XCD) and its ticket counter
   const int lst = static_cast<int>(blockIdx.x % kTaskLists);
@@ -532,36 +477,18 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_k(TrsvArgs t, const double* _
     // flight together with the record, not after it)
     const long long* trp = t.task_rp + T * (R + 1);
     const long long* tsp = t.task_sp + T * R;
-    long long q0[NR], q1[NR];  // the group's rows g + 64 j: off-panel ranges
-#pragma unroll
-    for (int j = 0; j < NR; ++j) {
-      const int r = g + kPanel * j;
-      const long long a0 = trp[r], a1 = trp[r + 1];
-      q0[j] = r < cnt ? a0 : 0;
-      q1[j] = r < cnt ? a1 : 0;
-    }
+    const bool live = r < cnt;
+    const long long a0 = trp[r], a1 = trp[r + 1];
+    long long q0 = live ? a0 : 0, q1 = live ? a1 : 0;  // the row's off-panel range
     if (kind >= 0 && kind < S) {
-      // ---- slice task: partial off-panel sums over one slice of every row's
+      // ---- slice task: partial off-panel sums over one slice of the row's
       // older entries (the ones on rows before off_split; the finish step
       // adds the newest ones itself)
-#pragma unroll
-      for (int j = 0; j < NR; ++j) {
-        const int r = g + kPanel * j;
-        if (r < cnt) q1[j] = tsp[r];
-        const long long len = q1[j] - q0[j];
-        q1[j] = q0[j] + len * (kind + 1) / S;
-        q0[j] = q0[j] + len * kind / S;
-      }
-      double part[NR];
-      if (NR == 1 || cnt <= kPanel)
-        part[0] = row_sum(q0[0], q1[0], sub, t.off_col, t.off_val, out, st);
-      else
-        row_sums<NR>(q0, q1, sub, t.off_col, t.off_val, out, st, part);
-#pragma unroll
-      for (int j = 0; j < NR; ++j) {
-        const int r = g + kPanel * j;
-        if (r < cnt && sub == 0) publish(slots + static_cast<long long>(kind) * R + r, part[j]);
-      }
+      if (live) q1 = tsp[r];
+      const long long len = q1 - q0;
+      const long long s1 = q0 + len * (kind + 1) / S, s0 = q0 + len * kind / S;
+      const double part = row_sum<LPR>(s0, s1, sub, t.off_col, t.off_val, out, st);
+      if (live && sub == 0) publish(slots + static_cast<long long>(kind) * R + r, part);
       __syncthreads();  // task_sh is reused
       continue;
     }
@@ -577,86 +504,63 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_k(TrsvArgs t, const double* _
         if (c0 + static_cast<int>(threadIdx.x) < nch)
           copy16_to_lds(w + 2 * (c0 + threadIdx.x), w_sh + 2 * (c0 + wave * 64));
     }
-    double bval[NR];
-#pragma unroll
-    for (int j = 0; j < NR; ++j) {
-      const int r = g + kPanel * j;
-      bval[j] = (r < cnt && sub == 0) ? (rhs_perm ? rhs[rhs_perm[lo + r]] : rhs[lo + r]) : 0.0;
-    }
-    // ---- off-panel sums of every row (these wait for the panel's inputs)
-    double sums[NR];
+    const double bval = (live && sub == 0) ? (rhs_perm ? rhs[rhs_perm[lo + r]] : rhs[lo + r]) : 0.0;
+    // ---- off-panel sums of the row (these wait for the panel's inputs)
+    double sum;
     if (kind < 0) {
-      if (NR == 1 || cnt <= kPanel) {
-        sums[0] = row_sum(q0[0], q1[0], sub, t.off_col, t.off_val, out, st);
-#pragma unroll
-        for (int j = 1; j < NR; ++j) sums[j] = 0.0;
-      } else {
-        row_sums<NR>(q0, q1, sub, t.off_col, t.off_val, out, st, sums);
-      }
+      sum = row_sum<LPR>(q0, q1, sub, t.off_col, t.off_val, out, st);
     } else {
-      // finish: the 16 lanes of a row read its slice partials together (lane
-      // sub takes slices sub, sub + 16, ...), add them in that fixed order,
-      // then re-arm the slots they read for the next solve
+      // finish: the LPR lanes of a row read its slice partials together
+      // (lane sub takes slices sub, sub + LPR, ...), add them in that fixed
+      // order, then re-arm the slots they read for the next solve
+      double acc = 0.0;
+      if (live) {
+        constexpr int kSlotsPerLane = kMaxSlicesDev / LPR;
+        unsigned long long bits[kSlotsPerLane];
+        int so[kSlotsPerLane];  // slot offsets from the row's first slot
+        unsigned long long* sp = reinterpret_cast<unsigned long long*>(slots) + r;
 #pragma unroll
-      for (int j = 0; j < NR; ++j) {
-        const int r = g + kPanel * j;
-        double acc = 0.0;
-        if (r < cnt) {
-          constexpr int kSlotsPerLane = kMaxSlicesDev / kLanesPerRow;
-          unsigned long long bits[kSlotsPerLane];
-          int so[kSlotsPerLane];  // slot offsets from the row's first slot
-          unsigned long long* sp = reinterpret_cast<unsigned long long*>(slots) + r;
-#pragma unroll
-          for (int u = 0; u < kSlotsPerLane; ++u) {
-            const int k = sub + u * kLanesPerRow;
-            so[u] = k < S ? k * R : -1;
-            bits[u] = k < S ? __hip_atomic_load(sp + so[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                            : 0ull;
-          }
-          resolve_pending<kSlotsPerLane>(slots + r, so, bits, &st->abort_wait);
-#pragma unroll
-          for (int u = 0; u < kSlotsPerLane; ++u)
-            if (so[u] >= 0) {
-              acc += __longlong_as_double(static_cast<long long>(bits[u]));
-              __hip_atomic_store(sp + so[u], kPending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
+        for (int u = 0; u < kSlotsPerLane; ++u) {
+          const int k = sub + u * LPR;
+          so[u] = k < S ? k * R : -1;
+          bits[u] = k < S ? __hip_atomic_load(sp + so[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                          : 0ull;
         }
+        resolve_pending<kSlotsPerLane>(slots + r, so, bits, &st->abort_wait);
 #pragma unroll
-        for (int off = kLanesPerRow / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kLanesPerRow);
-        // the row's newest entries (on the panel just before this one): the
-        // finish step waits for them itself, one hop fewer on a chain
-        const double recent = r < cnt ? row_sum(tsp[r], trp[r + 1], sub, t.off_col, t.off_val, out, st)
-                                      : 0.0;
-        sums[j] = acc + recent;
+        for (int u = 0; u < kSlotsPerLane; ++u)
+          if (so[u] >= 0) {
+            acc += __longlong_as_double(static_cast<long long>(bits[u]));
+            __hip_atomic_store(sp + so[u], kPending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
       }
+#pragma unroll
+      for (int off = LPR / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, LPR);
+      // the row's newest entries (on the panel just before this one): the
+      // finish step waits for them itself, one hop fewer on a chain
+      const double recent = live ? row_sum<LPR>(tsp[r], trp[r + 1], sub, t.off_col, t.off_val, out, st)
+                                 : 0.0;
+      sum = acc + recent;
     }
-#pragma unroll
-    for (int j = 0; j < NR; ++j) {
-      const int r = g + kPanel * j;
-      if (r < cnt && sub == 0) {
-        t_sh[r] = sums[j];
-        b_sh[r] = bval[j];
-      }
+    if (live && sub == 0) {
+      t_sh[r] = sum;
+      b_sh[r] = bval;
     }
     wait_all_memory();  // the inverse's copies into LDS have landed
     __syncthreads();
-    // ---- x = W (b - sums), row r by its 16 lanes
+    // ---- x = W (b - sums), row r by its LPR lanes
+    double acc = 0.0;
 #pragma unroll
-    for (int j = 0; j < NR; ++j) {
-      const int r = g + kPanel * j;
-      double acc = 0.0;
+    for (int u = 0; u < CPL; ++u) {
+      const int c = sub + u * LPR;
+      if (c <= r && c < cnt) acc += w_sh[r * (r + 1) / 2 + c] * (b_sh[c] - t_sh[c]);
+    }
 #pragma unroll
-      for (int u = 0; u < CPL; ++u) {
-        const int c = sub + u * kLanesPerRow;
-        if (c <= r && c < cnt) acc += w_sh[r * (r + 1) / 2 + c] * (b_sh[c] - t_sh[c]);
-      }
-#pragma unroll
-      for (int off = kLanesPerRow / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kLanesPerRow);
-      if (r < cnt && sub == 0) {
-        const long long i = lo + r;
-        publish(out + i, acc);
-        if (scatter) scatter[scatter_perm[i]] = acc;
-      }
+    for (int off = LPR / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, LPR);
+    if (live && sub == 0) {
+      const long long i = lo + r;
+      publish(out + i, acc);
+      if (scatter) scatter[scatter_perm[i]] = acc;
     }
     __syncthreads();  // LDS and task_sh are reused
   }

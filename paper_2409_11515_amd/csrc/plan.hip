@@ -547,7 +547,7 @@ int cond_plan_create(const cond_csr_t* A, const cond_opts_t* o, cond_plan_t** ou
       // the four schedules are independent host work, one thread each; each
       // is the same computation as on one thread
       auto sched = [](const HostCsr& t, const double* diag) {
-        PanelCsr s = split_panels(t, kPanel);
+        PanelCsr s = split_panels(t, kMaxPanelRows);
         invert_panels(s, diag);
         return s;
       };
