@@ -88,6 +88,7 @@ struct cond_batch {
   PanelCsr pL, pU, pUt, pLt;
   std::vector<int32_t> row_perm, rev, scat_s, scat_r;  // scat_r: host replay only
   DevTri dL, dU, dUt, dLt;
+  BatchLists lists;  // the four solves' lists, compacted to the running matrices
   int64_t nnz_l = 0, nnz_u = 0;
   double lu_ms = 0.0;
   bool rearm_slots = false;  // a solve wait timed out: re-arm the slice slots first
@@ -98,7 +99,7 @@ struct cond_batch {
         live_pref, mat_live;
     size_t vec[7], parts[4], pairs, g;
     size_t tri[4][kTriSlots];
-    size_t row_perm, rev, scat_s, svec[4], tickets;
+    size_t row_perm, rev, scat_s, svec[4], tickets, cl_slots[4], cl_cnt;
   } o{};
 };
 
@@ -152,11 +153,14 @@ void enqueue_batch_min_iteration(cond_batch* b, const BatchArgs& a, const AdamPa
   int* stop = &a.g->stop_all;
   int* abort = &a.g->abort_wait;
   batch_launch_live(a, s);
+  // once a matrix has stopped, the solves walk only its running neighbours'
+  // tasks: the lists are cut down whenever the running set changes
+  batch_launch_compact(a, b->lists, s);
   batch_launch_normalise(a, b->grid, s);
   batch_launch_rearm(a, b->grid, s);
   // r = A^-1 x: L c = P x, U z = c (z reversed); s = A^-T r: U^T h = z,
   // L^T wv = h, w = P^T wv
-  const int* live = a.mat_live;
+  const int* live = &a.g->compact;
   launch_trsv_multi(K, b->dL, a.x, reinterpret_cast<const int*>(b->ws + b->o.row_perm), a.c,
                     nullptr, nullptr, a.tickets, stop, abort, live, s);
   const int* rev = reinterpret_cast<const int*>(b->ws + b->o.rev);
@@ -391,6 +395,8 @@ int cond_batch_create(const cond_csr_t* As, int32_t count, const cond_opts_t* o,
     b->o.scat_s = L.take(n * 4);
     for (int k = 0; k < 4; ++k) b->o.svec[k] = L.take(n * K * 8);
     b->o.tickets = L.take(4 * kSolveTickets * sizeof(unsigned));  // four solves' counters
+    for (int f = 0; f < 4; ++f) b->o.cl_slots[f] = L.take(tris[f]->task_slot.size() * 4);
+    b->o.cl_cnt = L.take(4 * kTaskLists * 4);
     off = L.off;
   }
   b->need = off;
@@ -487,6 +493,15 @@ int cond_batch_bind(cond_batch_t* b, void* workspace, size_t bytes, void* stream
     for (int k = 0; k < 4; ++k) *sv[k] = reinterpret_cast<double*>(b->ws + b->o.svec[k]);
     a.tickets = reinterpret_cast<unsigned*>(b->ws + b->o.tickets);
     BCHK(hipMemsetAsync(a.tickets, 0, 4 * kSolveTickets * sizeof(unsigned), b->stream));
+    BatchLists& l = b->lists;
+    l.cl_cnt = reinterpret_cast<int*>(b->ws + b->o.cl_cnt);
+    for (int f = 0; f < 4; ++f) {
+      l.slot_group[f] = devs[f]->slot_group;
+      std::copy(tris[f]->list_off.begin(), tris[f]->list_off.end(), l.list_off[f]);
+      l.cl_slots[f] = reinterpret_cast<int*>(b->ws + b->o.cl_slots[f]);
+      devs[f]->cl_slots = l.cl_slots[f];
+      devs[f]->cl_cnt = l.cl_cnt + f * kTaskLists;
+    }
   }
   BCHK(hipMemsetAsync(b->ws + b->o.vec[0], 0, b->nrows * kBatchK * 8, b->stream));
   // every pair running: the autotuner's products cover every tile

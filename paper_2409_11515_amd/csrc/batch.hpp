@@ -29,9 +29,11 @@ struct BatchPair {
 struct BatchGlobal {
   long long t_done;
   double b1t, b2t;
-  int nlive;       // tiles of the matrices that still have a running start
-  int stop_all;    // 1 once every pair has stopped (the solves then skip)
-  int abort_wait;  // 1 when a triangular-solve wait timed out
+  int nlive;         // tiles of the matrices that still have a running start
+  int stop_all;      // 1 once every pair has stopped (the solves then skip)
+  int abort_wait;    // 1 when a triangular-solve wait timed out
+  int live_changed;  // 1 when this update's running matrices differ from the last's
+  int compact;       // 1 while some matrix has stopped: the solves take compacted lists
   int pad_;
 };
 
@@ -65,6 +67,17 @@ struct BatchArgs {
   unsigned* tickets = nullptr;
 };
 
+// The four solves' task lists for the compaction: solve f's slots of list l
+// are [list_off[f][l], list_off[f][l+1]), slot_group[f] the matrix of each
+// slot; the compacted list l goes to cl_slots[f] from list_off[f][l] on, its
+// length to cl_cnt[f * kTaskLists + l].
+struct BatchLists {
+  const int* slot_group[4] = {};
+  int list_off[4][kTaskLists + 1] = {};
+  int* cl_slots[4] = {};
+  int* cl_cnt = nullptr;
+};
+
 void batch_launch_init(const BatchArgs& a, const double* x0, int grid, hipStream_t s);
 void batch_launch_live(const BatchArgs& a, hipStream_t s);
 void batch_launch_reduce(const BatchArgs& a, int mode, const AdamParams& p, hipStream_t s);
@@ -76,5 +89,8 @@ void batch_launch_pass2(const BatchArgs& a, const AdamParams& p, int grid, hipSt
 // (tile, start) from the mirrored tiles
 void batch_launch_rearm(const BatchArgs& a, int grid, hipStream_t s);
 void batch_launch_sumsq_rev(const BatchArgs& a, int grid, hipStream_t s);
+// When the running matrices changed and some matrix has stopped: cut each
+// list of each solve down to the slots of the running matrices, in order.
+void batch_launch_compact(const BatchArgs& a, const BatchLists& l, hipStream_t s);
 
 }  // namespace condest

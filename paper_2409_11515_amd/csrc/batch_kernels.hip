@@ -23,7 +23,6 @@ namespace condest {
 namespace {
 
 constexpr int kB = 256;
-constexpr int kElemBatch = 4;  // elements per thread in flight in the element kernels
 
 __device__ __forceinline__ double wsum(double v) {
 #pragma unroll
@@ -115,6 +114,10 @@ __global__ __launch_bounds__(kB) void b_init_k(BatchArgs a, const double* __rest
     }
     tile_partials<K>(acc, static_cast<int>(t), a.parts_xx);
   }
+  // no update of this run has seen the running matrices: the first one
+  // finds them changed (and cuts the solves' lists down if some have stopped)
+  if (blockIdx.x == 0 && a.mat_live)
+    for (int m = threadIdx.x; m < a.nmat; m += kB) a.mat_live[m] = -1;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     a.g->t_done = 0;
     a.g->b1t = 1.0;
@@ -129,8 +132,8 @@ __global__ __launch_bounds__(kB) void b_init_k(BatchArgs a, const double* __rest
 template <int K>
 __global__ __launch_bounds__(kB) void b_live_k(BatchArgs a) {
   __shared__ int run_sh[kB / K];
-  __shared__ int j_sh, u_sh;
-  if (threadIdx.x == 0) j_sh = u_sh = 0;
+  __shared__ int j_sh, u_sh, changed_sh;
+  if (threadIdx.x == 0) j_sh = u_sh = changed_sh = 0;
   // matrices in rounds of kB / K: one thread per pair reads its state, then
   // thread 0 appends the running matrices of the round in order
   for (int m0 = 0; m0 < a.nmat; m0 += kB / K) {
@@ -140,8 +143,10 @@ __global__ __launch_bounds__(kB) void b_live_k(BatchArgs a) {
     if (m < a.nmat && !a.pairs[static_cast<long long>(m) * K + threadIdx.x % K].stopped)
       run_sh[threadIdx.x / K] = 1;  // benign: every writer stores 1
     __syncthreads();
-    if (a.mat_live && threadIdx.x < kB / K && m0 + static_cast<int>(threadIdx.x) < a.nmat)
+    if (a.mat_live && threadIdx.x < kB / K && m0 + static_cast<int>(threadIdx.x) < a.nmat) {
+      if (a.mat_live[m0 + threadIdx.x] != run_sh[threadIdx.x]) changed_sh = 1;  // benign
       a.mat_live[m0 + threadIdx.x] = run_sh[threadIdx.x];
+    }
     if (threadIdx.x == 0) {
       int j = j_sh, u = u_sh;
       for (int q = 0; q < kB / K && m0 + q < a.nmat; ++q)
@@ -160,7 +165,47 @@ __global__ __launch_bounds__(kB) void b_live_k(BatchArgs a) {
     a.live_pref[j_sh] = u_sh;
     a.g->nlive = u_sh;
     a.g->stop_all = u_sh == 0 ? 1 : 0;
+    a.g->live_changed = changed_sh;
+    a.g->compact = j_sh < a.nmat ? 1 : 0;
   }
+}
+
+// ---------------------------------------------------------------- compaction
+// Block (f, l) cuts list l of solve f down to the slots of the running
+// matrices, keeping their order: 1024 slots at a time, each wave counts its
+// running slots by a ballot, the waves' counts are added in wave order, and
+// every running slot is written at its rank. Only when the running matrices
+// changed this update and some matrix has stopped; the solves then take the
+// compacted lists (each a subsequence of a list in dependency order, with
+// every task of the running matrices: the waits still end).
+constexpr int kCompactBlock = 1024;
+
+__global__ __launch_bounds__(kCompactBlock) void b_compact_k(BatchArgs a, BatchLists lists) {
+  if (!a.g->live_changed || !a.g->compact) return;
+  const int f = blockIdx.x / kTaskLists, l = blockIdx.x % kTaskLists;
+  const int q0 = lists.list_off[f][l], q1 = lists.list_off[f][l + 1];
+  const int* group = lists.slot_group[f];
+  int* out = lists.cl_slots[f];
+  __shared__ int wave_sh[kCompactBlock / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int base = 0;
+  for (int c = q0; c < q1; c += kCompactBlock) {
+    const int q = c + static_cast<int>(threadIdx.x);
+    const bool run = q < q1 && a.mat_live[group[q]];
+    const unsigned long long mask = __ballot(run);
+    const int before = __popcll(mask & ((1ull << lane) - 1ull));
+    if (lane == 0) wave_sh[wave] = __popcll(mask);
+    __syncthreads();
+    int wbase = 0, total = 0;
+    for (int w = 0; w < kCompactBlock / 64; ++w) {
+      if (w < wave) wbase += wave_sh[w];
+      total += wave_sh[w];
+    }
+    if (run) out[q0 + base + wbase + before] = q;
+    base += total;
+    __syncthreads();  // wave_sh is reused
+  }
+  if (threadIdx.x == 0) lists.cl_cnt[f * kTaskLists + l] = base;
 }
 
 // --------------------------------------------------------- per-matrix reduce
@@ -263,23 +308,10 @@ __global__ __launch_bounds__(kB) void b_normalise_k(BatchArgs a) {
     double acc = 0.0;
     if (!q.stopped) {
       const double nrm = q.nrm;
-      const long long e1 = r1 * K;
-      for (long long e0 = r0 * K + threadIdx.x; e0 < e1; e0 += kElemBatch * kB) {
-        double xs[kElemBatch];
-#pragma unroll
-        for (int u = 0; u < kElemBatch; ++u) {
-          const long long e = e0 + u * kB;
-          xs[u] = e < e1 ? a.x[e] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < kElemBatch; ++u) {
-          const long long e = e0 + u * kB;
-          if (e < e1) {
-            const double xi = xs[u] / nrm;
-            a.x[e] = xi;
-            acc += xi * xi;
-          }
-        }
+      for (long long e = r0 * K + threadIdx.x; e < r1 * K; e += kB) {
+        const double xi = a.x[e] / nrm;
+        a.x[e] = xi;
+        acc += xi * xi;
       }
     }
     tile_partials<K>(acc, static_cast<int>(t), a.parts_x);
@@ -291,14 +323,10 @@ __global__ __launch_bounds__(kB) void b_normalise_k(BatchArgs a) {
 // 32-row chunk and start t % K and walks that row: the K threads of a row
 // read the same column index and value (one transaction for all of them)
 // and K contiguous entries of X (64 bytes), so one read of the matrix serves
-// all starts, with no staging and no barrier inside a tile. A row's entries
-// are taken kRowBatch at a time, all of their loads issued before the first
-// product (a row of the stencil matrices fits in one or two such batches),
-// and the next row's pointers are loaded while this row is summed. Starts
-// that have stopped are skipped, and a tile whose matrix has no running
-// start is skipped entirely.
+// all starts, with no staging and no barrier inside a tile. Starts that have
+// stopped are skipped, and a tile whose matrix has no running start is
+// skipped entirely.
 constexpr int kChunkRowsB = kB / 8;  // 32 rows x 8 starts
-constexpr int kRowBatch = 8;
 
 template <int K>
 __global__ __launch_bounds__(kB) void b_spmm_k(BatchArgs a, const int* __restrict__ rowptr,
@@ -317,32 +345,25 @@ __global__ __launch_bounds__(kB) void b_spmm_k(BatchArgs a, const int* __restric
     const long long r0 = a.tiles[t], r1 = a.tiles[t + 1];
     double sq = 0.0;
     if (mine) {
-      long long r = r0 + rl;
-      int p0 = r < r1 ? rowptr[r] : 0, p1 = r < r1 ? rowptr[r + 1] : 0;
-      for (; r < r1; r += kChunkRowsB) {
-        const long long rn = r + kChunkRowsB;
-        const int n0 = rn < r1 ? rowptr[rn] : 0, n1 = rn < r1 ? rowptr[rn + 1] : 0;
+      for (long long r = r0 + rl; r < r1; r += kChunkRowsB) {
+        const int p0 = rowptr[r], p1 = rowptr[r + 1];
         double acc = 0.0;
-        for (int b = p0; b < p1; b += kRowBatch) {
-          int c[kRowBatch];
-          double v[kRowBatch], xv[kRowBatch];
-#pragma unroll
-          for (int u = 0; u < kRowBatch; ++u) {
-            const int q = b + u;
-            c[u] = q < p1 ? col[q] : -1;
-            v[u] = q < p1 ? val[q] : 0.0;
-          }
-#pragma unroll
-          for (int u = 0; u < kRowBatch; ++u)
-            xv[u] = c[u] >= 0 ? x[static_cast<long long>(c[u]) * K + k] : 0.0;
-#pragma unroll
-          for (int u = 0; u < kRowBatch; ++u)
-            if (c[u] >= 0) acc += v[u] * xv[u];
+        int q = p0;
+        for (; q + 4 <= p1; q += 4) {
+          const int c0 = col[q], c1 = col[q + 1], c2 = col[q + 2], c3 = col[q + 3];
+          const double v0 = val[q], v1 = val[q + 1], v2 = val[q + 2], v3 = val[q + 3];
+          const double x0 = x[static_cast<long long>(c0) * K + k];
+          const double x1 = x[static_cast<long long>(c1) * K + k];
+          const double x2 = x[static_cast<long long>(c2) * K + k];
+          const double x3 = x[static_cast<long long>(c3) * K + k];
+          acc += v0 * x0;
+          acc += v1 * x1;
+          acc += v2 * x2;
+          acc += v3 * x3;
         }
+        for (; q < p1; ++q) acc += val[q] * x[static_cast<long long>(col[q]) * K + k];
         y[r * K + k] = acc;
         sq += acc * acc;
-        p0 = n0;
-        p1 = n1;
       }
     }
     if (parts) tile_partials<K>(sq, static_cast<int>(t), parts);
@@ -366,37 +387,19 @@ __global__ __launch_bounds__(kB) void b_pass1_k(BatchArgs a, AdamParams p) {
     if (q.improved && a.xbest)
       for (long long e = r0 * K + threadIdx.x; e < r1 * K; e += kB) a.xbest[e] = a.x[e];
     if (!q.stopped) {
-      const double nx2 = q.nx2, ny2 = q.ny2, alpha = q.alpha;
-      const long long e1 = r1 * K;
-      // kElemBatch elements per thread in flight, each computed as alone and
-      // added in the thread's element order
-      for (long long e0 = r0 * K + threadIdx.x; e0 < e1; e0 += kElemBatch * kB) {
-        double xs[kElemBatch], ws[kElemBatch], ms[kElemBatch], vs[kElemBatch];
-#pragma unroll
-        for (int u = 0; u < kElemBatch; ++u) {
-          const long long e = e0 + u * kB;
-          xs[u] = e < e1 ? a.x[e] : 0.0;
-          ws[u] = e < e1 ? a.w[e] : 0.0;
-          ms[u] = e < e1 ? a.m[e] : 0.0;
-          vs[u] = e < e1 ? a.v[e] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < kElemBatch; ++u) {
-          const long long e = e0 + u * kB;
-          if (e < e1) {
-            const double xi = xs[u];
-            const double g = xi / nx2 - ws[u] / ny2;
-            const double mi = b1 * ms[u] + (1.0 - b1) * g;
-            const double vi = b2 * vs[u] + (1.0 - b2) * (g * g);
-            const double mh = mi / (1.0 - b1t);
-            const double vh = vi / (1.0 - b2t);
-            const double di = alpha * mh / (sqrt(vh) + p.eps);
-            a.m[e] = mi;
-            a.v[e] = vi;
-            a.d[e] = di;
-            acc += xi * di;
-          }
-        }
+      const double nx2 = q.nx2, ny2 = q.ny2;
+      for (long long e = r0 * K + threadIdx.x; e < r1 * K; e += kB) {
+        const double xi = a.x[e];
+        const double g = xi / nx2 - a.w[e] / ny2;
+        const double mi = b1 * a.m[e] + (1.0 - b1) * g;
+        const double vi = b2 * a.v[e] + (1.0 - b2) * (g * g);
+        const double mh = mi / (1.0 - b1t);
+        const double vh = vi / (1.0 - b2t);
+        const double di = q.alpha * mh / (sqrt(vh) + p.eps);
+        a.m[e] = mi;
+        a.v[e] = vi;
+        a.d[e] = di;
+        acc += xi * di;
       }
     }
     tile_partials<K>(acc, static_cast<int>(t), a.parts_xd);
@@ -417,26 +420,12 @@ __global__ __launch_bounds__(kB) void b_pass2_k(BatchArgs a, AdamParams p) {
     double acc = 0.0;
     if (!q.stopped) {
       const double xd = q.xd;
-      const long long e1 = r1 * K;
-      for (long long e0 = r0 * K + threadIdx.x; e0 < e1; e0 += kElemBatch * kB) {
-        double xs[kElemBatch], ds[kElemBatch];
-#pragma unroll
-        for (int u = 0; u < kElemBatch; ++u) {
-          const long long e = e0 + u * kB;
-          xs[u] = e < e1 ? a.x[e] : 0.0;
-          ds[u] = e < e1 ? a.d[e] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < kElemBatch; ++u) {
-          const long long e = e0 + u * kB;
-          if (e < e1) {
-            const double xi = xs[u];
-            const double dd = ds[u] - xd * xi;
-            const double xn = xi - dd;
-            a.x[e] = xn;
-            acc += xn * xn;
-          }
-        }
+      for (long long e = r0 * K + threadIdx.x; e < r1 * K; e += kB) {
+        const double xi = a.x[e];
+        const double dd = a.d[e] - xd * xi;
+        const double xn = xi - dd;
+        a.x[e] = xn;
+        acc += xn * xn;
       }
     }
     tile_partials<K>(acc, static_cast<int>(t), a.parts_xx);
@@ -526,6 +515,9 @@ void batch_launch_pass2(const BatchArgs& a, const AdamParams& p, int grid, hipSt
 
 void batch_launch_rearm(const BatchArgs& a, int grid, hipStream_t s) {
   b_rearm_k<<<grid, kB, 0, s>>>(a);
+}
+void batch_launch_compact(const BatchArgs& a, const BatchLists& l, hipStream_t s) {
+  b_compact_k<<<4 * kTaskLists, kCompactBlock, 0, s>>>(a, l);
 }
 void batch_launch_sumsq_rev(const BatchArgs& a, int grid, hipStream_t s) {
   b_sumsq_rev_k<kBatchK><<<grid, kB, 0, s>>>(a);

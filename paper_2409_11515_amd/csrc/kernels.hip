@@ -646,17 +646,19 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_multi_k(TrsvArgs t, const dou
                                                            double* out, double* __restrict__ scatter,
                                                            const int* __restrict__ scatter_perm,
                                                            unsigned* ticket, const int* stop,
-                                                           int* abort, const int* group_live) {
+                                                           int* abort, const int* compact) {
   constexpr int EL = kLanesPerRow / K;
   static_assert(EL >= 1 && EL * K == kLanesPerRow, "K divides the 16 lanes of a row");
   __shared__ double w_sh[kPanel * kLdW];  // the sub-panel triangle's inverse, row-major
   __shared__ double t_sh[kPanel * K];     // off-panel sums, row r side k at r * K + k
   __shared__ double b_sh[kPanel * K];     // right-hand sides
   __shared__ unsigned task_sh;
-  __shared__ int quit_sh;
-  if (threadIdx.x == 0)
+  __shared__ int quit_sh, compact_sh;
+  if (threadIdx.x == 0) {
     quit_sh = (stop && *stop) ||
               __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    compact_sh = compact && *compact;
+  }
   __syncthreads();
   if (quit_sh) return;
   const int lane = threadIdx.x & 63;
@@ -664,27 +666,20 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_multi_k(TrsvArgs t, const dou
   const int sub = lane & (kLanesPerRow - 1);
   const int es = sub / K, kk = sub % K;
   const int g = wave * (64 / kLanesPerRow) + lane / kLanesPerRow;  // this group's row, 0..63
-  const int lst = static_cast<int>(blockIdx.x % kTaskLists);  // as in trsv_k
+  // as in trsv_k; while the batch compacts its lists, list lst holds only
+  // the slots of the blocks (matrices) that still run, in the same order
+  const int lst = static_cast<int>(blockIdx.x % kTaskLists);
   const int l0 = t.list_off[lst];
-  const unsigned lcount = static_cast<unsigned>(t.list_off[lst + 1] - l0);
+  const bool cmp = compact_sh != 0;
+  const unsigned lcount = static_cast<unsigned>(cmp ? t.cl_cnt[lst] : t.list_off[lst + 1] - l0);
   unsigned* const ctr = ticket + lst * kTicketStride;
   for (;;) {
     if (threadIdx.x == 0) task_sh = atomicAdd(ctr, 1u);
     __syncthreads();
     if (task_sh >= lcount) break;
-    const long long T = l0 + static_cast<long long>(task_sh);  // the task's slot
-    // a block (matrix) whose starts have all stopped: nothing reads its
-    // values, so the rest of its list's run of tasks at this level is
-    // skipped at once (the counter jumps past it; tickets already handed out
-    // inside the run are skipped by their holders the same way)
-    if (group_live && !group_live[t.slot_group[T]]) {
-      if (threadIdx.x == 0) atomicMax(ctr, static_cast<unsigned>(t.slot_seg_end[T]));
-      __syncthreads();  // task_sh is reused
-      continue;
-    }
+    const long long T = cmp ? t.cl_slots[l0 + task_sh] : l0 + static_cast<long long>(task_sh);
     const int4 ra = reinterpret_cast<const int4*>(t.task_rec)[2 * T];
     const int4 rb = reinterpret_cast<const int4*>(t.task_rec)[2 * T + 1];
-    const int P = ra.x;
     const int kind = ra.y;  // -1 whole panel, 0..S-1 slice, S finish
     const long long lo = ra.z;
     const int cnt = ra.w;
@@ -1101,20 +1096,20 @@ void launch_trsv(const DevTri& t, const double* rhs, const int* rhs_perm, double
 
 void launch_trsv_multi(int K, const DevTri& t, const double* rhs, const int* rhs_perm, double* out,
                        double* scatter, const int* scatter_perm, unsigned* ticket, const int* stop,
-                       int* abort, const int* group_live, hipStream_t s) {
+                       int* abort, const int* compact, hipStream_t s) {
   const int g = trsv_grid(t.ntasks);
   switch (K) {
     case 2:
       trsv_multi_k<2><<<g, kTrsvBlock, 0, s>>>(t, rhs, rhs_perm, out, scatter, scatter_perm, ticket,
-                                               stop, abort, group_live);
+                                               stop, abort, compact);
       break;
     case 4:
       trsv_multi_k<4><<<g, kTrsvBlock, 0, s>>>(t, rhs, rhs_perm, out, scatter, scatter_perm, ticket,
-                                               stop, abort, group_live);
+                                               stop, abort, compact);
       break;
     default:
       trsv_multi_k<8><<<g, kTrsvBlock, 0, s>>>(t, rhs, rhs_perm, out, scatter, scatter_perm, ticket,
-                                               stop, abort, group_live);
+                                               stop, abort, compact);
       break;
   }
 }

@@ -111,15 +111,17 @@ struct DevTri {
   // 0..S-1 slice, S finish), first row, rows, slices S, first partial-sum
   // slot, offset of the panel's inverse in winv (low and high 32 bits)
   const int* task_rec = nullptr;
-  // per slot: off-panel row pointers of its rows (kPanelRows + 1 values,
-  // padded) and their split points (kPanelRows values)
+  // per slot: off-panel row pointers of its rows (prows + 1 values,
+  // padded) and their split points (prows values)
   const long long* task_rp = nullptr;
   const long long* task_sp = nullptr;
-  // joined schedules (a batch), per slot: the block (matrix), and one past
-  // the end of its list's run of same-block same-level slots, counted from
-  // the list's first slot; or null
+  // joined schedules (a batch): the block (matrix) of each slot, and the
+  // lists cut down to the slots of the blocks that still run (list l's at
+  // cl_slots[list_off[l] ..], cl_cnt[l] of them), used while the batch's
+  // compaction flag is set; or null
   const int* slot_group = nullptr;
-  const int* slot_seg_end = nullptr;
+  const int* cl_slots = nullptr;
+  const int* cl_cnt = nullptr;
 };
 using TrsvArgs = DevTri;
 
@@ -154,12 +156,13 @@ void launch_trsv(const DevTri& t, const double* rhs, const int* rhs_perm, double
 // The same solve for K in {2, 4, 8} interleaved right-hand sides (row i,
 // side k at i * K + k; rhs, out and scatter in that layout, the permutations
 // over rows). t.partials must hold K values per slot row. Skipped when *stop
-// (may be null) is non-zero; a timed-out wait sets *abort. With group_live
-// and t.task_group, the tasks of a block whose flag is 0 are skipped (the
-// blocks of a joined schedule never read each other's values).
+// (may be null) is non-zero; a timed-out wait sets *abort. While *compact
+// (may be null) is non-zero the tasks come from t's compacted lists (the
+// blocks of a joined schedule that still run; they never read the others'
+// values).
 void launch_trsv_multi(int K, const DevTri& t, const double* rhs, const int* rhs_perm, double* out,
                        double* scatter, const int* scatter_perm, unsigned* ticket, const int* stop,
-                       int* abort, const int* group_live, hipStream_t s);
+                       int* abort, const int* compact, hipStream_t s);
 void launch_pass1(int n, const double* x, const double* w, double* m, double* v, double* d,
                   double* xbest, const double* parts_x, const double* parts_y, int grid,
                   double* parts_xd, RunState* st, double* trace, const AdamParams& p,

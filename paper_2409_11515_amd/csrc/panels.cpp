@@ -121,7 +121,7 @@ double cut_cost(const HostCsr& t, const std::vector<int32_t>& pstart) {
 // dealt round-robin to kTaskLists lists in dependency order (so each list is
 // in dependency order, and each holds about 1/kTaskLists of every level),
 // then the records, row pointers and split points (and, for joined
-// schedules, the blocks and runs) are laid out list after list. Built from
+// schedules, the blocks) are laid out list after list. Built from
 // the tasks, panels and inverse offsets alone.
 void finish_records(PanelCsr& s) {
   const size_t ntasks = s.task_panel.size();
@@ -148,22 +148,9 @@ void finish_records(PanelCsr& s) {
     for (int32_t r = 0; r < cnt; ++r) s.task_sp[q * R + r] = s.off_split[lo + r];
   }
   s.slot_group.clear();
-  s.slot_seg_end.clear();
   if (s.task_group.empty()) return;
   s.slot_group.assign(ntasks, 0);
-  std::vector<int32_t> level(ntasks, 0);
-  for (size_t k = 0; k < ntasks; ++k) {
-    s.slot_group[s.task_slot[k]] = s.task_group[k];
-    level[s.task_slot[k]] = s.task_level[k];
-  }
-  s.slot_seg_end.assign(ntasks, 0);
-  for (int l = 0; l < kTaskLists; ++l) {
-    const int32_t q0 = s.list_off[l], q1 = s.list_off[l + 1];
-    for (int32_t q = q1; q-- > q0;) {
-      const bool last = q + 1 == q1 || s.slot_group[q + 1] != s.slot_group[q] || level[q + 1] != level[q];
-      s.slot_seg_end[q] = last ? q + 1 - q0 : s.slot_seg_end[q + 1];
-    }
-  }
+  for (size_t k = 0; k < ntasks; ++k) s.slot_group[s.task_slot[k]] = s.task_group[k];
 }
 
 }  // namespace
@@ -436,7 +423,6 @@ void tri_layout(const PanelCsr& t, int K, Layout& L, size_t* o) {
   o[kTaskRp] = L.take(t.task_rp.size() * 8);
   o[kTaskSp] = L.take(t.task_sp.size() * 8);
   o[kSlotGroup] = L.take(t.slot_group.size() * 4);
-  o[kSlotSegEnd] = L.take(t.slot_seg_end.size() * 4);
 }
 
 }  // namespace condest

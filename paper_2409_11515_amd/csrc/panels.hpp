@@ -27,7 +27,7 @@ struct Layout {
 // Device arrays of one solve's panel structure (offsets into the workspace).
 enum TriSlot {
   kOffRp, kOffCol, kOffVal, kOffSplit, kPartials, kWinv, kWoff, kTaskRec, kTaskRp, kTaskSp,
-  kSlotGroup, kSlotSegEnd, kTriSlots
+  kSlotGroup, kTriSlots
 };
 
 // A strictly lower-triangular factor in solve order, cut into panels of at
@@ -57,10 +57,9 @@ struct PanelCsr {
   // (prows values, 0 past the end), so a block loads them together
   // with the record instead of after it
   std::vector<int64_t> task_rp, task_sp;
-  // joined schedules, per slot: the block, and one past the end of the run
-  // of consecutive slots of its list with the same block and level, counted
-  // from the list's first slot (a dead block's run is skipped at once)
-  std::vector<int32_t> slot_group, slot_seg_end;
+  // joined schedules, per slot: the block (a batch keeps each list's slots
+  // of the blocks that still run)
+  std::vector<int32_t> slot_group;
   // inverse of each panel's triangle, lower rows packed ((r, c) at
   // r (r + 1) / 2 + c); panel p's at winv[woff[p]]
   std::vector<double> winv;

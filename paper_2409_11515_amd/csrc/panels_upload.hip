@@ -20,7 +20,6 @@ int tri_upload(char* ws, const size_t* off, const PanelCsr& t, int K, hipStream_
   if (e == hipSuccess) e = up(kTaskRp, t.task_rp.data(), t.task_rp.size() * 8);
   if (e == hipSuccess) e = up(kTaskSp, t.task_sp.data(), t.task_sp.size() * 8);
   if (e == hipSuccess) e = up(kSlotGroup, t.slot_group.data(), t.slot_group.size() * 4);
-  if (e == hipSuccess) e = up(kSlotSegEnd, t.slot_seg_end.data(), t.slot_seg_end.size() * 4);
   if (e != hipSuccess) return fail(COND_EHIP, std::string("solve upload: ") + hipGetErrorString(e));
   auto at = [&](int slot) { return ws + off[slot]; };
   if (t.nslots > 0)
@@ -38,7 +37,6 @@ int tri_upload(char* ws, const size_t* off, const PanelCsr& t, int K, hipStream_
   out.task_rp = reinterpret_cast<const long long*>(at(kTaskRp));
   out.task_sp = reinterpret_cast<const long long*>(at(kTaskSp));
   out.slot_group = t.slot_group.empty() ? nullptr : reinterpret_cast<const int*>(at(kSlotGroup));
-  out.slot_seg_end = t.slot_seg_end.empty() ? nullptr : reinterpret_cast<const int*>(at(kSlotSegEnd));
   out.ntasks = static_cast<int>(t.task_panel.size());
   for (int l = 0; l <= kTaskLists; ++l) out.list_off[l] = t.list_off[l];
   return COND_OK;

@@ -231,23 +231,20 @@ int main() {
       EXPECT(row >= lo && row < hi, "task group");
       EXPECT(J.slot_group[J.task_slot[q]] == g, "slot group");
     }
-    // in each list, the run of same-block same-level slots ends at
-    // slot_seg_end (counted from the list's first slot)
+    // a list cut down to some blocks' slots still runs: each list is in
+    // level order, and a block's rows read only columns of the same block
     std::vector<int32_t> slot_task(J.task_panel.size());
     for (size_t q = 0; q < J.task_panel.size(); ++q) slot_task[J.task_slot[q]] = static_cast<int32_t>(q);
-    for (int l = 0; l < kTaskLists; ++l) {
-      const int32_t q0 = J.list_off[l], q1 = J.list_off[l + 1];
-      for (int32_t q = q0; q < q1; ++q) {
-        const int32_t e = J.slot_seg_end[q];
-        EXPECT(e > q - q0 && e <= q1 - q0, "seg end range");
-        for (int32_t u = q; u < q0 + e; ++u)
-          EXPECT(J.slot_group[u] == J.slot_group[q] &&
-                     J.task_level[slot_task[u]] == J.task_level[slot_task[q]],
-                 "seg end run");
-        EXPECT(q0 + e == q1 || J.slot_group[q0 + e] != J.slot_group[q] ||
-                   J.task_level[slot_task[q0 + e]] != J.task_level[slot_task[q]],
-               "seg end is the run's end");
-      }
+    for (int l = 0; l < kTaskLists; ++l)
+      for (int32_t q = J.list_off[l] + 1; q < J.list_off[l + 1]; ++q)
+        EXPECT(J.task_level[slot_task[q - 1]] <= J.task_level[slot_task[q]], "list level order");
+    for (size_t q = 0; q < J.task_panel.size(); ++q) {
+      const int32_t g = J.task_group[q];
+      const int64_t lo = reversed ? total - row0[g + 1] : row0[g];
+      const int32_t p = J.task_panel[q];
+      for (int32_t i = J.pstart[p]; i < J.pstart[p + 1]; ++i)
+        for (int64_t e = J.off_rp[i]; e < J.off_rp[i + 1]; ++e)
+          EXPECT(J.off_col[e] >= lo && J.off_col[e] < J.pstart[p], "block-local columns");
     }
   }
   joined.row_perm.resize(total);
