@@ -50,23 +50,34 @@ __device__ __forceinline__ void tile_range(int ntiles, long long& t0, long long&
 }
 
 // The tiles of the matrices that still have a running start ("live" tiles),
-// numbered u = 0..nlive-1 in matrix order, are split over the blocks in
-// contiguous, XCD-aware ranges; live tile u maps to tile
-// mat_tile0[live_mat[j]] + (u - live_pref[j]) for the j with
-// live_pref[j] <= u < live_pref[j+1]. Once every start of a matrix has
-// stopped, no element kernel visits its tiles again.
+// numbered u = 0..nlive-1 in matrix order, are split over the XCDs in
+// contiguous eighths, and inside an XCD dealt to its blocks round-robin
+// (block j of the XCD takes live tiles j, j + g/8, ...), so the blocks of one
+// XCD sweep neighbouring rows together and share the gathered vector entries
+// in that XCD's L2; live tile u maps to tile mat_tile0[live_mat[j]] +
+// (u - live_pref[j]) for the j with live_pref[j] <= u < live_pref[j+1].
+// Once every start of a matrix has stopped, no element kernel visits its
+// tiles again.
 struct LiveTiles {
   long long u, u1;
-  int j;
+  int j, step;
   __device__ __forceinline__ void begin(const BatchArgs& a) {
-    const int n = a.g->nlive;
+    const long long n = a.g->nlive;
     const int b = blockIdx.x, g = gridDim.x;
-    const int lb = (g % 8 == 0) ? (b % 8) * (g / 8) + b / 8 : b;
-    u = static_cast<long long>(n) * lb / g;
-    u1 = static_cast<long long>(n) * (lb + 1) / g;
+    if (g % 8 == 0) {
+      const int x = b % 8;
+      u = n * x / 8 + b / 8;
+      u1 = n * (x + 1) / 8;
+      step = g / 8;
+    } else {
+      u = b;
+      u1 = n;
+      step = g;
+    }
     j = 0;
   }
-  // the tile of live index u (advancing j), or -1 past the block's range
+  __device__ __forceinline__ void next() { u += step; }
+  // the tile of live index u (advancing j), or -1 past the block's share
   __device__ __forceinline__ long long tile(const BatchArgs& a) {
     if (u >= u1) return -1;
     while (u >= a.live_pref[j + 1]) ++j;
@@ -301,7 +312,7 @@ __global__ __launch_bounds__(kB) void b_normalise_k(BatchArgs a) {
   LiveTiles lt;
   lt.begin(a);
   const int k = threadIdx.x % K;
-  for (long long t = lt.tile(a); t >= 0; ++lt.u, t = lt.tile(a)) {
+  for (long long t = lt.tile(a); t >= 0; lt.next(), t = lt.tile(a)) {
     const int mat = a.tile_mat[t];
     const BatchPair& q = a.pairs[static_cast<long long>(mat) * K + k];
     const long long r0 = a.tiles[t], r1 = a.tiles[t + 1];
@@ -319,14 +330,18 @@ __global__ __launch_bounds__(kB) void b_normalise_k(BatchArgs a) {
 }
 
 // -------------------------------------------------------------------- spmm
-// Y = M X for K interleaved starts. Thread t of a block takes row t / K of a
-// 32-row chunk and start t % K and walks that row: the K threads of a row
-// read the same column index and value (one transaction for all of them)
-// and K contiguous entries of X (64 bytes), so one read of the matrix serves
-// all starts, with no staging and no barrier inside a tile. Starts that have
-// stopped are skipped, and a tile whose matrix has no running start is
-// skipped entirely.
+// Y = M X for K interleaved starts. A tile's column indices, values and row
+// pointers are first copied into LDS by coalesced streaming loads (when the
+// tile has at most kSpmmStage entries; a larger tile reads them from memory
+// row by row). Thread t then takes row t / K of a 32-row chunk and start
+// t % K and walks that row: the K threads of a row read the same staged
+// index and value and K contiguous entries of X (64 bytes), so one read of
+// the matrix serves all starts. Starts that have stopped are skipped, and a
+// tile whose matrix has no running start is skipped entirely. Y is written
+// with streaming stores (nothing reads it before the next kernel).
 constexpr int kChunkRowsB = kB / 8;  // 32 rows x 8 starts
+constexpr int kSpmmStage = 1536;     // entries staged per tile (18 KB of LDS)
+constexpr int kTileMaxRows = 256;    // the largest row tile the autotuner tries
 
 template <int K>
 __global__ __launch_bounds__(kB) void b_spmm_k(BatchArgs a, const int* __restrict__ rowptr,
@@ -335,37 +350,55 @@ __global__ __launch_bounds__(kB) void b_spmm_k(BatchArgs a, const int* __restric
                                                const double* __restrict__ x, double* __restrict__ y,
                                                double* __restrict__ parts) {
 #pragma clang fp contract(off)  // products rounded, then added in entry order, as in the plain SpMV
+  __shared__ int c_sh[kSpmmStage];
+  __shared__ double v_sh[kSpmmStage];
+  __shared__ int rp_sh[kTileMaxRows + 1];
   LiveTiles lt;
   lt.begin(a);
   const int k = threadIdx.x % K;
   const int rl = threadIdx.x / K;  // row of this thread inside a chunk
-  for (long long t = lt.tile(a); t >= 0; ++lt.u, t = lt.tile(a)) {
+  for (long long t = lt.tile(a); t >= 0; lt.next(), t = lt.tile(a)) {
     const int mat = a.tile_mat[t];
     const bool mine = !a.pairs[static_cast<long long>(mat) * K + k].stopped;
     const long long r0 = a.tiles[t], r1 = a.tiles[t + 1];
+    const int e0 = rowptr[r0];
+    const int ne = rowptr[r1] - e0;
+    const bool staged = ne <= kSpmmStage && r1 - r0 <= kTileMaxRows;
+    if (staged) {
+      for (int e = threadIdx.x; e < ne; e += kB) {
+        c_sh[e] = __builtin_nontemporal_load(col + e0 + e);
+        v_sh[e] = __builtin_nontemporal_load(val + e0 + e);
+      }
+      for (int i = threadIdx.x; i <= r1 - r0; i += kB) rp_sh[i] = rowptr[r0 + i] - e0;
+    }
+    __syncthreads();
     double sq = 0.0;
     if (mine) {
       for (long long r = r0 + rl; r < r1; r += kChunkRowsB) {
-        const int p0 = rowptr[r], p1 = rowptr[r + 1];
         double acc = 0.0;
-        int q = p0;
-        for (; q + 4 <= p1; q += 4) {
-          const int c0 = col[q], c1 = col[q + 1], c2 = col[q + 2], c3 = col[q + 3];
-          const double v0 = val[q], v1 = val[q + 1], v2 = val[q + 2], v3 = val[q + 3];
-          const double x0 = x[static_cast<long long>(c0) * K + k];
-          const double x1 = x[static_cast<long long>(c1) * K + k];
-          const double x2 = x[static_cast<long long>(c2) * K + k];
-          const double x3 = x[static_cast<long long>(c3) * K + k];
-          acc += v0 * x0;
-          acc += v1 * x1;
-          acc += v2 * x2;
-          acc += v3 * x3;
+        if (staged) {
+          const int p0 = rp_sh[r - r0], p1 = rp_sh[r - r0 + 1];
+          int q = p0;
+          for (; q + 4 <= p1; q += 4) {
+            const double x0 = x[static_cast<long long>(c_sh[q]) * K + k];
+            const double x1 = x[static_cast<long long>(c_sh[q + 1]) * K + k];
+            const double x2 = x[static_cast<long long>(c_sh[q + 2]) * K + k];
+            const double x3 = x[static_cast<long long>(c_sh[q + 3]) * K + k];
+            acc += v_sh[q] * x0;
+            acc += v_sh[q + 1] * x1;
+            acc += v_sh[q + 2] * x2;
+            acc += v_sh[q + 3] * x3;
+          }
+          for (; q < p1; ++q) acc += v_sh[q] * x[static_cast<long long>(c_sh[q]) * K + k];
+        } else {
+          const int p0 = rowptr[r], p1 = rowptr[r + 1];
+          for (int q = p0; q < p1; ++q) acc += val[q] * x[static_cast<long long>(col[q]) * K + k];
         }
-        for (; q < p1; ++q) acc += val[q] * x[static_cast<long long>(col[q]) * K + k];
-        y[r * K + k] = acc;
+        __builtin_nontemporal_store(acc, y + r * K + k);
         sq += acc * acc;
       }
     }
+    __syncthreads();  // the staged tile is replaced next
     if (parts) tile_partials<K>(sq, static_cast<int>(t), parts);
   }
 }
@@ -379,7 +412,7 @@ __global__ __launch_bounds__(kB) void b_pass1_k(BatchArgs a, AdamParams p) {
   const int k = threadIdx.x % K;
   const double b1 = p.beta1, b2 = p.beta2;
   const double b1t = a.g->b1t * b1, b2t = a.g->b2t * b2;
-  for (long long t = lt.tile(a); t >= 0; ++lt.u, t = lt.tile(a)) {
+  for (long long t = lt.tile(a); t >= 0; lt.next(), t = lt.tile(a)) {
     const int mat = a.tile_mat[t];
     const BatchPair& q = a.pairs[static_cast<long long>(mat) * K + k];
     const long long r0 = a.tiles[t], r1 = a.tiles[t + 1];
@@ -413,7 +446,7 @@ __global__ __launch_bounds__(kB) void b_pass2_k(BatchArgs a, AdamParams p) {
   LiveTiles lt;
   lt.begin(a);
   const int k = threadIdx.x % K;
-  for (long long t = lt.tile(a); t >= 0; ++lt.u, t = lt.tile(a)) {
+  for (long long t = lt.tile(a); t >= 0; lt.next(), t = lt.tile(a)) {
     const int mat = a.tile_mat[t];
     const BatchPair& q = a.pairs[static_cast<long long>(mat) * K + k];
     const long long r0 = a.tiles[t], r1 = a.tiles[t + 1];
@@ -452,7 +485,7 @@ __global__ __launch_bounds__(kB) void b_rearm_k(BatchArgs a) {
   unsigned long long* wv = reinterpret_cast<unsigned long long*>(a.wv);
   LiveTiles lt;
   lt.begin(a);
-  for (long long t = lt.tile(a); t >= 0; ++lt.u, t = lt.tile(a)) {
+  for (long long t = lt.tile(a); t >= 0; lt.next(), t = lt.tile(a)) {
     const long long r0 = a.tiles[t], r1 = a.tiles[t + 1];
     const long long m0 = a.nrows - r1;  // the mirrored rows
     for (long long e = threadIdx.x; e < (r1 - r0) * kBatchK; e += kB) {
@@ -472,7 +505,7 @@ __global__ __launch_bounds__(kB) void b_sumsq_rev_k(BatchArgs a) {
   LiveTiles lt;
   lt.begin(a);
   const int k = threadIdx.x % K;
-  for (long long t = lt.tile(a); t >= 0; ++lt.u, t = lt.tile(a)) {
+  for (long long t = lt.tile(a); t >= 0; lt.next(), t = lt.tile(a)) {
     const int mat = a.tile_mat[t];
     const BatchPair& q = a.pairs[static_cast<long long>(mat) * K + k];
     const long long r0 = a.nrows - a.tiles[t + 1], r1 = a.nrows - a.tiles[t];
