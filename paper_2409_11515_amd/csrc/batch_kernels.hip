@@ -232,9 +232,19 @@ __global__ __launch_bounds__(kB) void b_reduce_k(BatchArgs a, int mode, AdamPara
   for (int src = 0; src < (mode == 1 ? 2 : 1); ++src) {
     const double* parts = src == 0 ? src0 : a.parts_y;
     // thread layout: K starts x (kB / K) strided tiles, then a fixed-order combine
+    // (eight loads issued before their eight additions, in the same order)
+    constexpr int S = kB / K;
     const int k = threadIdx.x % K, lane_t = threadIdx.x / K;
     double acc = 0.0;
-    for (int t = t0 + lane_t; t < t1; t += kB / K) acc += parts[static_cast<long long>(t) * K + k];
+    int t = t0 + lane_t;
+    for (; t + 7 * S < t1; t += 8 * S) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = parts[static_cast<long long>(t + u * S) * K + k];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    for (; t < t1; t += S) acc += parts[static_cast<long long>(t) * K + k];
     __shared__ double red[kB];
     red[threadIdx.x] = acc;
     __syncthreads();
