@@ -122,3 +122,36 @@ def test_batched_kappa_matches_oracle_with_a_201_system(torch_cuda):
                        for k in range(8))
         assert res[i]["kappa"] == pytest.approx(best_max * best_inv, rel=1e-3), i
         assert res[i]["status_max"] == 0 and res[i]["status_min"] == 0
+
+
+def test_running_matrix_unaffected_by_stopped_ones(torch_cuda):
+    """Once a matrix's starts have all stopped, the solves walk only the
+    running matrices' tasks (the lists cut down on the device) and the
+    element kernels skip its tiles. None of this may touch a running
+    matrix's arithmetic: with the same row tiles, each matrix's run in a
+    batch whose other matrices stop at other updates is bit for bit its run
+    alone."""
+    import paper_2409_11515_amd as pa
+
+    torch = torch_cuda
+    mats = [hydromech2d(17, seed=91)] + [hydromech2d(s, seed=92 + s) for s in (5, 7)]
+    opts = dict(max_iter=3000, stop_rtol=1e-6, stop_window=25)
+    starts = [start_block(m.n, 8, 910 + i) for i, m in enumerate(mats)]
+
+    def run(ms, ss):
+        b = pa.Batch([(m.n, m.rowptr, m.col, m.val) for m in ms], sigma_min=True).bind(tile_rows=64,
+                                                                                       grid=1024)
+        r = b.run_min(torch.as_tensor(pa.interleave_starts(ss), device="cuda"), trace=True, **opts)
+        b.close()
+        return r
+
+    r = run(mats, starts)
+    last = r["pair_iters"].max(axis=1)
+    # the matrices stop at different updates: the later ones ran on with
+    # the earlier ones' tasks cut from the lists
+    assert last.min() < last.max()
+    for i, m in enumerate(mats):
+        r1 = run([m], [starts[i]])
+        np.testing.assert_array_equal(r["pair_iters"][i], r1["pair_iters"][0])
+        np.testing.assert_array_equal(r["pair_best"][i], r1["pair_best"][0])
+        np.testing.assert_array_equal(r["trace"][i], r1["trace"][0])
