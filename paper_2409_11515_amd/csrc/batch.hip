@@ -153,25 +153,26 @@ void enqueue_batch_min_iteration(cond_batch* b, const BatchArgs& a, const AdamPa
   int* stop = &a.g->stop_all;
   int* abort = &a.g->abort_wait;
   batch_launch_live(a, s);
-  // once a matrix has stopped, the solves walk only its running neighbours'
-  // tasks: the lists are cut down whenever the running set changes
+  // once a matrix has stopped, the solves walk only the running matrices'
+  // tasks: the lists are cut down whenever the set of running matrices
+  // changes
   batch_launch_compact(a, b->lists, s);
   batch_launch_normalise(a, b->grid, s);
   batch_launch_rearm(a, b->grid, s);
   // r = A^-1 x: L c = P x, U z = c (z reversed); s = A^-T r: U^T h = z,
   // L^T wv = h, w = P^T wv
-  const int* live = &a.g->compact;
+  const int* cut = &a.g->compact;  // set while the solves take the cut lists
   launch_trsv_multi(K, b->dL, a.x, reinterpret_cast<const int*>(b->ws + b->o.row_perm), a.c,
-                    nullptr, nullptr, a.tickets, stop, abort, live, s);
+                    nullptr, nullptr, a.tickets, stop, abort, cut, s);
   const int* rev = reinterpret_cast<const int*>(b->ws + b->o.rev);
-  launch_trsv_multi(K, b->dU, a.c, rev, a.z, nullptr, nullptr, tix(a.tickets, 1), stop, abort, live,
+  launch_trsv_multi(K, b->dU, a.c, rev, a.z, nullptr, nullptr, tix(a.tickets, 1), stop, abort, cut,
                     s);
   batch_launch_sumsq_rev(a, b->grid, s);
   batch_launch_reduce(a, 1, p, s);
-  launch_trsv_multi(K, b->dUt, a.z, rev, a.h, nullptr, nullptr, tix(a.tickets, 2), stop, abort, live,
+  launch_trsv_multi(K, b->dUt, a.z, rev, a.h, nullptr, nullptr, tix(a.tickets, 2), stop, abort, cut,
                     s);
   launch_trsv_multi(K, b->dLt, a.h, rev, a.wv, a.w, reinterpret_cast<const int*>(b->ws + b->o.scat_s),
-                    tix(a.tickets, 3), stop, abort, live, s);
+                    tix(a.tickets, 3), stop, abort, cut, s);
   batch_launch_pass1(a, p, b->grid, s);
   batch_launch_reduce(a, 2, p, s);
   batch_launch_pass2(a, p, b->grid, s);
