@@ -423,8 +423,6 @@ __device__ __forceinline__ void wait_all_memory() { __builtin_amdgcn_s_waitcnt(0
 // lane, without passing through registers) -- is requested before the first
 // wait, so that once the panel's inputs are published only the off-panel
 // sums and one product with the inverse remain.
-constexpr int kLocalPerLane = kPanel / kLanesPerRow;  // inverse columns per lane of a 64-row panel
-constexpr int kLdW = kPanel + 1;  // LDS row stride of a staged 64-row inverse (padded against bank conflicts)
 
 template <int R>
 __global__ __launch_bounds__(kTrsvBlock) void trsv_k(TrsvArgs t, const double* __restrict__ rhs,
@@ -649,7 +647,8 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_multi_k(TrsvArgs t, const dou
                                                            int* abort, const int* compact) {
   constexpr int EL = kLanesPerRow / K;
   static_assert(EL >= 1 && EL * K == kLanesPerRow, "K divides the 16 lanes of a row");
-  __shared__ double w_sh[kPanel * kLdW];  // the sub-panel triangle's inverse, row-major
+  constexpr int kW = kPanel * (kPanel + 1) / 2;  // values of a packed 64-row triangle (even)
+  __shared__ double w_sh[kW];  // the panel's inverse, rows packed: (r, c) at r (r + 1) / 2 + c
   __shared__ double t_sh[kPanel * K];     // off-panel sums, row r side k at r * K + k
   __shared__ double b_sh[kPanel * K];     // right-hand sides
   __shared__ unsigned task_sh;
@@ -705,17 +704,17 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_multi_k(TrsvArgs t, const dou
       continue;
     }
     // everything that needs no solved value: right-hand sides and the
-    // inverse (into LDS: registers are what the K sums need)
+    // inverse, copied from memory straight into LDS as in trsv_k (no
+    // registers, and no wait before the sums' loads are issued)
     if (row && es == 0)
       b_sh[g * K + kk] = rhs_perm ? rhs[static_cast<long long>(rhs_perm[lo + g]) * K + kk]
                                   : rhs[(lo + g) * K + kk];
     {
       const double* w = t.winv + woff;
-#pragma unroll
-      for (int u = 0; u < kLocalPerLane; ++u) {
-        const int c = sub + u * kLanesPerRow;
-        w_sh[g * kLdW + c] = (row && c <= g) ? w[g * (g + 1) / 2 + c] : 0.0;
-      }
+      const int nch = (cnt * (cnt + 1) / 2 + 1) / 2;
+      for (int c0 = 0; c0 < nch; c0 += kTrsvBlock)
+        if (c0 + static_cast<int>(threadIdx.x) < nch)
+          copy16_to_lds(w + 2 * (c0 + threadIdx.x), w_sh + 2 * (c0 + wave * 64));
     }
     double sum;
     if (kind < 0) {
@@ -752,13 +751,14 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_multi_k(TrsvArgs t, const dou
       sum = acc + recent;
     }
     if (row && es == 0) t_sh[g * K + kk] = sum;
+    wait_all_memory();  // the inverse's copies into LDS have landed
     __syncthreads();
     // x = W (b - sums) for side kk: entry lane es takes columns es, es + EL, ...
     double acc = 0.0;
 #pragma unroll 8
     for (int u = 0; u < kPanel / EL; ++u) {
       const int c = es + u * EL;
-      if (c <= g && c < cnt) acc += w_sh[g * kLdW + c] * (b_sh[c * K + kk] - t_sh[c * K + kk]);
+      if (c <= g && c < cnt) acc += w_sh[g * (g + 1) / 2 + c] * (b_sh[c * K + kk] - t_sh[c * K + kk]);
     }
 #pragma unroll
     for (int off = kLanesPerRow / 2; off >= K; off >>= 1) acc += __shfl_xor(acc, off, kLanesPerRow);
