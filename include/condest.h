@@ -252,7 +252,7 @@ int cond_plan_solve_info(const cond_plan_t* plan, int32_t* levels, int64_t* task
 /* Algorithm 2's r = A^-1 x and s = A^-T r (x, r, s: host arrays of length
  * n, caller-owned) computed on the host from the same device-ready data the
  * four solves run on -- task records, slices and their partial-sum slots,
- * packed inverses of the sub-panel triangles, right-hand-side gathers and
+ * packed inverses of the panel triangles, right-hand-side gathers and
  * output scatters -- taking the tasks in ticket order. For checking the
  * solve schedule without a device; available after cond_plan_create.
  * COND_ESTATE if a task would read a value that only a later ticket solves,

@@ -277,7 +277,8 @@ __global__ __launch_bounds__(kBlock) void sumsq_k(int n, const double* __restric
 // ----------------------------------------------------------------- trsv
 // Sparse lower-triangular solve in solve order (upper factors arrive
 // reversed). Work items ("tasks") come in the order the host prepared, by
-// dependency level of their panel (at most 64 consecutive rows). A task is a
+// dependency level of their panel (at most 128 consecutive rows for the
+// single-side solve, 64 for the several-sides one). A task is a
 // whole panel, or -- for a panel with many entries left of it -- one slice
 // of those entries, or the finish step of such a panel; it only waits on
 // tasks earlier in that order (panels of lower level, or the slices of its
@@ -294,14 +295,15 @@ __global__ __launch_bounds__(kBlock) void sumsq_k(int n, const double* __restric
 // the grid is a multiple of kTaskLists and the lowest block ids start
 // first).
 //
-// Off-panel sums: each wave takes 4 rows at once, 16 lanes per row, loads
-// unrolled for memory-level parallelism. A slice task stores its partial
-// sums into fixed slots; the finish task adds the slices in slice order, so
-// the result does not depend on timing. In-panel part: the inverse of the
-// sub-panel's triangle, formed on the host, is staged in LDS before the
-// first wait, and once the sums are in the sub-panel's values are one
-// product with it, each row by its 16 lanes, instead of a substitution whose
-// 64 dependent steps sat on the critical path of every level.
+// Off-panel sums: each row by its 1024 / R lanes (8 for 128-row panels, 16
+// for 64-row ones), loads unrolled for memory-level parallelism. A slice
+// task stores its partial sums into fixed slots; the finish task adds the
+// slices in slice order, so the result does not depend on timing. In-panel
+// part: the inverse of the panel's triangle, formed on the host, is copied
+// into LDS before the first wait, and once the sums are in the panel's
+// values are one product with it, each row by its lanes, instead of a
+// substitution whose dependent steps (one per row) sat on the critical path
+// of every level.
 //
 // Solved values and slice partials are published by one 64-bit atomic store
 // each; until then a slot holds the kPending pattern, so the value is its
@@ -566,14 +568,16 @@ __global__ __launch_bounds__(kTrsvBlock) void trsv_k(TrsvArgs t, const double* _
 
 // ------------------------------------------------- trsv, several sides
 // The same solve for K interleaved right-hand sides (row i, side k at index
-// i * K + k), on the same tasks, records, panel inverses and waits as trsv_k,
-// with one 64-row sub-panel per panel. A row's 16 lanes are EL = 16 / K
-// entry lanes times K side lanes: the K lanes of an entry read its column and
-// value once between them (one address) and K contiguous solved values, so
-// one pass over the factor, and one wait per dependency, serve all K sides.
-// Slice partials are K per row. The run is skipped when *stop is non-zero
-// (every start of the run has stopped); a wait that times out sets *abort.
-// (Panels of kPanel rows: the host plans these schedules with that height.)
+// i * K + k), on the same kind of tasks, records, packed panel inverses and
+// waits as trsv_k, with panels of at most kPanel = 64 rows (the host plans
+// these schedules with that height). Each row has 16 lanes. In the
+// off-panel sums every lane takes a share of the row's entries for all K
+// sides at once: it reads an entry's column and value once and its K
+// contiguous solved values, so one pass over the factor, and one wait per
+// dependency, serve all K sides. In the finish step and the product the 16
+// lanes are EL = 16 / K entry lanes times K side lanes. Slice partials are
+// K per row. The run is skipped when *stop is non-zero (every start of the
+// run has stopped); a wait that times out sets *abort.
 
 // Off-panel sums of one row over entries [p0, p1) for all K sides at once:
 // lane sub of the row's 16 takes entries sub, sub + 16, ... (the single-side

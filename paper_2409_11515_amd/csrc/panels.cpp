@@ -1,6 +1,6 @@
 // Panel schedules of the sparse triangular solves: the planner (panel cuts
 // chosen by a measured cost model, dependency levels, slices of heavy panels,
-// task records), the inverses of the sub-panel triangles, the schedule of
+// task records), the inverses of the panel triangles, the schedule of
 // several independent blocks joined into one, the host replay of a solve,
 // and the device layout of one solve. Plain host C++.
 
@@ -342,8 +342,7 @@ HostCsr reverse_order(const HostCsr& u) {
 // read from the same task records; a slice task sums its share of each row's
 // older off-panel entries into its slot, a finish task adds the slots in
 // order and the newest entries, a whole-panel task all off-panel entries;
-// then a second sub-panel's entries on the first come off, and each
-// sub-panel's values are the product with its packed triangle inverse.
+// then the panel's values are the product with its packed triangle inverse.
 // Every value a task reads must have been solved by an earlier ticket (the
 // condition under which every wait on the device ends) and every slot a
 // finish step reads must have been written; otherwise the schedule is

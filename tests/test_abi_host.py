@@ -180,7 +180,7 @@ def _perm_diag(n, seed):
                                       (lambda: hydromech2d(201, seed=1), 1e-6)])
 def test_solve_schedule_replayed_on_host(mk, bound):
     # the data the device solves run on (task records, slices and slots,
-    # packed inverses of the sub-panel triangles, gathers, scatters), with
+    # packed inverses of the panel triangles, gathers, scatters), with
     # the tasks taken in ticket order, solve the system: componentwise
     # backward errors, and agreement with the oracle's SuperLU solves (two
     # pivoted factorisations). The replay itself refuses a schedule in
