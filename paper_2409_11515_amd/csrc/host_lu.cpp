@@ -94,6 +94,18 @@ int lu_factor(const HostCsr& a, const HostCsr& at, const int32_t* col_perm_in, d
   std::vector<double> udiag(n, 0.0), x(n, 0.0);
   std::vector<int32_t> pinv(n, -1), mark(n, -1), xi(n), stk(n);
   std::vector<int64_t> pstk(n);
+  // Symmetric pruning (Eisenstat and Liu): the depth-first searches read
+  // column kk of L only up to lpend[kk]. Once a later column k has kk in its
+  // reach and its pivot row in L(:, kk), the rows of L(:, kk) not yet
+  // pivotal are all in L(:, k) as well (stored even where their value is
+  // zero), so a search reaching kk finds them through the pivot row and
+  // column k: L(:, kk) is reordered with its pivotal rows first and the
+  // search stops after them. The reach, and so the factors' structure, is
+  // unchanged; only the order the searches list it in (and with it the
+  // order of the numeric updates) can differ.
+  std::vector<int64_t> lpend;
+  lpend.reserve(n);
+  std::vector<char> pruned(n, 0);
   for (int32_t k = 0; k < n; ++k) {
     const int32_t j = q[k];
     // --- symbolic: rows reachable from the pattern of A(:, j) through L
@@ -112,7 +124,7 @@ int lu_factor(const HostCsr& a, const HostCsr& at, const int32_t* col_perm_in, d
         }
         bool done = true;
         if (kk >= 0) {
-          const int64_t pend = f.lp[kk + 1];
+          const int64_t pend = lpend[kk];
           for (int64_t p = pstk[head]; p < pend; ++p) {
             int32_t w = f.li[p];
             if (mark[w] == k) continue;
@@ -165,7 +177,9 @@ int lu_factor(const HostCsr& a, const HostCsr& at, const int32_t* col_perm_in, d
           f.ui.push_back(kk);
           f.ux.push_back(v);
         }
-      } else if (v != 0.0) {
+      } else {
+        // kept where zero too: the pruning relies on L(:, k) holding every
+        // non-pivotal row of the reach
         f.li.push_back(r);
         f.lx.push_back(v / pv);
       }
@@ -174,6 +188,30 @@ int lu_factor(const HostCsr& a, const HostCsr& at, const int32_t* col_perm_in, d
     pinv[piv] = k;
     f.lp.push_back(static_cast<int64_t>(f.li.size()));
     f.up.push_back(static_cast<int64_t>(f.ui.size()));
+    lpend.push_back(f.lp[k + 1]);
+    // --- prune the columns of the reach whose L holds this pivot row
+    for (int32_t p = top; p < n; ++p) {
+      const int32_t kk = pinv[xi[p]];
+      if (kk < 0 || kk == k || pruned[kk]) continue;
+      bool has = false;
+      for (int64_t pl = f.lp[kk]; pl < lpend[kk] && !has; ++pl) has = f.li[pl] == piv;
+      if (!has) continue;
+      int64_t lo = f.lp[kk], hi = f.lp[kk + 1] - 1;
+      while (lo <= hi) {
+        if (pinv[f.li[lo]] >= 0) {
+          ++lo;
+        } else if (pinv[f.li[hi]] < 0) {
+          --hi;
+        } else {
+          std::swap(f.li[lo], f.li[hi]);
+          std::swap(f.lx[lo], f.lx[hi]);
+          ++lo;
+          --hi;
+        }
+      }
+      lpend[kk] = lo;
+      pruned[kk] = 1;
+    }
   }
   // rows of L to pivot order
   for (auto& r : f.li) r = pinv[r];
