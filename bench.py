@@ -411,8 +411,10 @@ def make_matrix(w):
 def _source_hash(kind):
     """SHA-256 of the code a kernel family's counters in profiles/pmc_traffic.json
     were taken on: for "trsv" the single-side triangular-solve section of
-    kernels.hip and the panel schedule in panels.cpp, for "spmv" the streaming
-    SpMV section of kernels.hip and the row tiles in plan.hip."""
+    kernels.hip and the single-matrix panel schedule in panels.cpp (the
+    joining of several matrices' schedules, which only the batch uses, left
+    out), for "spmv" the streaming SpMV section of kernels.hip and the row
+    tiles in plan.hip."""
     import hashlib
 
     csrc = os.path.join(ROOT, "paper_2409_11515_amd", "csrc")
@@ -425,7 +427,8 @@ def _source_hash(kind):
             panels = f.read()
         parts = [src[src.index("// ----------------------------------------------------------------- trsv"):
                      src.index("// ------------------------------------------------- trsv, several sides")],
-                 panels[panels.index("constexpr int64_t kSliceEntries"):panels.index("// Row i -> n-1-i")]]
+                 panels[panels.index("constexpr int64_t kSliceEntries"):panels.index("PanelCsr merge_panels(")],
+                 panels[panels.index("// The inverse of every panel's triangle"):panels.index("// Row i -> n-1-i")]]
     else:
         parts = [src[src.index("// ---------------------------------------------------------- spmv (stream)"):
                      src.index("// ---------------------------------------------------------------- sumsq")],
