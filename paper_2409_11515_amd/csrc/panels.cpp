@@ -223,6 +223,33 @@ PanelCsr merge_panels(const std::vector<const PanelCsr*>& parts, const std::vect
                       const std::vector<int32_t>& groups) {
   PanelCsr m;
   m.prows = parts.empty() ? kPanel : parts[0]->prows;  // the parts share one panel height
+  // every array sized once (the joined schedules of a large batch hold
+  // billions of entries: no regrowth)
+  size_t rows = 0, off = 0, in = 0, panels = 0, winv = 0, tasks = 0;
+  for (const PanelCsr* s : parts) {
+    rows += static_cast<size_t>(s->n);
+    off += s->off_col.size();
+    in += s->in_col.size();
+    panels += s->pstart.size() - 1;
+    winv += s->winv.size();
+    tasks += s->task_panel.size();
+  }
+  m.off_rp.reserve(rows + 1);
+  m.in_rp.reserve(rows + 1);
+  m.off_split.reserve(rows);
+  m.off_col.reserve(off);
+  m.off_val.reserve(off);
+  m.in_col.reserve(in);
+  m.in_val.reserve(in);
+  m.pstart.reserve(panels + 1);
+  m.panel_split.reserve(panels);
+  m.panel_slot.reserve(panels);
+  m.woff.reserve(panels);
+  m.winv.reserve(winv);
+  m.task_panel.reserve(tasks);
+  m.task_kind.reserve(tasks);
+  m.task_level.reserve(tasks);
+  m.task_group.reserve(tasks);
   m.off_rp.push_back(0);
   m.in_rp.push_back(0);
   m.pstart.push_back(0);
@@ -261,6 +288,7 @@ PanelCsr merge_panels(const std::vector<const PanelCsr*>& parts, const std::vect
     int32_t level, part, task;
   };
   std::vector<Ref> refs;
+  refs.reserve(tasks);
   for (size_t k = 0; k < parts.size(); ++k)
     for (size_t t = 0; t < parts[k]->task_panel.size(); ++t)
       refs.push_back({parts[k]->task_level[t], static_cast<int32_t>(k), static_cast<int32_t>(t)});
